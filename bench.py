@@ -1,0 +1,130 @@
+"""Benchmark of the multipole Poisson solve on one MI355X.
+
+One step = one full solve (density streaming, moment contraction, split-K
+sum, radial scans and coefficients, expansion contraction and potential
+streaming) of a synthetic density already resident in HBM.  Prints one JSON
+line with throughput in cell*(l,m)-modes/s (fine cells x (lmax+1)^2 per
+second), the roofline position of the dominant kernel measured with HIP
+events inside the timed region, and the FP64 CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell*(l,m)-modes/s, multipole Phi solve: mixed vs FP64 on GPU at <=1e-6 rel err"
+UNIT = "cell*(l,m)-modes/s"
+PEAK = {"f64": (78.6e12, "TFLOP/s"), "bf16": (2.5e15, "TFLOP/s"), "f16": (2.5e15, "TFLOP/s")}
+DTYPE = {"fp64": "f64", "bf16x3": "bf16", "fp16x2": "f16"}
+
+WORKLOADS = {
+    # name: (workload generator key, precision)
+    "production_fp64": ("production", "fp64"),
+    "production_l32_fp64": ("production_l32", "fp64"),
+    "spheroid_fp64": ("spheroid", "fp64"),
+}
+DEFAULT = "production_fp64"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        sys.stderr.write("bench.py: this build runs on one GPU only; --gpus %d is not supported\n" % args.gpus)
+        sys.exit(2)
+    import torch
+    from paper_2602_02507_amd import mpole
+    from paper_2602_02507_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        sys.stderr.write("bench.py: no GPU visible\n")
+        sys.exit(1)
+    key, precision = WORKLOADS[args.workload]
+    mesh, rho_h = wl.workload(key)
+    dev = torch.device("cuda:0")
+    print("bench: workload %s %dx%dx%d lmax %d precision %s" % (args.workload, mesh.nr, mesh.ntheta, mesh.nphi,
+                                                                mesh.lmax, precision), file=sys.stderr, flush=True)
+    plan = mpole.Plan.from_mesh(mesh, precision=precision, device=dev)
+    rho = torch.from_numpy(rho_h).to(dev)
+    out = plan.empty_outputs()
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        plan.solve_into(rho, **out)
+    torch.cuda.synchronize()
+
+    plan.set_timing(True)
+    plan.phase_ms()                     # clear
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.solve_into(rho, **out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1) / args.steps
+    phases = plan.phase_ms()
+    plan.set_timing(False)
+    print("bench: %.4f ms/solve (wall %.4f ms); phases %s" % (
+        ms, 1e3 * wall / args.steps,
+        {k: round(v[0] / max(v[1], 1), 5) for k, v in phases.items() if v[1]}), file=sys.stderr, flush=True)
+
+    cell_modes = float(mesh.ncells) * mesh.nmodes
+    value = cell_modes / (ms * 1e-3)
+    mflops, eflops, min_bytes = plan.work()
+    dom = max(("moment", "expand"), key=lambda k: phases[k][0])
+    dom_ms = phases[dom][0] / max(phases[dom][1], 1)
+    flops = mflops if dom == "moment" else eflops
+    dtype = DTYPE[precision]
+    peak, punit = PEAK[dtype]
+    achieved = flops / (dom_ms * 1e-3)
+    roof = {"bound": "mfma", "kernel": "k_%s_%s" % (dom, "f64" if precision == "fp64" else precision),
+            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
+            "traffic": None, "launch_ms": dom_ms,
+            "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
+
+    result = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+              "config": {"workload": args.workload, "nr": mesh.nr, "ntheta": mesh.ntheta, "nphi": mesh.nphi,
+                         "lmax": mesh.lmax, "precision": precision,
+                         "coarsened": mesh.class_block is not None},
+              "roofline": roof}
+
+    if not (args.no_cpu_baseline and args.no_check):
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.solve(rho=rho_h, **mesh.oracle_kwargs())
+        tot = time.perf_counter() - t0
+        t_tables, t_solve = ref["seconds"]
+        if not args.no_cpu_baseline:
+            result["cpu_baseline"] = {"value": cell_modes / t_solve, "unit": UNIT, "cores": oracle.threads(),
+                                      "kind": "oracle",
+                                      "sample": "one full solve of the same workload (tables excluded: %.2f s; "
+                                                "solve %.2f s; total %.2f s)" % (t_tables, t_solve, tot)}
+        if not args.no_check:
+            torch.cuda.synchronize()
+            phi = out["phi"].cpu().numpy()
+            result["max_rel_err_vs_oracle"] = float(np.max(np.abs(phi - ref["phi"]) / np.abs(ref["phi"])))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

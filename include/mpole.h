@@ -1,0 +1,190 @@
+/*
+ * mpole -- multipole Poisson solve for Newtonian self-gravity on a
+ * spherical-coordinate mesh, for one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of GenASiS II, Sec. 2.2 ("Poisson Solver"): the
+ * Green-function solution of the Poisson equation (Eq. IntPoisson) expanded
+ * in multipoles (Eq. Multipole) with real angular kernels
+ * A^c_lm = P~_l^m(cos th) cos m ph, A^s_lm = P~_l^m(cos th) sin m ph
+ * (Eqs. AngularKernel_c/_s), discrete angular moments per radial shell
+ * (Eq. AngularMomentsDiscrete), outward/inward radial integration of the
+ * regular (r^l) and irregular (r^-(l+1)) radial moments at shell edges, and
+ * the potential of Eq. Solution at cell centres.  Angular cells may be
+ * merged into coarsening blocks (Sec. 2.1), per radial shell.
+ *
+ * Conventions fixed by this library where the paper leaves a choice:
+ *   - modes: 0 <= m <= l <= lmax, a in {cos, sin}, without the identically
+ *     zero A^s_l0, so nAM = (lmax+1)^2; mode index iAM = l*l for m = 0,
+ *     l*l + 2m - 1 for (m, cos), l*l + 2m for (m, sin);
+ *   - the source is S = 4 pi G rho (Sec. 3);
+ *   - angular cell averages are solid-angle weighted, radial cell averages
+ *     of r^l and r^-(l+1) are r^2 dr (volume) weighted;
+ *   - edge moments are averaged to the shell centre (arithmetic mean of the
+ *     two edges) before Eq. Solution is evaluated with cell-averaged kernels;
+ *   - a shell whose inner edge is r = 0 has no irregular increment and no
+ *     <r^-(l+1)> term for l >= 2 (the average diverges there);
+ *   - a coarsening block is one cell of the solve: its density is the
+ *     solid-angle weighted mean of its member cells, its kernels are the
+ *     solid-angle weighted means of theirs, and its potential is written to
+ *     every member cell.
+ *
+ * Layouts.  rho and phi are C-order [nr][ntheta][nphi] (phi fastest), FP64,
+ * in device memory.  Moments are [shell or edge][iAM], FP64, device memory.
+ * Everything crossing this interface is FP64; the precision mode only
+ * changes how the two angular contractions are evaluated internally.
+ *
+ * Ownership.  The caller owns every device buffer, including the workspace
+ * whose size mpole_plan_workspace_bytes() reports.  The library never
+ * allocates or frees device memory.  A plan holds host metadata and
+ * pointers into the bound workspace; one plan serves one stream at a time
+ * (solves that overlap on one workspace race).
+ *
+ * Errors.  Every call returns an mpole_status.  On an error nothing has been
+ * enqueued and mpole_last_error() (per thread) describes it.  Faults inside
+ * already-enqueued kernels surface at the caller's next stream
+ * synchronisation.  No call aborts or throws.
+ */
+#ifndef MPOLE_H
+#define MPOLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPOLE_ABI_VERSION 1
+#define MPOLE_LMAX_MAX 64
+
+typedef enum {
+  MPOLE_OK = 0,
+  MPOLE_ERR_INVALID = 1,     /* bad argument: null pointer, bad size, non-monotone edges, ... */
+  MPOLE_ERR_RANGE = 2,       /* r^(l+3) or r^(2-l) leaves [1e-290, 1e290] for a nonzero edge */
+  MPOLE_ERR_WORKSPACE = 3,   /* workspace missing, too small or misaligned (256 B) */
+  MPOLE_ERR_DEVICE = 4,      /* a HIP runtime call or kernel launch failed */
+  MPOLE_ERR_UNSUPPORTED = 5  /* lmax above MPOLE_LMAX_MAX, unknown precision, ... */
+} mpole_status;
+
+typedef enum {
+  MPOLE_FP64 = 0,            /* both contractions in FP64 (MFMA f64) */
+  MPOLE_BF16X3 = 1,          /* both contractions as three-way split BF16 products, FP32 accumulation */
+  MPOLE_FP16X2 = 2           /* both contractions as two-way split FP16 products, per-shell scaling */
+} mpole_precision;
+
+typedef struct mpole_plan_t *mpole_plan;
+
+/*
+ * Mesh descriptor (all pointers are HOST pointers; the plan copies them).
+ *   nr, ntheta, nphi >= 1; 0 <= lmax <= MPOLE_LMAX_MAX.
+ *   r_edges[nr+1]: strictly increasing, finite, r_edges[0] >= 0.
+ *   theta_edges[ntheta+1]: strictly increasing within [0, pi].
+ *   phi_edges[nphi+1]: strictly increasing, total span at most 2 pi.
+ *   nclasses: 0 = no coarsening (every angular cell is its own block);
+ *     otherwise shell_class[nr] in [0, nclasses) picks the class of each
+ *     shell, and class_block[nclasses][ntheta*nphi] gives each angular cell
+ *     (index j*nphi + k) its block id in that class; the ids of a class must
+ *     be exactly 0..nblocks-1, each used at least once.
+ *   G: gravitational constant (S = 4 pi G rho); must be finite.
+ *   precision: an mpole_precision value.
+ */
+typedef struct {
+  int32_t nr, ntheta, nphi, lmax;
+  const double *r_edges;
+  const double *theta_edges;
+  const double *phi_edges;
+  int32_t nclasses;
+  const int32_t *shell_class;
+  const int32_t *class_block;
+  double G;
+  int32_t precision;
+} mpole_mesh;
+
+/* ABI version of the loaded library (MPOLE_ABI_VERSION). */
+int mpole_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *mpole_last_error(void);
+
+/*
+ * Validate a mesh and build a plan on the host (no device work, no HIP call).
+ * Returns MPOLE_ERR_INVALID / _RANGE / _UNSUPPORTED for a bad mesh; *out is
+ * set only on success.
+ */
+int mpole_plan_create(const mpole_mesh *mesh, mpole_plan *out);
+
+/* Device workspace the plan needs, in bytes (0 for a null plan). */
+size_t mpole_plan_workspace_bytes(mpole_plan plan);
+
+/* Number of angular moments (lmax+1)^2 of a plan (0 for a null plan). */
+int mpole_plan_nmodes(mpole_plan plan);
+
+/*
+ * Bind a device workspace (256-byte aligned, at least
+ * mpole_plan_workspace_bytes) and enqueue the one-time table construction
+ * on hip_stream (a hipStream_t; NULL = default stream): Legendre cell
+ * averages by composite Gauss-Legendre quadrature in FP64, phi-cell
+ * averages, merged-block kernel tables, radial kernel integrals and, for
+ * the split precisions, their split planes (Sec. 2.2: kernels "computed once
+ * and for all at the beginning").  The workspace must stay allocated while
+ * the plan is used.  Rebinding is allowed.
+ */
+int mpole_plan_bind(mpole_plan plan, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/*
+ * One solve on hip_stream; asynchronous, no allocation, no host sync.
+ *   rho  [nr][ntheta][nphi] device, FP64 density (required).
+ *   phi  [nr][ntheta][nphi] device, FP64 potential out (may be NULL).
+ *   ang_moments [nr][nAM] device, angular moments of S = 4 pi G rho per
+ *     shell, Eq. AngularMomentsDiscrete (may be NULL).
+ *   interior [nr+1][nAM] device, regular radial moments at shell edges,
+ *     edge 0 = 0, outward sums (may be NULL).
+ *   exterior [nr+1][nAM] device, irregular radial moments at shell edges,
+ *     edge nr = 0, inward sums (may be NULL).
+ * Output buffers must not overlap each other or rho.
+ */
+int mpole_solve(mpole_plan plan, const double *rho, double *phi, double *ang_moments,
+                double *interior, double *exterior, void *hip_stream);
+
+/*
+ * Copy the FP64 block-averaged kernel table of coarsening class cls
+ * ([nblocks][nAM], row b = block b) to host memory, synchronously on
+ * hip_stream.  *nblocks receives the block count (query with host_out =
+ * NULL first).  For tests of the table construction.
+ */
+int mpole_plan_copy_table(mpole_plan plan, int32_t cls, double *host_out, int64_t *nblocks,
+                          void *hip_stream);
+
+/*
+ * Per-phase device timing for profiling.  While enabled, every solve records
+ * a pair of HIP events around each of its kernels on the solve's stream (host
+ * event objects only; no device memory).  mpole_plan_phase_ms synchronises
+ * the recorded events, writes the summed milliseconds and launch counts per
+ * phase, and clears the record.  Phases: MPOLE_PHASE_PACK (density
+ * streaming), _MOMENT (moment contraction), _REDUCE (split-K sum), _SCAN
+ * (radial sums and coefficients), _SPLIT (coefficient split, split
+ * precisions only), _EXPAND (expansion contraction and potential streaming).
+ */
+enum {
+  MPOLE_PHASE_PACK = 0, MPOLE_PHASE_MOMENT = 1, MPOLE_PHASE_REDUCE = 2, MPOLE_PHASE_SCAN = 3,
+  MPOLE_PHASE_SPLIT = 4, MPOLE_PHASE_EXPAND = 5, MPOLE_NPHASES = 6
+};
+int mpole_plan_set_timing(mpole_plan plan, int enable);
+int mpole_plan_phase_ms(mpole_plan plan, double *total_ms, int64_t *launches);
+
+/*
+ * Algorithmic work of one solve of this plan: flops of the two angular
+ * contractions counted on merged blocks (2 per block x shell x mode, each),
+ * and the minimum HBM bytes of the solve (FP64 rho in, FP64 phi out, the
+ * kernel tables read once).  Either pointer may be NULL.
+ */
+int mpole_plan_work(mpole_plan plan, double *moment_flops, double *expand_flops, double *min_bytes);
+
+/* Free the plan's host memory (the workspace stays the caller's). NULL is a no-op. */
+int mpole_plan_destroy(mpole_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPOLE_H */

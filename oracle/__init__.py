@@ -34,7 +34,7 @@ def lib():
         L.oracle_mode_index.argtypes = [c_int, c_int, c_int]
         L.oracle_mode_index.restype = c_int
         L.oracle_solve.argtypes = [c_int, c_int, c_int, c_int, dp, dp, dp, c_double, c_int, ip, ip,
-                                   dp, dp, dp, dp, dp, dp]
+                                   dp, dp, dp, dp, dp, dp, dp]
         L.oracle_solve.restype = c_int
         _lib = L
     return _lib
@@ -109,7 +109,8 @@ def angular_tables(theta_edges, phi_edges, lmax):
 
 
 def solve(r_edges, theta_edges, phi_edges, lmax, rho, G=1.0, shell_class=None, class_block=None):
-    """Full FP64 solve.  Returns dict(phi, ang, interior, exterior, coef)."""
+    """Full FP64 solve.  Returns dict(phi, ang, interior, exterior, coef, seconds);
+    seconds = (table construction, solve proper) wall times."""
     r = np.ascontiguousarray(r_edges, dtype=np.float64)
     th = np.ascontiguousarray(theta_edges, dtype=np.float64)
     ph = np.ascontiguousarray(phi_edges, dtype=np.float64)
@@ -130,6 +131,14 @@ def solve(r_edges, theta_edges, phi_edges, lmax, rho, G=1.0, shell_class=None, c
     itr = np.zeros((nr + 1, nam))
     ext = np.zeros((nr + 1, nam))
     coef = np.zeros((nr, nam))
+    sec = np.zeros(2)
     lib().oracle_solve(nr, nt, npf, lmax, _dp(r), _dp(th), _dp(ph), float(G), ncls, _ip(sc), _ip(cb),
-                       _dp(rho), _dp(phi), _dp(ang), _dp(itr), _dp(ext), _dp(coef))
-    return dict(phi=phi, ang=ang, interior=itr, exterior=ext, coef=coef)
+                       _dp(rho), _dp(phi), _dp(ang), _dp(itr), _dp(ext), _dp(coef), _dp(sec))
+    return dict(phi=phi, ang=ang, interior=itr, exterior=ext, coef=coef, seconds=(sec[0], sec[1]))
+
+
+def threads():
+    """OpenMP threads the oracle uses."""
+    import os
+    n = os.environ.get("OMP_NUM_THREADS")
+    return int(n) if n else os.cpu_count()

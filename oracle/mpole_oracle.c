@@ -41,6 +41,7 @@
  *     written to every member cell.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -279,14 +280,16 @@ int oracle_angular_tables(int ntheta, int nphi, int lmax, const double *th, cons
  * angular cell's block id within class c.
  * rho and phi are [nr][ntheta][nphi] (phi fastest).  Optional outputs (may
  * be NULL): ang [nr][nAM] angular moments, interior / exterior [nr+1][nAM]
- * edge radial moments, coef [nr][nAM] the assembled expansion coefficients.
+ * edge radial moments, coef [nr][nAM] the assembled expansion coefficients,
+ * seconds[2] wall time of the table construction and of the solve proper.
  */
 int oracle_solve(int nr, int ntheta, int nphi, int lmax, const double *r, const double *th,
                  const double *ph, double G, int nclasses, const int32_t *shell_class,
                  const int32_t *class_block, const double *rho, double *phi, double *ang,
-                 double *interior, double *exterior, double *coef) {
+                 double *interior, double *exterior, double *coef, double *seconds) {
   const int nam = oracle_n_modes(lmax), ncell = ntheta * nphi;
   const double fourpiG = 4.0 * ORACLE_PI * G;
+  const double t_start = omp_get_wtime();
 
   /* angular tables on the fine cells */
   double *dom = (double *)malloc(sizeof(double) * ncell);
@@ -321,6 +324,7 @@ int oracle_solve(int nr, int ntheta, int nphi, int lmax, const double *r, const 
     bker[c] = bk;
   }
   free(afine);
+  const double t_tables = omp_get_wtime();
 
   /* angular moments: A[i][n] = sum_b dOmega_b <A_n>_b S_ib, S = 4 pi G rho_b */
   double *A = (double *)calloc((size_t)nr * nam, sizeof(double));
@@ -392,6 +396,10 @@ int oracle_solve(int nr, int ntheta, int nphi, int lmax, const double *r, const 
     }
   }
 
+  if (seconds) {
+    seconds[0] = t_tables - t_start;
+    seconds[1] = omp_get_wtime() - t_tables;
+  }
   if (ang) memcpy(ang, A, sizeof(double) * (size_t)nr * nam);
   if (interior) memcpy(interior, MR, sizeof(double) * (size_t)(nr + 1) * nam);
   if (exterior) memcpy(exterior, MI, sizeof(double) * (size_t)(nr + 1) * nam);

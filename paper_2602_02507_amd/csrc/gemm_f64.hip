@@ -1,0 +1,234 @@
+// The two angular contractions of the solve in FP64 on MFMA (v_mfma_f64_16x16x4):
+//
+//   moment:  A[i][n]   = sum_b  P[i][b] T[b][n]   (Eq. AngularMomentsDiscrete;
+//            P = dOmega_b S_ib packed per class, T = block-mean kernels)
+//   expand:  Phi[i][b] = sum_n  C[i][n] T[b][n]   (Eq. Solution at the shell
+//            centre with the assembled coefficients C)
+//
+// Both read the same kernel table T[b][n] (mode index fastest) staged through
+// LDS; the moment contraction reads it row-wise (k = b), the expansion
+// column-wise (k = n).  Tiles are 64 x 64 per workgroup of four waves, each
+// wave owning a 32 x 32 corner as 2 x 2 MFMA 16x16 tiles; K advances 16 per
+// LDS stage, double-buffered with register prefetch of the next stage.
+//
+// The moment contraction is skinny (M = shells, N = modes, K = blocks up to
+// ~1e5), so K is split across workgroups; each split writes its own FP64
+// partial and a separate pass sums them in a fixed order (deterministic, no
+// atomics).  Workgroup ids are remapped so that each XCD (8 per MI355X, with
+// private L2) receives a contiguous run of tiles that share table panels.
+//
+// f64 MFMA 16x16x4 lane layout on gfx950 (checked on the device): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; result element (i, j) sits in
+// lane 16*(i%4) + j, accumulator register i/4.
+#include "mpole_internal.h"
+
+namespace mpole {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, NTHREADS = 256;
+constexpr int LDS_LD = BM + 4;  // row stride of an LDS stage, in doubles
+
+// Linear workgroup id -> logical tile id such that XCD x (which receives
+// hardware ids w = x mod 8) owns logical ids [x*q + min(x, r), ...).
+__device__ inline int xcd_remap(int w, int g) {
+  const int q = g >> 3, r = g & 7, x = w & 7;
+  return x * q + min(x, r) + (w >> 3);
+}
+
+__device__ inline void mfma_stage(const double (*As)[LDS_LD], const double (*Bs)[LDS_LD], int wm, int wn,
+                                  int lane, d4 acc[2][2]) {
+#pragma unroll
+  for (int kk = 0; kk < BK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+    const int c = lane & 15;
+    const double a0 = As[kr][wm * 32 + c];
+    const double a1 = As[kr][wm * 32 + 16 + c];
+    const double b0 = Bs[kr][wn * 32 + c];
+    const double b1 = Bs[kr][wn * 32 + 16 + c];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// 4 consecutive doubles from a 32-byte aligned address, or zeros
+__device__ inline void load4(const double *p, bool ok, double v[4]) {
+  if (ok) {
+    const double2 x = *reinterpret_cast<const double2 *>(p);
+    const double2 y = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+  } else {
+    v[0] = v[1] = v[2] = v[3] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_moment_f64(PlanDev P) {
+  __shared__ double As[2][BK][LDS_LD];
+  __shared__ double Bs[2][BK][LDS_LD];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int c = 0;
+  while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_mom_begin) ++c;
+  const ClassDev C = P.classes[c];
+  const int local = wg - C.wg_mom_begin;
+  const int mt = local % C.m_tiles;
+  const int rest = local / C.m_tiles;
+  const int nt = rest % C.n_tiles_mom;
+  const int split = rest / C.n_tiles_mom;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = split * C.kchunk;
+  const int kend = min(kbeg + C.kchunk, C.nblocks_pad);
+  const int nrows = C.nrows, ldp = C.nblocks_pad, namp = P.namp;
+  const double *__restrict__ Pk = C.pack;
+  const double *__restrict__ T = C.table;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  // loader roles: A rows (k contiguous) and B rows (n contiguous)
+  const int ar = tid >> 2, ak = (tid & 3) * 4;
+  const int bk = tid >> 4, bn = (tid & 15) * 4;
+  const bool a_ok = (m0 + ar) < nrows;
+  const bool b_ok = (n0 + bn) < namp;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double av[4], bv[4];
+  const int nk = (kend - kbeg) / BK;
+  if (nk > 0) {
+    load4(Pk + (size_t)(m0 + ar) * ldp + kbeg + ak, a_ok, av);
+    load4(T + (size_t)(kbeg + bk) * namp + n0 + bn, b_ok, bv);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) As[0][ak + e][ar] = av[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Bs[0][bk][bn + e] = bv[e];
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      const int k = kbeg + (kt + 1) * BK;
+      load4(Pk + (size_t)(m0 + ar) * ldp + k + ak, a_ok, av);
+      load4(T + (size_t)(k + bk) * namp + n0 + bn, b_ok, bv);
+    }
+    mfma_stage(As[cur], Bs[cur], wm, wn, lane, acc);
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[cur ^ 1][ak + e][ar] = av[e];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][bk][bn + e] = bv[e];
+    }
+    __syncthreads();
+  }
+
+  double *__restrict__ out = C.partial + (size_t)split * nrows * namp;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + t * 16 + 4 * r + (lane >> 4);
+        const int col = n0 + wn * 32 + u * 16 + (lane & 15);
+        if (row < nrows && col < namp) out[(size_t)row * namp + col] = acc[t][u][r];
+      }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_expand_f64(PlanDev P, double *__restrict__ phi) {
+  __shared__ double As[2][BK][LDS_LD];
+  __shared__ double Bs[2][BK][LDS_LD];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int c = 0;
+  while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_exp_begin) ++c;
+  const ClassDev C = P.classes[c];
+  const int local = wg - C.wg_exp_begin;
+  const int mt = local % C.m_tiles;
+  const int nt = local / C.m_tiles;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int nrows = C.nrows, namp = P.namp;
+  const double *__restrict__ T = C.table;
+  const double *__restrict__ coef = P.coef;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  // both operands are rows with the mode index contiguous: 64 rows x 16 modes
+  const int lr = tid >> 2, lk = (tid & 3) * 4;
+  const bool a_ok = (m0 + lr) < nrows;
+  const int shell_a = a_ok ? C.rows[m0 + lr] : 0;
+  const bool b_ok = (n0 + lr) < C.nblocks_pad;
+  const double *arow = coef + (size_t)shell_a * namp;
+  const double *brow = T + (size_t)(b_ok ? n0 + lr : 0) * namp;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double av[4], bv[4];
+  const int nk = namp / BK;
+  load4(arow + lk, a_ok, av);
+  load4(brow + lk, b_ok, bv);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) As[0][lk + e][lr] = av[e];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) Bs[0][lk + e][lr] = bv[e];
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      const int k = (kt + 1) * BK;
+      load4(arow + k + lk, a_ok, av);
+      load4(brow + k + lk, b_ok, bv);
+    }
+    mfma_stage(As[cur], Bs[cur], wm, wn, lane, acc);
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[cur ^ 1][lk + e][lr] = av[e];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][lk + e][lr] = bv[e];
+    }
+    __syncthreads();
+  }
+
+  // epilogue: the block potential goes to every member cell of the block
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm * 32 + t * 16 + 4 * r + (lane >> 4);
+      if (row >= nrows) continue;
+      double *__restrict__ dst = phi + (size_t)C.rows[row] * P.ncell;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int b = n0 + wn * 32 + u * 16 + (lane & 15);
+        if (b >= C.nblocks) continue;
+        const double v = acc[t][u][r];
+        const int e1 = C.moff[b + 1];
+        for (int e = C.moff[b]; e < e1; ++e) dst[C.mem[e]] = v;
+      }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_moment_f64(const PlanDev &P, int total_wgs, hipStream_t s) {
+  if (total_wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_moment_f64, dim3(total_wgs), dim3(NTHREADS), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_f64(const PlanDev &P, int total_wgs, double *phi, hipStream_t s) {
+  if (total_wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_f64, dim3(total_wgs), dim3(NTHREADS), 0, s, P, phi);
+  return hipGetLastError();
+}
+
+}  // namespace mpole

@@ -1,0 +1,68 @@
+// Internal interfaces between the host plan (plan.cpp) and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mpole {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kGaussNodes = 16;   // Gauss-Legendre points per theta sub-interval
+constexpr int kModePad = 16;      // nAM is padded to a multiple of this
+constexpr int kBlockPad = 16;     // block counts are padded to a multiple of this
+
+// Gauss-Legendre rule on [-1, 1], computed on the host.
+struct GaussRule {
+  double x[kGaussNodes];
+  double w[kGaussNodes];
+};
+
+// Per-coarsening-class device view (lives in the workspace).
+struct ClassDev {
+  const int32_t *rows;   // [nrows] global shell of each class row, ascending
+  const int32_t *moff;   // [nblocks+1] CSR offsets of block members
+  const int32_t *mem;    // [ncell] member fine-cell index j*nphi+k, ascending per block
+  double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, zero padded
+  uint16_t *tplanes;     // [nplanes][nblocks_pad][namp] split planes (mixed precision) or null
+  double *pack;          // [nrows][nblocks_pad] FP64 packed S*dOmega (FP64 path)
+  uint16_t *ppacks;      // [nplanes][nrows][nblocks_pad] split planes of the packed source
+  double *pscale;        // [nrows] power-of-two row scales of the packed source
+  double *partial;       // [splits][nrows][namp] split-K partial moments
+  int32_t nrows, nblocks, nblocks_pad;
+  int32_t splits, kchunk;             // moment split-K: splits x kchunk >= nblocks_pad
+  int32_t m_tiles, n_tiles_mom, n_tiles_exp;
+  int32_t wg_mom_begin, wg_exp_begin;  // prefix sums over classes
+};
+
+// Whole-plan device view.
+struct PlanDev {
+  int32_t nr, ntheta, nphi, lmax, nam, namp, ncell, nclasses, nplanes;
+  double G;
+  const double *r_edges, *theta_edges, *phi_edges;  // device copies
+  const int32_t *shell_class;  // [nr]
+  const int32_t *shell_row;    // [nr] row of each shell within its class
+  ClassDev *classes;           // [nclasses] (device copy)
+  double *pavg;      // [ntheta][nplm] theta-cell averages of P~_l^m
+  double *trig;      // [nphi][2*(lmax+1)] (<cos m ph>, <sin m ph>)
+  double *weight;    // [ncell] 4 pi G dOmega
+  double *jr, *ji;   // [nr][lmax+1] exact shell integrals of r^(2+l), r^(1-l)
+  double *rr, *ri;   // [nr][lmax+1] volume-averaged r^l, r^-(l+1)
+  double *ang;       // [nr][namp] reduced angular moments
+  double *coef;      // [nr][namp] expansion coefficients
+  uint16_t *cplanes; // [nplanes][nr][namp] split planes of coef
+  double *cscale;    // [nr] row scales of coef
+  double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
+};
+
+// ---- launchers (all asynchronous on `s`; return hipSuccess or the launch error)
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g,
+                         hipStream_t s);
+hipError_t launch_pack_f64(const PlanDev &P, const ClassDev *host_classes, const double *rho,
+                           hipStream_t s);
+hipError_t launch_moment_f64(const PlanDev &P, int total_wgs, hipStream_t s);
+hipError_t launch_reduce(const PlanDev &P, double *ang_out, hipStream_t s);
+hipError_t launch_scan(const PlanDev &P, double *interior, double *exterior, hipStream_t s);
+hipError_t launch_expand_f64(const PlanDev &P, int total_wgs, double *phi, hipStream_t s);
+
+}  // namespace mpole

@@ -1,0 +1,484 @@
+// Host side of the C ABI declared in include/mpole.h: mesh validation, the
+// per-class block maps (CSR), workspace layout, table construction at bind
+// time and the kernel sequence of one solve.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mpole.h"
+#include "mpole_internal.h"
+
+using namespace mpole;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int ok() {
+  g_error.clear();
+  return MPOLE_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// 16-point Gauss-Legendre rule on [-1, 1] by Newton iteration on P_16.
+GaussRule make_gauss_rule() {
+  GaussRule g{};
+  const int n = kGaussNodes;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    g.x[i] = x;
+    g.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return g;
+}
+
+struct ClassHost {
+  std::vector<int32_t> rows, moff, mem;
+  int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
+  int m_tiles = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
+  size_t off_rows = 0, off_moff = 0, off_mem = 0, off_table = 0, off_pack = 0, off_partial = 0;
+};
+
+}  // namespace
+
+struct mpole_plan_t {
+  int nr = 0, nt = 0, np = 0, L = 0, nam = 0, namp = 0, ncell = 0, ncls = 0, precision = 0;
+  double G = 1.0;
+  std::vector<double> r, th, ph;
+  std::vector<int32_t> shell_class, shell_row;
+  std::vector<ClassHost> cls;
+  size_t ws_bytes = 0;
+  size_t off_r = 0, off_th = 0, off_ph = 0, off_shell_class = 0, off_shell_row = 0, off_classes = 0;
+  size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
+  size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0;
+  int wg_mom = 0, wg_exp = 0;
+  GaussRule rule{};
+  // per-phase timing events (host objects), recorded while timing is on
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs: [2k] before, [2k+1] after launch k
+  std::vector<int> ev_phase;
+  size_t ev_used = 0;
+  // bound state
+  bool bound = false;
+  char *ws = nullptr;
+  PlanDev dev{};
+  std::vector<ClassDev> cdev;
+};
+
+namespace {
+
+int check_edges(const char *name, const double *e, int n, double lo, double hi) {
+  if (!e) return fail(MPOLE_ERR_INVALID, "%s is null", name);
+  for (int i = 0; i <= n; ++i)
+    if (!std::isfinite(e[i])) return fail(MPOLE_ERR_INVALID, "%s[%d] is not finite", name, i);
+  for (int i = 0; i < n; ++i)
+    if (!(e[i + 1] > e[i])) return fail(MPOLE_ERR_INVALID, "%s is not strictly increasing at %d", name, i);
+  if (e[0] < lo || e[n] > hi) return fail(MPOLE_ERR_INVALID, "%s leaves [%g, %g]", name, lo, hi);
+  return MPOLE_OK;
+}
+
+// Split-K choice for the moment contraction: spread about `target` workgroups
+// over the classes in proportion to their work, at least one 16-wide K step
+// per split.
+void choose_splits(mpole_plan_t &p, int target) {
+  double total = 0.0;
+  for (auto &c : p.cls) total += (double)c.rows.size() * c.nblocks_pad;
+  for (auto &c : p.cls) {
+    const int tiles = c.m_tiles * c.n_tiles_mom;
+    const double share = total > 0 ? target * (double)c.rows.size() * c.nblocks_pad / total : 1.0;
+    int s = (int)std::lround(share / std::max(tiles, 1));
+    s = std::max(1, std::min(s, c.nblocks_pad / 16));
+    c.kchunk = round_up((c.nblocks_pad + s - 1) / s, 16);
+    c.splits = (c.nblocks_pad + c.kchunk - 1) / c.kchunk;
+  }
+}
+
+int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
+  if (!m) return fail(MPOLE_ERR_INVALID, "mesh is null");
+  if (m->nr < 1 || m->ntheta < 1 || m->nphi < 1)
+    return fail(MPOLE_ERR_INVALID, "mesh sizes must be >= 1 (nr=%d ntheta=%d nphi=%d)", m->nr, m->ntheta, m->nphi);
+  if (m->lmax < 0) return fail(MPOLE_ERR_INVALID, "lmax must be >= 0");
+  if (m->lmax > MPOLE_LMAX_MAX) return fail(MPOLE_ERR_UNSUPPORTED, "lmax %d above %d", m->lmax, MPOLE_LMAX_MAX);
+  if (m->precision != MPOLE_FP64)
+    return fail(MPOLE_ERR_UNSUPPORTED, "precision %d is not available in this build", m->precision);
+  if (!std::isfinite(m->G)) return fail(MPOLE_ERR_INVALID, "G is not finite");
+  const long long ncell = (long long)m->ntheta * m->nphi;
+  if (ncell > (1LL << 30) || (long long)m->nr * ncell > (1LL << 40))
+    return fail(MPOLE_ERR_INVALID, "mesh too large");
+  int rc;
+  if ((rc = check_edges("r_edges", m->r_edges, m->nr, 0.0, INFINITY))) return rc;
+  if ((rc = check_edges("theta_edges", m->theta_edges, m->ntheta, 0.0, kPi * (1 + 1e-15)))) return rc;
+  if ((rc = check_edges("phi_edges", m->phi_edges, m->nphi, -INFINITY, INFINITY))) return rc;
+  if (m->phi_edges[m->nphi] - m->phi_edges[0] > 2 * kPi * (1 + 1e-15))
+    return fail(MPOLE_ERR_INVALID, "phi_edges span more than 2 pi");
+  // FP64 range of r^(l+3) and r^(2-l) for l <= lmax on every nonzero edge
+  const double pmax = std::max(m->lmax + 3.0, std::fabs(2.0 - m->lmax));
+  for (int i = 0; i <= m->nr; ++i) {
+    const double r = m->r_edges[i];
+    if (r > 0.0 && std::fabs(std::log10(r)) * pmax > 290.0)
+      return fail(MPOLE_ERR_RANGE, "r_edges[%d] = %g: r^%g leaves the FP64 range", i, r, pmax);
+  }
+  if (m->nclasses < 0) return fail(MPOLE_ERR_INVALID, "nclasses < 0");
+  if (m->nclasses > 0 && (!m->shell_class || !m->class_block))
+    return fail(MPOLE_ERR_INVALID, "shell_class and class_block are required when nclasses > 0");
+
+  p->nr = m->nr;
+  p->nt = m->ntheta;
+  p->np = m->nphi;
+  p->L = m->lmax;
+  p->nam = (m->lmax + 1) * (m->lmax + 1);
+  p->namp = round_up(p->nam, kModePad);
+  p->ncell = (int)ncell;
+  p->precision = m->precision;
+  p->G = m->G;
+  p->r.assign(m->r_edges, m->r_edges + m->nr + 1);
+  p->th.assign(m->theta_edges, m->theta_edges + m->ntheta + 1);
+  p->ph.assign(m->phi_edges, m->phi_edges + m->nphi + 1);
+  p->ncls = m->nclasses > 0 ? m->nclasses : 1;
+  p->cls.assign(p->ncls, ClassHost{});
+  p->shell_class.assign(p->nr, 0);
+  p->shell_row.assign(p->nr, 0);
+  for (int i = 0; i < p->nr; ++i) {
+    const int c = m->nclasses > 0 ? m->shell_class[i] : 0;
+    if (c < 0 || c >= p->ncls) return fail(MPOLE_ERR_INVALID, "shell_class[%d] = %d out of range", i, c);
+    p->shell_class[i] = c;
+    p->shell_row[i] = (int)p->cls[c].rows.size();
+    p->cls[c].rows.push_back(i);
+  }
+  for (int c = 0; c < p->ncls; ++c) {
+    ClassHost &C = p->cls[c];
+    std::vector<int32_t> id(p->ncell);
+    if (m->nclasses > 0) {
+      std::memcpy(id.data(), m->class_block + (size_t)c * p->ncell, sizeof(int32_t) * p->ncell);
+    } else {
+      for (int q = 0; q < p->ncell; ++q) id[q] = q;
+    }
+    int nb = 0;
+    for (int q = 0; q < p->ncell; ++q) {
+      if (id[q] < 0 || id[q] >= p->ncell)
+        return fail(MPOLE_ERR_INVALID, "class_block[%d][%d] = %d out of range", c, q, id[q]);
+      nb = std::max(nb, id[q] + 1);
+    }
+    std::vector<int32_t> count(nb, 0);
+    for (int q = 0; q < p->ncell; ++q) ++count[id[q]];
+    for (int b = 0; b < nb; ++b)
+      if (count[b] == 0) return fail(MPOLE_ERR_INVALID, "class %d: block id %d unused (ids must be dense)", c, b);
+    C.nblocks = nb;
+    C.nblocks_pad = round_up(nb, kBlockPad);
+    C.moff.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) C.moff[b + 1] = C.moff[b] + count[b];
+    C.mem.assign(p->ncell, 0);
+    std::vector<int32_t> fillp(C.moff.begin(), C.moff.end() - 1);
+    for (int q = 0; q < p->ncell; ++q) C.mem[fillp[id[q]]++] = q;   // ascending q per block
+    C.m_tiles = std::max(1, ((int)C.rows.size() + 63) / 64);
+    C.n_tiles_mom = (p->namp + 63) / 64;
+    C.n_tiles_exp = (C.nblocks + 63) / 64;
+  }
+  choose_splits(*p, 512);
+  int wm = 0, we = 0;
+  for (auto &C : p->cls) {
+    C.wg_mom_begin = wm;
+    C.wg_exp_begin = we;
+    if (!C.rows.empty()) {
+      wm += C.m_tiles * C.n_tiles_mom * C.splits;
+      we += C.m_tiles * C.n_tiles_exp;
+    }
+  }
+  p->wg_mom = wm;
+  p->wg_exp = we;
+
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const int nplm = (p->L + 1) * (p->L + 2) / 2;
+  p->off_r = take(sizeof(double) * (p->nr + 1));
+  p->off_th = take(sizeof(double) * (p->nt + 1));
+  p->off_ph = take(sizeof(double) * (p->np + 1));
+  p->off_shell_class = take(sizeof(int32_t) * p->nr);
+  p->off_shell_row = take(sizeof(int32_t) * p->nr);
+  p->off_classes = take(sizeof(ClassDev) * p->ncls);
+  p->off_pavg = take(sizeof(double) * (size_t)p->nt * nplm);
+  p->off_trig = take(sizeof(double) * (size_t)p->np * 2 * (p->L + 1));
+  p->off_weight = take(sizeof(double) * (size_t)p->ncell);
+  p->off_jr = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
+  p->off_ji = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
+  p->off_rr = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
+  p->off_ri = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
+  p->off_ang = take(sizeof(double) * (size_t)p->nr * p->namp);
+  p->off_coef = take(sizeof(double) * (size_t)p->nr * p->namp);
+  p->off_edge_r = take(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
+  p->off_edge_i = take(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
+  for (auto &C : p->cls) {
+    const size_t nrows = C.rows.size();
+    C.off_rows = take(sizeof(int32_t) * std::max<size_t>(nrows, 1));
+    C.off_moff = take(sizeof(int32_t) * (C.nblocks + 1));
+    C.off_mem = take(sizeof(int32_t) * p->ncell);
+    C.off_table = take(sizeof(double) * (size_t)C.nblocks_pad * p->namp);
+    C.off_pack = take(sizeof(double) * nrows * C.nblocks_pad);
+    C.off_partial = take(sizeof(double) * (size_t)C.splits * nrows * p->namp);
+  }
+  p->ws_bytes = off;
+  p->rule = make_gauss_rule();
+  return MPOLE_OK;
+}
+
+// Runs one phase launch, bracketed by timing events when timing is on.
+template <class F>
+hipError_t timed(mpole_plan_t *p, int phase, hipStream_t s, F &&launch) {
+  if (!p->timing) return launch();
+  if (p->ev_used * 2 + 2 > p->ev.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      p->ev.push_back(e);
+    }
+    p->ev_phase.push_back(0);
+  }
+  const size_t k = p->ev_used++;
+  p->ev_phase[k] = phase;
+  hipError_t r = hipEventRecord(p->ev[2 * k], s);
+  if (r == hipSuccess) r = launch();
+  if (r == hipSuccess) r = hipEventRecord(p->ev[2 * k + 1], s);
+  return r;
+}
+
+hipError_t upload(char *ws, size_t off, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpole_abi_version(void) { return MPOLE_ABI_VERSION; }
+
+const char *mpole_last_error(void) { return g_error.c_str(); }
+
+int mpole_plan_create(const mpole_mesh *mesh, mpole_plan *out) {
+  if (!out) return fail(MPOLE_ERR_INVALID, "out is null");
+  try {
+    mpole_plan_t *p = new mpole_plan_t();
+    const int rc = build_plan(mesh, p);
+    if (rc != MPOLE_OK) {
+      delete p;
+      return rc;
+    }
+    *out = p;
+    return ok();
+  } catch (const std::bad_alloc &) {
+    return fail(MPOLE_ERR_INVALID, "host allocation failed");
+  } catch (...) {
+    return fail(MPOLE_ERR_INVALID, "unexpected host exception");
+  }
+}
+
+size_t mpole_plan_workspace_bytes(mpole_plan p) { return p ? p->ws_bytes : 0; }
+
+int mpole_plan_nmodes(mpole_plan p) { return p ? p->nam : 0; }
+
+int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!dev_ws) return fail(MPOLE_ERR_WORKSPACE, "workspace is null");
+  if (((uintptr_t)dev_ws & 255) != 0) return fail(MPOLE_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < p->ws_bytes)
+    return fail(MPOLE_ERR_WORKSPACE, "workspace has %zu bytes, plan needs %zu", bytes, p->ws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)dev_ws;
+  PlanDev &D = p->dev;
+  D = PlanDev{};
+  D.nr = p->nr;
+  D.ntheta = p->nt;
+  D.nphi = p->np;
+  D.lmax = p->L;
+  D.nam = p->nam;
+  D.namp = p->namp;
+  D.ncell = p->ncell;
+  D.nclasses = p->ncls;
+  D.nplanes = 0;
+  D.G = p->G;
+  D.r_edges = (const double *)(ws + p->off_r);
+  D.theta_edges = (const double *)(ws + p->off_th);
+  D.phi_edges = (const double *)(ws + p->off_ph);
+  D.shell_class = (const int32_t *)(ws + p->off_shell_class);
+  D.shell_row = (const int32_t *)(ws + p->off_shell_row);
+  D.classes = (ClassDev *)(ws + p->off_classes);
+  D.pavg = (double *)(ws + p->off_pavg);
+  D.trig = (double *)(ws + p->off_trig);
+  D.weight = (double *)(ws + p->off_weight);
+  D.jr = (double *)(ws + p->off_jr);
+  D.ji = (double *)(ws + p->off_ji);
+  D.rr = (double *)(ws + p->off_rr);
+  D.ri = (double *)(ws + p->off_ri);
+  D.ang = (double *)(ws + p->off_ang);
+  D.coef = (double *)(ws + p->off_coef);
+  D.edge_r = (double *)(ws + p->off_edge_r);
+  D.edge_i = (double *)(ws + p->off_edge_i);
+  p->cdev.assign(p->ncls, ClassDev{});
+  for (int c = 0; c < p->ncls; ++c) {
+    const ClassHost &H = p->cls[c];
+    ClassDev &C = p->cdev[c];
+    C.rows = (const int32_t *)(ws + H.off_rows);
+    C.moff = (const int32_t *)(ws + H.off_moff);
+    C.mem = (const int32_t *)(ws + H.off_mem);
+    C.table = (double *)(ws + H.off_table);
+    C.pack = (double *)(ws + H.off_pack);
+    C.partial = (double *)(ws + H.off_partial);
+    C.nrows = (int)H.rows.size();
+    C.nblocks = H.nblocks;
+    C.nblocks_pad = H.nblocks_pad;
+    C.splits = H.splits;
+    C.kchunk = H.kchunk;
+    C.m_tiles = H.m_tiles;
+    C.n_tiles_mom = H.n_tiles_mom;
+    C.n_tiles_exp = H.n_tiles_exp;
+    C.wg_mom_begin = H.wg_mom_begin;
+    C.wg_exp_begin = H.wg_exp_begin;
+  }
+  hipError_t e = hipSuccess;
+  // zero the whole workspace first: padding rows/columns of every operand must be 0
+  if (e == hipSuccess) e = launch_fill_zero(ws, p->ws_bytes, s);
+  if (e == hipSuccess) e = upload(ws, p->off_r, p->r.data(), sizeof(double) * p->r.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_th, p->th.data(), sizeof(double) * p->th.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_ph, p->ph.data(), sizeof(double) * p->ph.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_shell_class, p->shell_class.data(), sizeof(int32_t) * p->nr, s);
+  if (e == hipSuccess) e = upload(ws, p->off_shell_row, p->shell_row.data(), sizeof(int32_t) * p->nr, s);
+  if (e == hipSuccess) e = upload(ws, p->off_classes, p->cdev.data(), sizeof(ClassDev) * p->ncls, s);
+  for (int c = 0; c < p->ncls && e == hipSuccess; ++c) {
+    const ClassHost &H = p->cls[c];
+    e = upload(ws, H.off_rows, H.rows.data(), sizeof(int32_t) * H.rows.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_moff, H.moff.data(), sizeof(int32_t) * H.moff.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_mem, H.mem.data(), sizeof(int32_t) * H.mem.size(), s);
+  }
+  if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, s);
+  if (e != hipSuccess) {
+    p->bound = false;
+    return fail(MPOLE_ERR_DEVICE, "bind: %s", hipGetErrorString(e));
+  }
+  p->ws = ws;
+  p->bound = true;
+  return ok();
+}
+
+int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, double *interior, double *exterior,
+                void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!p->bound) return fail(MPOLE_ERR_WORKSPACE, "plan has no bound workspace");
+  if (!rho) return fail(MPOLE_ERR_INVALID, "rho is null");
+  hipStream_t s = (hipStream_t)stream;
+  const PlanDev &D = p->dev;
+  hipError_t e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_f64(D, p->cdev.data(), rho, s); });
+  if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_f64(D, p->wg_mom, s); });
+  if (e == hipSuccess) e = timed(p, MPOLE_PHASE_REDUCE, s, [&] { return launch_reduce(D, ang, s); });
+  if (e == hipSuccess) e = timed(p, MPOLE_PHASE_SCAN, s, [&] { return launch_scan(D, interior, exterior, s); });
+  if (e == hipSuccess && phi)
+    e = timed(p, MPOLE_PHASE_EXPAND, s, [&] { return launch_expand_f64(D, p->wg_exp, phi, s); });
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int mpole_plan_copy_table(mpole_plan p, int32_t cls, double *host_out, int64_t *nblocks, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (cls < 0 || cls >= p->ncls) return fail(MPOLE_ERR_INVALID, "class %d out of range", cls);
+  const ClassHost &H = p->cls[cls];
+  if (nblocks) *nblocks = H.nblocks;
+  if (!host_out) return ok();
+  if (!p->bound) return fail(MPOLE_ERR_WORKSPACE, "plan has no bound workspace");
+  hipStream_t s = (hipStream_t)stream;
+  // rows are namp wide on the device, nAM wide on the host
+  hipError_t e = hipMemcpy2DAsync(host_out, sizeof(double) * p->nam, p->ws + H.off_table, sizeof(double) * p->namp,
+                                  sizeof(double) * p->nam, H.nblocks, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "copy_table: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int mpole_plan_set_timing(mpole_plan p, int enable) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  return ok();
+}
+
+int mpole_plan_phase_ms(mpole_plan p, double *total_ms, int64_t *launches) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!total_ms || !launches) return fail(MPOLE_ERR_INVALID, "output arrays are null");
+  for (int k = 0; k < MPOLE_NPHASES; ++k) {
+    total_ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (size_t k = 0; k < p->ev_used; ++k) {
+    hipError_t e = hipEventSynchronize(p->ev[2 * k + 1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]);
+    if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "phase_ms: %s", hipGetErrorString(e));
+    total_ms[p->ev_phase[k]] += ms;
+    launches[p->ev_phase[k]] += 1;
+  }
+  p->ev_used = 0;
+  return ok();
+}
+
+int mpole_plan_work(mpole_plan p, double *moment_flops, double *expand_flops, double *min_bytes) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  double f = 0.0, tb = 0.0;
+  for (const auto &C : p->cls) {
+    f += 2.0 * (double)C.rows.size() * C.nblocks * p->nam;
+    if (!C.rows.empty()) tb += 8.0 * (double)C.nblocks * p->nam;
+  }
+  if (moment_flops) *moment_flops = f;
+  if (expand_flops) *expand_flops = f;
+  if (min_bytes) *min_bytes = 16.0 * (double)p->nr * p->ncell + tb;
+  return ok();
+}
+
+int mpole_plan_destroy(mpole_plan p) {
+  if (p)
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  delete p;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+"""Python binding of the mpole C ABI (include/mpole.h).
+
+Argument marshalling only: every step of the solve runs in the gfx950 HIP
+kernels of libmpole.so.  PyTorch supplies device memory (the workspace and
+output tensors) and the HIP stream; nothing here computes any part of the
+method, and there is no CPU fallback -- without the built library or a GPU
+every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+FP64, BF16X3, FP16X2 = 0, 1, 2
+_PRECISIONS = {"fp64": FP64, "bf16x3": BF16X3, "fp16x2": FP16X2}
+
+STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE_ERR_WORKSPACE",
+          4: "MPOLE_ERR_DEVICE", 5: "MPOLE_ERR_UNSUPPORTED"}
+
+# every entry point include/mpole.h declares
+EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_plan_workspace_bytes",
+           "mpole_plan_nmodes", "mpole_plan_bind", "mpole_solve", "mpole_plan_copy_table",
+           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_plan_destroy")
+PHASES = ("pack", "moment", "reduce", "scan", "split", "expand")
+
+
+class MpoleError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class MeshC(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int32), ("ntheta", ctypes.c_int32), ("nphi", ctypes.c_int32),
+                ("lmax", ctypes.c_int32),
+                ("r_edges", ctypes.POINTER(ctypes.c_double)),
+                ("theta_edges", ctypes.POINTER(ctypes.c_double)),
+                ("phi_edges", ctypes.POINTER(ctypes.c_double)),
+                ("nclasses", ctypes.c_int32),
+                ("shell_class", ctypes.POINTER(ctypes.c_int32)),
+                ("class_block", ctypes.POINTER(ctypes.c_int32)),
+                ("G", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library_path():
+    return _build.LIB
+
+
+def lib():
+    """Load libmpole.so (building it first only if it is absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.mpole_abi_version.restype = ctypes.c_int
+        L.mpole_last_error.restype = ctypes.c_char_p
+        L.mpole_plan_create.argtypes = [ctypes.POINTER(MeshC), ctypes.POINTER(vp)]
+        L.mpole_plan_workspace_bytes.argtypes = [vp]
+        L.mpole_plan_workspace_bytes.restype = sz
+        L.mpole_plan_nmodes.argtypes = [vp]
+        L.mpole_plan_bind.argtypes = [vp, vp, sz, vp]
+        L.mpole_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.mpole_plan_copy_table.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int64), vp]
+        L.mpole_plan_set_timing.argtypes = [vp, ctypes.c_int]
+        L.mpole_plan_phase_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        dptr = ctypes.POINTER(ctypes.c_double)
+        L.mpole_plan_work.argtypes = [vp, dptr, dptr, dptr]
+        L.mpole_plan_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise MpoleError(rc, lib().mpole_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+def _dev_ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class HostPlan:
+    """A validated plan without device state (mpole_plan_create only)."""
+
+    def __init__(self, r_edges, theta_edges, phi_edges, lmax, shell_class=None, class_block=None,
+                 G=1.0, precision="fp64"):
+        self._keep = [np.ascontiguousarray(r_edges, np.float64), np.ascontiguousarray(theta_edges, np.float64),
+                      np.ascontiguousarray(phi_edges, np.float64)]
+        r, th, ph = self._keep
+        self.nr, self.ntheta, self.nphi = r.size - 1, th.size - 1, ph.size - 1
+        self.lmax = int(lmax)
+        prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        m = MeshC()
+        m.nr, m.ntheta, m.nphi, m.lmax = self.nr, self.ntheta, self.nphi, self.lmax
+        m.r_edges, m.theta_edges, m.phi_edges = _ptr(r, ctypes.c_double), _ptr(th, ctypes.c_double), _ptr(ph, ctypes.c_double)
+        if class_block is not None:
+            cb = np.ascontiguousarray(class_block, np.int32).reshape(-1, self.ntheta * self.nphi)
+            sc = np.ascontiguousarray(shell_class, np.int32)
+            self._keep += [cb, sc]
+            m.nclasses = cb.shape[0]
+            m.shell_class, m.class_block = _ptr(sc, ctypes.c_int32), _ptr(cb, ctypes.c_int32)
+        else:
+            m.nclasses = 0
+        m.G, m.precision = float(G), prec
+        self._mesh = m
+        h = ctypes.c_void_p()
+        _check(lib().mpole_plan_create(ctypes.byref(m), ctypes.byref(h)))
+        self.handle = h
+        self.nmodes = lib().mpole_plan_nmodes(h)
+        self.workspace_bytes = lib().mpole_plan_workspace_bytes(h)
+
+    @classmethod
+    def from_mesh(cls, mesh, precision="fp64"):
+        return cls(mesh.r_edges, mesh.theta_edges, mesh.phi_edges, mesh.lmax, mesh.shell_class,
+                   mesh.class_block, mesh.G, precision)
+
+    def work(self):
+        """(moment flops, expansion flops, minimum HBM bytes) of one solve."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().mpole_plan_work(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_timing(self, enable):
+        _check(lib().mpole_plan_set_timing(self.handle, int(bool(enable))))
+
+    def phase_ms(self):
+        """{phase: (total ms, launches)} since timing was enabled or last read."""
+        ms = (ctypes.c_double * 6)()
+        n = (ctypes.c_int64 * 6)()
+        _check(lib().mpole_plan_phase_ms(self.handle, ms, n))
+        return {PHASES[k]: (ms[k], n[k]) for k in range(6)}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mpole_plan_destroy(h)
+            self.handle = None
+
+
+class Plan(HostPlan):
+    """Plan bound to a device workspace on a torch CUDA (HIP) device."""
+
+    def __init__(self, *args, device="cuda", **kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("mpole needs a ROCm GPU; none is visible to torch")
+        super().__init__(*args, **kw)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_plan_bind(self.handle, ctypes.c_void_p(self._ws_ptr), self.workspace_bytes,
+                                     ctypes.c_void_p(stream)))
+
+    @classmethod
+    def from_mesh(cls, mesh, precision="fp64", device="cuda"):
+        return cls(mesh.r_edges, mesh.theta_edges, mesh.phi_edges, mesh.lmax, mesh.shell_class,
+                   mesh.class_block, mesh.G, precision=precision, device=device)
+
+    @property
+    def shape(self):
+        return (self.nr, self.ntheta, self.nphi)
+
+    def empty_outputs(self, phi=True, ang=True, interior=True, exterior=True):
+        import torch
+        f = lambda shp, want: torch.empty(shp, dtype=torch.float64, device=self.device) if want else None
+        return dict(phi=f(self.shape, phi), ang=f((self.nr, self.nmodes), ang),
+                    interior=f((self.nr + 1, self.nmodes), interior),
+                    exterior=f((self.nr + 1, self.nmodes), exterior))
+
+    def _check_tensor(self, t, shape, name):
+        import torch
+        if t is None:
+            return
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError("%s must be a contiguous float64 tensor on %s" % (name, self.device))
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+    def solve_into(self, rho, phi=None, ang=None, interior=None, exterior=None, stream=None):
+        """Enqueue one solve writing into caller-provided tensors (any may be None but rho)."""
+        import torch
+        self._check_tensor(rho, self.shape, "rho")
+        self._check_tensor(phi, self.shape, "phi")
+        self._check_tensor(ang, (self.nr, self.nmodes), "ang")
+        self._check_tensor(interior, (self.nr + 1, self.nmodes), "interior")
+        self._check_tensor(exterior, (self.nr + 1, self.nmodes), "exterior")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_solve(self.handle, _dev_ptr(rho), _dev_ptr(phi), _dev_ptr(ang), _dev_ptr(interior),
+                                 _dev_ptr(exterior), ctypes.c_void_p(s)))
+
+    def solve(self, rho, **want):
+        out = self.empty_outputs(**want)
+        self.solve_into(rho, **out)
+        return out
+
+    def table(self, cls=0):
+        """FP64 block-mean kernel table of a coarsening class, [nblocks][nAM] (host numpy)."""
+        import torch
+        n = ctypes.c_int64()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_plan_copy_table(self.handle, cls, None, ctypes.byref(n), ctypes.c_void_p(s)))
+        out = np.empty((n.value, self.nmodes))
+        _check(lib().mpole_plan_copy_table(self.handle, cls, out.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.byref(n), ctypes.c_void_p(s)))
+        return out
