@@ -26,10 +26,13 @@ DTYPE = {"fp64": "f64", "bf16x3": "bf16", "fp16x2": "f16"}
 WORKLOADS = {
     # name: (workload generator key, precision)
     "production_fp64": ("production", "fp64"),
+    "production_bf16x3": ("production", "bf16x3"),
     "production_l32_fp64": ("production_l32", "fp64"),
+    "production_l32_bf16x3": ("production_l32", "bf16x3"),
+    "production_l32_fp16x2": ("production_l32", "fp16x2"),
     "spheroid_fp64": ("spheroid", "fp64"),
 }
-DEFAULT = "production_fp64"
+DEFAULT = "production_l32_bf16x3"
 
 
 def parse():
@@ -40,6 +43,7 @@ def parse():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
+    ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path beside a split precision")
     return ap.parse_args()
 
 
@@ -60,10 +64,29 @@ def main():
     dev = torch.device("cuda:0")
     print("bench: workload %s %dx%dx%d lmax %d precision %s" % (args.workload, mesh.nr, mesh.ntheta, mesh.nphi,
                                                                 mesh.lmax, precision), file=sys.stderr, flush=True)
-    plan = mpole.Plan.from_mesh(mesh, precision=precision, device=dev)
     rho = torch.from_numpy(rho_h).to(dev)
-    out = plan.empty_outputs()
     stream = torch.cuda.current_stream(dev)
+
+    fp64 = None
+    if precision != "fp64" and not args.no_fp64:
+        # the plain FP64 GPU solve of the same workload, for the speedup figure
+        p64 = mpole.Plan.from_mesh(mesh, precision="fp64", device=dev)
+        o64 = p64.empty_outputs()
+        for _ in range(args.warmup):
+            p64.solve_into(rho, **o64)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(args.steps):
+            p64.solve_into(rho, **o64)
+        b.record(stream)
+        torch.cuda.synchronize()
+        fp64 = {"ms_per_step": a.elapsed_time(b) / args.steps, "phi": o64["phi"]}
+        del p64
+        print("bench: fp64 path %.4f ms/solve" % fp64["ms_per_step"], file=sys.stderr, flush=True)
+
+    plan = mpole.Plan.from_mesh(mesh, precision=precision, device=dev)
+    out = plan.empty_outputs()
     for _ in range(args.warmup):
         plan.solve_into(rho, **out)
     torch.cuda.synchronize()
@@ -107,6 +130,10 @@ def main():
                          "lmax": mesh.lmax, "precision": precision,
                          "coarsened": mesh.class_block is not None},
               "roofline": roof}
+    if fp64 is not None:
+        result["fp64_ms_per_step"] = fp64["ms_per_step"]
+        result["speedup_vs_fp64"] = fp64["ms_per_step"] / ms
+        result["max_rel_err_vs_fp64_gpu"] = float((out["phi"] - fp64["phi"]).abs().div(fp64["phi"].abs()).max())
 
     if not (args.no_cpu_baseline and args.no_check):
         import oracle

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libmpole.so")
-SOURCES = ["plan.cpp", "tables.hip", "pack.hip", "gemm_f64.hip", "scan.hip"]
+SOURCES = ["plan.cpp", "tables.hip", "pack.hip", "gemm_f64.hip", "scan.hip", "split.hip", "gemm_split.hip"]
 ARCH = "gfx950"
 
 

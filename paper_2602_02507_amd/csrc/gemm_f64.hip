@@ -54,15 +54,14 @@ __device__ inline void mfma_stage(const double (*As)[LDS_LD], const double (*Bs)
   }
 }
 
-// 4 consecutive doubles from a 32-byte aligned address, or zeros
-__device__ inline void load4(const double *p, bool ok, double v[4]) {
-  if (ok) {
-    const double2 x = *reinterpret_cast<const double2 *>(p);
-    const double2 y = *reinterpret_cast<const double2 *>(p + 2);
-    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
-  } else {
-    v[0] = v[1] = v[2] = v[3] = 0.0;
-  }
+// 4 consecutive doubles from a 32-byte aligned address.  The load is
+// unconditional (callers pass a valid address for rows outside the operand
+// and zero them when storing to LDS), so the compiler need not wait for it
+// before the store.
+__device__ inline void load4(const double *p, double v[4]) {
+  const double2 x = *reinterpret_cast<const double2 *>(p);
+  const double2 y = *reinterpret_cast<const double2 *>(p + 2);
+  v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_moment_f64(PlanDev P) {
@@ -91,6 +90,8 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(PlanDev P) {
   const int bk = tid >> 4, bn = (tid & 15) * 4;
   const bool a_ok = (m0 + ar) < nrows;
   const bool b_ok = (n0 + bn) < namp;
+  const double *abase = Pk + (size_t)(a_ok ? m0 + ar : 0) * ldp + ak;
+  const double *bbase = T + (size_t)bk * namp + (b_ok ? n0 + bn : 0);
 
   d4 acc[2][2];
 #pragma unroll
@@ -101,12 +102,12 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(PlanDev P) {
   double av[4], bv[4];
   const int nk = (kend - kbeg) / BK;
   if (nk > 0) {
-    load4(Pk + (size_t)(m0 + ar) * ldp + kbeg + ak, a_ok, av);
-    load4(T + (size_t)(kbeg + bk) * namp + n0 + bn, b_ok, bv);
+    load4(abase + kbeg, av);
+    load4(bbase + (size_t)kbeg * namp, bv);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) As[0][ak + e][ar] = av[e];
+    for (int e = 0; e < 4; ++e) As[0][ak + e][ar] = a_ok ? av[e] : 0.0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) Bs[0][bk][bn + e] = bv[e];
+    for (int e = 0; e < 4; ++e) Bs[0][bk][bn + e] = b_ok ? bv[e] : 0.0;
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
@@ -114,15 +115,15 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(PlanDev P) {
     const bool more = kt + 1 < nk;
     if (more) {
       const int k = kbeg + (kt + 1) * BK;
-      load4(Pk + (size_t)(m0 + ar) * ldp + k + ak, a_ok, av);
-      load4(T + (size_t)(k + bk) * namp + n0 + bn, b_ok, bv);
+      load4(abase + k, av);
+      load4(bbase + (size_t)k * namp, bv);
     }
     mfma_stage(As[cur], Bs[cur], wm, wn, lane, acc);
     if (more) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[cur ^ 1][ak + e][ar] = av[e];
+      for (int e = 0; e < 4; ++e) As[cur ^ 1][ak + e][ar] = a_ok ? av[e] : 0.0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][bk][bn + e] = bv[e];
+      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][bk][bn + e] = b_ok ? bv[e] : 0.0;
     }
     __syncthreads();
   }
@@ -173,27 +174,27 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(PlanDev P, double *__re
 
   double av[4], bv[4];
   const int nk = namp / BK;
-  load4(arow + lk, a_ok, av);
-  load4(brow + lk, b_ok, bv);
+  load4(arow + lk, av);
+  load4(brow + lk, bv);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) As[0][lk + e][lr] = av[e];
+  for (int e = 0; e < 4; ++e) As[0][lk + e][lr] = a_ok ? av[e] : 0.0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) Bs[0][lk + e][lr] = bv[e];
+  for (int e = 0; e < 4; ++e) Bs[0][lk + e][lr] = b_ok ? bv[e] : 0.0;
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) {
       const int k = (kt + 1) * BK;
-      load4(arow + k + lk, a_ok, av);
-      load4(brow + k + lk, b_ok, bv);
+      load4(arow + k + lk, av);
+      load4(brow + k + lk, bv);
     }
     mfma_stage(As[cur], Bs[cur], wm, wn, lane, acc);
     if (more) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[cur ^ 1][lk + e][lr] = av[e];
+      for (int e = 0; e < 4; ++e) As[cur ^ 1][lk + e][lr] = a_ok ? av[e] : 0.0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][lk + e][lr] = bv[e];
+      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][lk + e][lr] = b_ok ? bv[e] : 0.0;
     }
     __syncthreads();
   }
@@ -211,8 +212,14 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(PlanDev P, double *__re
         const int b = n0 + wn * 32 + u * 16 + (lane & 15);
         if (b >= C.nblocks) continue;
         const double v = acc[t][u][r];
-        const int e1 = C.moff[b + 1];
-        for (int e = C.moff[b]; e < e1; ++e) dst[C.mem[e]] = v;
+        if (C.rect != nullptr) {
+          const int4 q = C.rect[b];
+          for (int j = q.x; j < q.x + q.z; ++j)
+            for (int k = q.y; k < q.y + q.w; ++k) dst[j * P.nphi + k] = v;
+        } else {
+          const int e1 = C.moff[b + 1];
+          for (int e = C.moff[b]; e < e1; ++e) dst[C.mem[e]] = v;
+        }
       }
     }
 }

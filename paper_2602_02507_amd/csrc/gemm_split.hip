@@ -1,0 +1,272 @@
+// The two angular contractions with split narrow-float operands on MFMA
+// (v_mfma_f32_32x32x16_bf16 / _f16) with FP32 accumulation.
+//
+//   moment:  A[i][n]   = s_i sum_b  Ps[i][b] TT[n][b]      (Ps = P / s_i, split)
+//   expand:  Phi[i][b] = c_i sum_n  Cs[i][n] T[b][n]       (Cs = C / c_i, split)
+//
+// Both are "NT" products, out[m][n] = sum_k X[m][k] Y[n][k].  Every split
+// operand is stored k-slab major with its planes interleaved,
+// [k/16][row][plane][k%16] (the moment contraction reads a transposed copy of
+// the kernel table), so one 16-wide K stage of 128 consecutive rows is a
+// contiguous run that moves to LDS as fully coalesced 16-byte copies, and each
+// lane's MFMA fragment is one 16-byte LDS read.  With x = x_hi + x_mid + x_lo (BF16 x3) the product keeps the six
+// terms hi.hi, hi.mid, mid.hi, hi.lo, lo.hi, mid.mid (the dropped ones are
+// below 2^-24 relative); with FP16 x2 the three terms hi.hi, hi.lo, lo.hi.
+//
+// Workgroup: 4 wavefronts in 2 x 2, tile 128 x 128, each wavefront 64 x 64 as
+// 2 x 2 MFMA 32x32 tiles; K advances 16 per LDS stage (one MFMA step),
+// double-buffered in LDS with loads issued two stages ahead.  Accumulation is FP32.  The monopole (l = 0) carries most
+// of both sums for the near-spherical sources of interest, so it is taken out
+// of the FP32 sums and done in FP64 elsewhere: the monopole moment is summed in
+// FP64 by the packing kernel, and the expansion coefficient of l = 0 is zeroed
+// in the split planes and its term C_i0 T_b0 added in FP64 here, in the
+// epilogue.  The FP32 sums then only carry the (small) l >= 1 remainder.
+//
+// 32x32x16 lane layout on gfx950 (checked on the device): lane l supplies
+// X[l%32][8(l/32) .. 8(l/32)+7] and Y[l%32][same k]; result register r of lane
+// l holds out[(r%4) + 8(r/4) + 4(l/32)][l%32].
+#include "mpole_internal.h"
+
+namespace mpole {
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));   // 16 raw bytes
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 128, TN = 128, TK = 16, NTH = 256;
+
+__device__ inline int xcd_remap(int w, int g) {
+  const int q = g >> 3, r = g & 7, x = w & 7;
+  return x * q + min(x, r) + (w >> 3);
+}
+
+template <int KIND>
+struct Split;
+template <>
+struct Split<kSplitBf16x3> {
+  static constexpr int planes = 3, products = 6;
+  // (x plane, y plane) of each kept product
+  static constexpr int px[6] = {0, 0, 1, 0, 2, 1};
+  static constexpr int py[6] = {0, 1, 0, 2, 0, 1};
+  __device__ static inline f16v mfma(u4 a, u4 b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+  }
+};
+template <>
+struct Split<kSplitFp16x2> {
+  static constexpr int planes = 2, products = 3;
+  static constexpr int px[3] = {0, 0, 1};
+  static constexpr int py[3] = {0, 1, 0};
+  __device__ static inline f16v mfma(u4 a, u4 b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+  }
+};
+
+// Operand source: element (row, k, plane) at base + ((k/16) rows + row) 16 NP + 16 plane + k%16.
+struct Operand {
+  const uint16_t *base;
+  int rows;
+};
+
+template <int KIND, bool EXPAND>
+__global__ __launch_bounds__(NTH) void k_gemm_split(PlanDev P, double *__restrict__ phi) {
+  using S = Split<KIND>;
+  constexpr int NP = S::planes;
+  __shared__ u4 Xs[2][NP][TM][2];   // [stage][plane][row][k half]: 16 narrow floats per row
+  __shared__ u4 Ys[2][NP][TN][2];
+
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  int c = 0;
+  if (EXPAND) {
+    while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_exp_begin) ++c;
+  } else {
+    while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_mom_begin) ++c;
+  }
+  const ClassDev C = P.classes[c];
+  const int local = wg - (EXPAND ? C.wg_exp_begin : C.wg_mom_begin);
+  const int mt = local % C.m_tiles;
+  const int rest = local / C.m_tiles;
+  int nt, split = 0;
+  if (EXPAND) {
+    nt = rest;
+  } else {
+    nt = rest % C.n_tiles_mom;
+    split = rest / C.n_tiles_mom;
+  }
+  const int m0 = mt * TM, n0 = nt * TN;
+  const int M = C.nrows;
+  const int N = EXPAND ? C.nblocks : P.namp;
+  int kbeg, kend;
+  if (EXPAND) {
+    kbeg = 0;
+    kend = P.namp;
+  } else {
+    kbeg = split * C.kchunk;
+    kend = min(kbeg + C.kchunk, C.nblocks_pad);
+  }
+  // operands, k-slab major with interleaved planes
+  Operand X, Y;
+  if (EXPAND) {
+    X = {P.cplanes, P.nr};
+    Y = {C.tplanes, C.nblocks_pad};
+  } else {
+    X = {C.ppacks, C.nrows};
+    Y = {C.ttplanes, P.namp};
+  }
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  // loader roles: a stage row is 2 NP chunks of 16 bytes (plane, k half);
+  // thread t moves chunks t + 256 u, u < NP, of the 128-row tile
+  constexpr int CH = 2 * NP;
+  const int yrow_max = EXPAND ? C.nblocks_pad : P.namp;
+  int l_row[NP], l_pl[NP], l_h[NP];
+  bool x_ok[NP], y_ok[NP];
+  size_t x_off[NP], y_off[NP];   // element offsets within a k slab
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int j = tid + NTH * u;
+    l_row[u] = j / CH;
+    const int ch = j % CH;
+    l_pl[u] = ch >> 1;
+    l_h[u] = ch & 1;
+    x_ok[u] = (m0 + l_row[u]) < M;
+    y_ok[u] = (n0 + l_row[u]) < yrow_max;
+    const int xr = EXPAND ? (x_ok[u] ? C.rows[m0 + l_row[u]] : 0) : (x_ok[u] ? m0 + l_row[u] : 0);
+    const int yr = y_ok[u] ? n0 + l_row[u] : 0;
+    x_off[u] = (size_t)xr * (16 * NP) + 8 * ch;
+    y_off[u] = (size_t)yr * (16 * NP) + 8 * ch;
+  }
+  const size_t x_slab = (size_t)X.rows * 16 * NP, y_slab = (size_t)Y.rows * 16 * NP;
+
+  f16v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
+
+  // two register sets of staged operands: the loads of stage k+2 are issued
+  // before stage k is computed and land in LDS only after stage k+1 is, so
+  // each load has two stages of MFMA work to hide behind.  Loads are
+  // unconditional (rows outside the operand read row 0 and are zeroed at the
+  // LDS store) and go through global address-space pointers, so nothing waits
+  // on them before the store.
+  typedef const __attribute__((address_space(1))) u4 *gptr;
+  u4 xa[NP], ya[NP], xb[NP], yb[NP];
+  const u4 zero = {0u, 0u, 0u, 0u};
+#define GLOAD(XV, YV, K)                                                           \
+  {                                                                                \
+    const size_t kx_ = (size_t)((K) >> 4) * x_slab, ky_ = (size_t)((K) >> 4) * y_slab; \
+    _Pragma("unroll") for (int u = 0; u < NP; ++u) {                               \
+      XV[u] = *(gptr)(X.base + kx_ + x_off[u]);                                    \
+      YV[u] = *(gptr)(Y.base + ky_ + y_off[u]);                                    \
+    }                                                                              \
+  }
+#define LSTORE(XV, YV, BUF)                                                        \
+  {                                                                                \
+    _Pragma("unroll") for (int u = 0; u < NP; ++u) {                               \
+      Xs[BUF][l_pl[u]][l_row[u]][l_h[u]] = x_ok[u] ? XV[u] : zero;                 \
+      Ys[BUF][l_pl[u]][l_row[u]][l_h[u]] = y_ok[u] ? YV[u] : zero;                 \
+    }                                                                              \
+  }
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+    u4 fa[2][NP], fb[2][NP];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        fa[t][p] = Xs[buf][p][wm * 64 + t * 32 + (lane & 31)][lane >> 5];
+        fb[t][p] = Ys[buf][p][wn * 64 + t * 32 + (lane & 31)][lane >> 5];
+      }
+#pragma unroll
+    for (int q = 0; q < S::products; ++q)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = S::mfma(fa[a][S::px[q]], fb[b][S::py[q]], acc[a][b]);
+  };
+
+  const int nk = (kend - kbeg) / TK;
+  if (nk > 0) GLOAD(xa, ya, kbeg);
+  if (nk > 1) GLOAD(xb, yb, kbeg + TK);
+  if (nk > 0) LSTORE(xa, ya, 0);
+  __syncthreads();
+  int kt = 0;
+  // prefetches past the last stage re-read the last stage (branch-free, so
+  // the wait before each LDS store covers only the older register set)
+  const int klast = kend - TK;
+  for (; kt + 1 < nk; kt += 2) {
+    // even stage kt from LDS 0; register set b holds stage kt+1
+    GLOAD(xa, ya, min(kbeg + (kt + 2) * TK, klast));
+    compute(0);
+    LSTORE(xb, yb, 1);
+    __syncthreads();
+    // odd stage kt+1 from LDS 1; register set a holds stage kt+2
+    GLOAD(xb, yb, min(kbeg + (kt + 3) * TK, klast));
+    compute(1);
+    if (kt + 2 < nk) LSTORE(xa, ya, 0);
+    __syncthreads();
+  }
+#undef GLOAD
+#undef LSTORE
+  if (kt < nk) compute(0);   // odd stage count: the last stage sits in LDS 0
+
+  // epilogue: undo the row scale in FP64
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = m0 + wm * 64 + a * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+      if (row >= M) continue;
+      if (EXPAND) {
+        const int shell = C.rows[row];
+        const double sc = P.cscale[shell];
+        const double c0 = P.coef[(size_t)shell * P.namp];   // l = 0 coefficient, FP64
+        double *__restrict__ dst = phi + (size_t)shell * P.ncell;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int blk = n0 + wn * 64 + b * 32 + (lane & 31);
+          if (blk >= N) continue;
+          const double v = c0 * C.table[(size_t)blk * P.namp] + sc * (double)acc[a][b][r];
+          if (C.rect != nullptr) {
+            const int4 q = C.rect[blk];
+            for (int j = q.x; j < q.x + q.z; ++j)
+              for (int k = q.y; k < q.y + q.w; ++k) dst[j * P.nphi + k] = v;
+          } else {
+            for (int e = C.moff[blk]; e < C.moff[blk + 1]; ++e) dst[C.mem[e]] = v;
+          }
+        }
+      } else {
+        const double sc = C.pscale[row];
+        double *__restrict__ out = C.partial + ((size_t)split * M + row) * P.namp;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int col = n0 + wn * 64 + b * 32 + (lane & 31);
+          if (col < N) out[col] = sc * (double)acc[a][b][r];
+        }
+      }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_moment_split(const PlanDev &P, int total_wgs, int kind, hipStream_t s) {
+  if (total_wgs <= 0) return hipSuccess;
+  if (kind == kSplitBf16x3)
+    hipLaunchKernelGGL((k_gemm_split<kSplitBf16x3, false>), dim3(total_wgs), dim3(NTH), 0, s, P, nullptr);
+  else
+    hipLaunchKernelGGL((k_gemm_split<kSplitFp16x2, false>), dim3(total_wgs), dim3(NTH), 0, s, P, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_split(const PlanDev &P, int total_wgs, int kind, double *phi, hipStream_t s) {
+  if (total_wgs <= 0) return hipSuccess;
+  if (kind == kSplitBf16x3)
+    hipLaunchKernelGGL((k_gemm_split<kSplitBf16x3, true>), dim3(total_wgs), dim3(NTH), 0, s, P, phi);
+  else
+    hipLaunchKernelGGL((k_gemm_split<kSplitFp16x2, true>), dim3(total_wgs), dim3(NTH), 0, s, P, phi);
+  return hipGetLastError();
+}
+
+}  // namespace mpole

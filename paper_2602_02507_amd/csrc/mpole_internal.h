@@ -22,8 +22,10 @@ struct ClassDev {
   const int32_t *rows;   // [nrows] global shell of each class row, ascending
   const int32_t *moff;   // [nblocks+1] CSR offsets of block members
   const int32_t *mem;    // [ncell] member fine-cell index j*nphi+k, ascending per block
+  const int4 *rect;      // [nblocks] (j0, k0, nj, nk) when every block is a theta-phi rectangle, else null
   double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, zero padded
-  uint16_t *tplanes;     // [nplanes][nblocks_pad][namp] split planes (mixed precision) or null
+  uint16_t *tplanes;     // [nplanes][nblocks_pad][namp] split planes of table (expansion operand)
+  uint16_t *ttplanes;    // [nplanes][namp][nblocks_pad] split planes of the transposed table (moment operand)
   double *pack;          // [nrows][nblocks_pad] FP64 packed S*dOmega (FP64 path)
   uint16_t *ppacks;      // [nplanes][nrows][nblocks_pad] split planes of the packed source
   double *pscale;        // [nrows] power-of-two row scales of the packed source
@@ -51,8 +53,13 @@ struct PlanDev {
   double *coef;      // [nr][namp] expansion coefficients
   uint16_t *cplanes; // [nplanes][nr][namp] split planes of coef
   double *cscale;    // [nr] row scales of coef
+  double *mono;      // [nr] FP64 monopole moments (split precisions), or null
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
 };
+
+// Split precisions: operands are sums of nplanes narrow floats (hi + mid + lo),
+// stored as raw 16-bit patterns.
+enum SplitKind { kSplitBf16x3 = 1, kSplitFp16x2 = 2 };
 
 // ---- launchers (all asynchronous on `s`; return hipSuccess or the launch error)
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
@@ -64,5 +71,11 @@ hipError_t launch_moment_f64(const PlanDev &P, int total_wgs, hipStream_t s);
 hipError_t launch_reduce(const PlanDev &P, double *ang_out, hipStream_t s);
 hipError_t launch_scan(const PlanDev &P, double *interior, double *exterior, hipStream_t s);
 hipError_t launch_expand_f64(const PlanDev &P, int total_wgs, double *phi, hipStream_t s);
+// split precisions
+hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, int kind, hipStream_t s);
+hipError_t launch_pack_split(const PlanDev &P, const double *rho, int kind, hipStream_t s);
+hipError_t launch_split_coef(const PlanDev &P, int kind, hipStream_t s);
+hipError_t launch_moment_split(const PlanDev &P, int total_wgs, int kind, hipStream_t s);
+hipError_t launch_expand_split(const PlanDev &P, int total_wgs, int kind, double *phi, hipStream_t s);
 
 }  // namespace mpole

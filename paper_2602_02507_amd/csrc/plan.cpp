@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -71,10 +72,18 @@ GaussRule make_gauss_rule() {
 
 struct ClassHost {
   std::vector<int32_t> rows, moff, mem;
+  std::vector<int32_t> rect;  // 4 per block when every block is a rectangle in (j, k)
+  size_t off_rect = 0;
   int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
   int m_tiles = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
   size_t off_rows = 0, off_moff = 0, off_mem = 0, off_table = 0, off_pack = 0, off_partial = 0;
+  size_t off_tplanes = 0, off_ttplanes = 0, off_ppacks = 0, off_pscale = 0;
 };
+
+// planes of a split precision (0 for FP64)
+int n_planes(int precision) {
+  return precision == MPOLE_BF16X3 ? 3 : precision == MPOLE_FP16X2 ? 2 : 0;
+}
 
 }  // namespace
 
@@ -87,7 +96,8 @@ struct mpole_plan_t {
   size_t ws_bytes = 0;
   size_t off_r = 0, off_th = 0, off_ph = 0, off_shell_class = 0, off_shell_row = 0, off_classes = 0;
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
-  size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0;
+  size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0;
+  int nplanes = 0, tile = 64;
   int wg_mom = 0, wg_exp = 0;
   GaussRule rule{};
   // per-phase timing events (host objects), recorded while timing is on
@@ -136,8 +146,8 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     return fail(MPOLE_ERR_INVALID, "mesh sizes must be >= 1 (nr=%d ntheta=%d nphi=%d)", m->nr, m->ntheta, m->nphi);
   if (m->lmax < 0) return fail(MPOLE_ERR_INVALID, "lmax must be >= 0");
   if (m->lmax > MPOLE_LMAX_MAX) return fail(MPOLE_ERR_UNSUPPORTED, "lmax %d above %d", m->lmax, MPOLE_LMAX_MAX);
-  if (m->precision != MPOLE_FP64)
-    return fail(MPOLE_ERR_UNSUPPORTED, "precision %d is not available in this build", m->precision);
+  if (m->precision != MPOLE_FP64 && m->precision != MPOLE_BF16X3 && m->precision != MPOLE_FP16X2)
+    return fail(MPOLE_ERR_UNSUPPORTED, "unknown precision %d", m->precision);
   if (!std::isfinite(m->G)) return fail(MPOLE_ERR_INVALID, "G is not finite");
   const long long ncell = (long long)m->ntheta * m->nphi;
   if (ncell > (1LL << 30) || (long long)m->nr * ncell > (1LL << 40))
@@ -167,6 +177,8 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->namp = round_up(p->nam, kModePad);
   p->ncell = (int)ncell;
   p->precision = m->precision;
+  p->nplanes = n_planes(m->precision);
+  p->tile = p->nplanes ? 128 : 64;   // output tile edge of the contraction kernels
   p->G = m->G;
   p->r.assign(m->r_edges, m->r_edges + m->nr + 1);
   p->th.assign(m->theta_edges, m->theta_edges + m->ntheta + 1);
@@ -207,11 +219,31 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     C.mem.assign(p->ncell, 0);
     std::vector<int32_t> fillp(C.moff.begin(), C.moff.end() - 1);
     for (int q = 0; q < p->ncell; ++q) C.mem[fillp[id[q]]++] = q;   // ascending q per block
-    C.m_tiles = std::max(1, ((int)C.rows.size() + 63) / 64);
-    C.n_tiles_mom = (p->namp + 63) / 64;
-    C.n_tiles_exp = (C.nblocks + 63) / 64;
+    // rectangle descriptors: a block is a rectangle when its member count
+    // equals the area of its bounding box in (theta row, phi column)
+    C.rect.assign(4 * (size_t)nb, 0);
+    bool rect_ok = true;
+    for (int b = 0; b < nb && rect_ok; ++b) {
+      int j0 = p->nt, j1 = -1, k0 = p->np, k1 = -1;
+      for (int e = C.moff[b]; e < C.moff[b + 1]; ++e) {
+        const int j = C.mem[e] / p->np, k = C.mem[e] % p->np;
+        j0 = std::min(j0, j); j1 = std::max(j1, j);
+        k0 = std::min(k0, k); k1 = std::max(k1, k);
+      }
+      if ((j1 - j0 + 1) * (k1 - k0 + 1) != C.moff[b + 1] - C.moff[b]) rect_ok = false;
+      C.rect[4 * b] = j0;
+      C.rect[4 * b + 1] = k0;
+      C.rect[4 * b + 2] = j1 - j0 + 1;
+      C.rect[4 * b + 3] = k1 - k0 + 1;
+    }
+    if (!rect_ok) C.rect.clear();
+    C.m_tiles = std::max(1, ((int)C.rows.size() + p->tile - 1) / p->tile);
+    C.n_tiles_mom = (p->namp + p->tile - 1) / p->tile;
+    C.n_tiles_exp = (C.nblocks + p->tile - 1) / p->tile;
   }
-  choose_splits(*p, 512);
+  int target = 1024;
+  if (const char *env = std::getenv("MPOLE_MOMENT_WGS")) target = std::max(1, std::atoi(env));
+  choose_splits(*p, target);
   int wm = 0, we = 0;
   for (auto &C : p->cls) {
     C.wg_mom_begin = wm;
@@ -249,14 +281,22 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->off_coef = take(sizeof(double) * (size_t)p->nr * p->namp);
   p->off_edge_r = take(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
   p->off_edge_i = take(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
+  p->off_cplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * p->nr * p->namp);
+  p->off_cscale = take(sizeof(double) * (size_t)p->nr);
+  p->off_mono = take(sizeof(double) * (size_t)p->nr);
   for (auto &C : p->cls) {
     const size_t nrows = C.rows.size();
     C.off_rows = take(sizeof(int32_t) * std::max<size_t>(nrows, 1));
     C.off_moff = take(sizeof(int32_t) * (C.nblocks + 1));
     C.off_mem = take(sizeof(int32_t) * p->ncell);
+    C.off_rect = take(sizeof(int32_t) * C.rect.size());
     C.off_table = take(sizeof(double) * (size_t)C.nblocks_pad * p->namp);
     C.off_pack = take(sizeof(double) * nrows * C.nblocks_pad);
     C.off_partial = take(sizeof(double) * (size_t)C.splits * nrows * p->namp);
+    C.off_tplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
+    C.off_ttplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
+    C.off_ppacks = take(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.nblocks_pad);
+    C.off_pscale = take(sizeof(double) * std::max<size_t>(nrows, 1));
   }
   p->ws_bytes = off;
   p->rule = make_gauss_rule();
@@ -337,7 +377,7 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   D.namp = p->namp;
   D.ncell = p->ncell;
   D.nclasses = p->ncls;
-  D.nplanes = 0;
+  D.nplanes = p->nplanes;
   D.G = p->G;
   D.r_edges = (const double *)(ws + p->off_r);
   D.theta_edges = (const double *)(ws + p->off_th);
@@ -356,6 +396,9 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   D.coef = (double *)(ws + p->off_coef);
   D.edge_r = (double *)(ws + p->off_edge_r);
   D.edge_i = (double *)(ws + p->off_edge_i);
+  D.cplanes = (uint16_t *)(ws + p->off_cplanes);
+  D.cscale = (double *)(ws + p->off_cscale);
+  D.mono = p->nplanes ? (double *)(ws + p->off_mono) : nullptr;
   p->cdev.assign(p->ncls, ClassDev{});
   for (int c = 0; c < p->ncls; ++c) {
     const ClassHost &H = p->cls[c];
@@ -363,9 +406,14 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
     C.rows = (const int32_t *)(ws + H.off_rows);
     C.moff = (const int32_t *)(ws + H.off_moff);
     C.mem = (const int32_t *)(ws + H.off_mem);
+    C.rect = H.rect.empty() ? nullptr : (const int4 *)(ws + H.off_rect);
     C.table = (double *)(ws + H.off_table);
     C.pack = (double *)(ws + H.off_pack);
     C.partial = (double *)(ws + H.off_partial);
+    C.tplanes = (uint16_t *)(ws + H.off_tplanes);
+    C.ttplanes = (uint16_t *)(ws + H.off_ttplanes);
+    C.ppacks = (uint16_t *)(ws + H.off_ppacks);
+    C.pscale = (double *)(ws + H.off_pscale);
     C.nrows = (int)H.rows.size();
     C.nblocks = H.nblocks;
     C.nblocks_pad = H.nblocks_pad;
@@ -391,8 +439,10 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
     e = upload(ws, H.off_rows, H.rows.data(), sizeof(int32_t) * H.rows.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_moff, H.moff.data(), sizeof(int32_t) * H.moff.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_mem, H.mem.data(), sizeof(int32_t) * H.mem.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_rect, H.rect.data(), sizeof(int32_t) * H.rect.size(), s);
   }
   if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, s);
+  if (e == hipSuccess && p->nplanes) e = launch_split_tables(D, p->cdev.data(), p->precision, s);
   if (e != hipSuccess) {
     p->bound = false;
     return fail(MPOLE_ERR_DEVICE, "bind: %s", hipGetErrorString(e));
@@ -409,12 +459,27 @@ int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, doubl
   if (!rho) return fail(MPOLE_ERR_INVALID, "rho is null");
   hipStream_t s = (hipStream_t)stream;
   const PlanDev &D = p->dev;
-  hipError_t e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_f64(D, p->cdev.data(), rho, s); });
-  if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_f64(D, p->wg_mom, s); });
+  hipError_t e;
+  if (p->nplanes == 0) {
+    e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_f64(D, p->cdev.data(), rho, s); });
+    if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_f64(D, p->wg_mom, s); });
+  } else {
+    const int k = p->precision;
+    e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_split(D, rho, k, s); });
+    if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_split(D, p->wg_mom, k, s); });
+  }
   if (e == hipSuccess) e = timed(p, MPOLE_PHASE_REDUCE, s, [&] { return launch_reduce(D, ang, s); });
   if (e == hipSuccess) e = timed(p, MPOLE_PHASE_SCAN, s, [&] { return launch_scan(D, interior, exterior, s); });
-  if (e == hipSuccess && phi)
-    e = timed(p, MPOLE_PHASE_EXPAND, s, [&] { return launch_expand_f64(D, p->wg_exp, phi, s); });
+  if (e == hipSuccess && phi) {
+    if (p->nplanes == 0) {
+      e = timed(p, MPOLE_PHASE_EXPAND, s, [&] { return launch_expand_f64(D, p->wg_exp, phi, s); });
+    } else {
+      const int k = p->precision;
+      e = timed(p, MPOLE_PHASE_SPLIT, s, [&] { return launch_split_coef(D, k, s); });
+      if (e == hipSuccess)
+        e = timed(p, MPOLE_PHASE_EXPAND, s, [&] { return launch_expand_split(D, p->wg_exp, k, phi, s); });
+    }
+  }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
   return ok();
 }

@@ -10,12 +10,13 @@
 //             Solution C[i][n] = -Delta_m/(2l+1) (<r^l> M^I_c + <r^-(l+1)> M^R_c)
 //
 // The scan is a segmented prefix/suffix sum over radius, one segment per mode.
-// A wavefront owns 16 consecutive modes (coalesced 128-byte rows) split into
-// 4 radial chunks, one per 16-lane group: each lane sums its chunk, the four
-// chunk totals are exchanged with wavefront shuffles, and a second pass writes
-// edges and coefficients.  Chunk-boundary edges are always taken from the
-// shuffled totals (never from a lane's running sum), so the two chunks that
-// meet at an edge use bitwise the same value.
+// A workgroup owns 16 consecutive modes (coalesced 128-byte rows) and splits
+// radius into 64 chunks: each thread sums one chunk of one mode, then one
+// wavefront per mode scans the 64 chunk totals with lane shuffles (prefix for
+// the outward sums, suffix for the inward ones), and a second pass writes
+// edges and coefficients.  Chunk-boundary edges are always the scanned totals
+// (never a thread's running sum), so the two chunks meeting at an edge use
+// bitwise the same value.
 #include "mpole_internal.h"
 
 namespace mpole {
@@ -30,18 +31,25 @@ __global__ __launch_bounds__(256) void k_reduce(PlanDev P, double *__restrict__ 
   const double *__restrict__ src = C.partial + (size_t)row * P.namp + n;
   const size_t stride = (size_t)C.nrows * P.namp;
   double s = 0.0;
-  for (int q = 0; q < C.splits; ++q) s += src[q * stride];
+  if (n == 0 && P.mono != nullptr) {
+    s = P.mono[i];   // split precisions: the monopole moment summed in FP64
+  } else {
+    for (int q = 0; q < C.splits; ++q) s += src[q * stride];
+  }
   P.ang[(size_t)i * P.namp + n] = s;
   if (ang_out != nullptr && n < P.nam) ang_out[(size_t)i * P.nam + n] = s;
 }
 
-__global__ __launch_bounds__(256) void k_scan(PlanDev P, double *__restrict__ er, int ld_r,
-                                              double *__restrict__ ei, int ld_i) {
-  const int lane = threadIdx.x & 63;
-  const int slab = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int n = slab * 16 + (lane & 15);
-  if (slab * 16 >= P.namp) return;          // whole wavefront idle
-  const int g = lane >> 4;                  // radial chunk of this lane
+constexpr int SCAN_MODES = 16;    // modes per workgroup (one 128-byte row segment)
+constexpr int SCAN_CHUNKS = 64;   // radial chunks per mode (one per lane of a wavefront)
+
+__global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(PlanDev P, double *__restrict__ er, int ld_r,
+                                                                  double *__restrict__ ei, int ld_i) {
+  __shared__ double tot_r[SCAN_CHUNKS][SCAN_MODES], tot_i[SCAN_CHUNKS][SCAN_MODES];
+  __shared__ double base_r[SCAN_CHUNKS + 1][SCAN_MODES], base_i[SCAN_CHUNKS + 1][SCAN_MODES];
+  const int t = threadIdx.x;
+  const int mode = t % SCAN_MODES, c = t / SCAN_MODES;   // chunk c of mode n
+  const int n = blockIdx.x * SCAN_MODES + mode;
   const int nr = P.nr, L1 = P.lmax + 1, namp = P.namp;
   const bool live = n < P.nam;
   int l = 0;
@@ -50,50 +58,70 @@ __global__ __launch_bounds__(256) void k_scan(PlanDev P, double *__restrict__ er
     while ((l + 1) * (l + 1) <= n) ++l;
     while (l * l > n) --l;
   }
-  const int cs = (nr + 3) / 4;
-  const int i0 = min(nr, g * cs), i1 = min(nr, i0 + cs);
+  const int cs = (nr + SCAN_CHUNKS - 1) / SCAN_CHUNKS;
+  const int i0 = min(nr, c * cs), i1 = min(nr, i0 + cs);
   const double *__restrict__ A = P.ang;
+  const double *__restrict__ jr = P.jr;
+  const double *__restrict__ ji = P.ji;
 
   // pass 1: chunk totals of the regular and irregular increments
   double sr = 0.0, si = 0.0;
-  if (live)
+  if (live) {
+#pragma unroll 8
     for (int i = i0; i < i1; ++i) {
       const double a = A[(size_t)i * namp + n];
-      sr += P.jr[i * L1 + l] * a;
-      si += P.ji[i * L1 + l] * a;
+      sr += jr[i * L1 + l] * a;
+      si += ji[i * L1 + l] * a;
     }
-  // exchange the four chunk totals of this mode (lanes n%16 + 16 q)
-  double tr[4], ti[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    tr[q] = __shfl(sr, (lane & 15) + 16 * q, 64);
-    ti[q] = __shfl(si, (lane & 15) + 16 * q, 64);
   }
-  double base_r = 0.0, base_i = 0.0;      // M^R at edge i0, M^I at edge i1
-  for (int q = 0; q < g; ++q) base_r += tr[q];
-  for (int q = 3; q > g; --q) base_i += ti[q];
+  tot_r[c][mode] = sr;
+  tot_i[c][mode] = si;
+  __syncthreads();
+
+  // wavefront w scans the 64 chunk totals of mode w with lane = chunk:
+  // inclusive prefix (outward) and inclusive suffix (inward) by shuffles
+  {
+    const int w = t / 64, lane = t % 64;
+    double x = tot_r[lane][w];
+    double z = tot_i[lane][w];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const double xu = __shfl_up(x, d, 64);
+      const double zd = __shfl_down(z, d, 64);
+      if (lane >= d) x += xu;
+      if (lane + d < 64) z += zd;
+    }
+    base_r[lane + 1][w] = x;    // M^R at the first edge of chunk lane+1
+    base_i[lane][w] = z;        // M^I at the first edge of chunk lane
+    if (lane == 0) base_r[0][w] = 0.0;
+    if (lane == 63) base_i[SCAN_CHUNKS][w] = 0.0;
+  }
+  __syncthreads();
+
   if (!live) {
     for (int i = i0; i < i1; ++i) P.coef[(size_t)i * namp + n] = 0.0;
     return;
   }
-  // pass 2a: outward edges i0 .. i1-1 (edge i1 belongs to the next chunk)
-  double mr = base_r;
+  // pass 2a: outward edges i0 .. i1-1; chunk boundaries come from base_r only
+  double mr = base_r[c][mode];
+#pragma unroll 8
   for (int i = i0; i < i1; ++i) {
     er[(size_t)i * ld_r + n] = mr;
-    mr += P.jr[i * L1 + l] * A[(size_t)i * namp + n];
+    mr += jr[i * L1 + l] * A[(size_t)i * namp + n];
   }
-  const double mr_end = base_r + sr;        // = base_r of the next chunk, same order
-  if (i1 == nr && i0 < i1) er[(size_t)nr * ld_r + n] = mr_end;
+  const double mr_end = base_r[c + 1][mode];
+  const double mi_end = base_i[c + 1][mode];
+  if (i1 == nr && i0 < i1) {
+    er[(size_t)nr * ld_r + n] = mr_end;
+    ei[(size_t)nr * ld_i + n] = mi_end;
+  }
   // pass 2b: inward edges and the coefficients of Eq. Solution
   const double dm = (n == l * l) ? 1.0 : 2.0;
   const double f = -dm / (2.0 * l + 1.0);
-  double mi = base_i;
-  if (i1 == nr && i0 < i1) ei[(size_t)nr * ld_i + n] = mi;
-  double mr_hi = mr_end;
+  double mi = mi_end, mr_hi = mr_end;
   for (int i = i1 - 1; i >= i0; --i) {
     const double mi_hi = mi;
-    // edge i0 is the previous chunk's base: take it from the shuffled totals
-    mi = (i == i0) ? base_i + si : mi + P.ji[i * L1 + l] * A[(size_t)i * namp + n];
+    mi = (i == i0) ? base_i[c][mode] : mi + ji[i * L1 + l] * A[(size_t)i * namp + n];
     ei[(size_t)i * ld_i + n] = mi;
     const double mr_lo = er[(size_t)i * ld_r + n];
     const double mic = 0.5 * (mi + mi_hi), mrc = 0.5 * (mr_lo + mr_hi);
@@ -114,8 +142,7 @@ hipError_t launch_scan(const PlanDev &P, double *interior, double *exterior, hip
   double *ei = exterior ? exterior : P.edge_i;
   const int ldr = interior ? P.nam : P.namp;
   const int ldi = exterior ? P.nam : P.namp;
-  const int slabs = P.namp / 16;
-  hipLaunchKernelGGL(k_scan, dim3((slabs + 3) / 4), dim3(256), 0, s, P, er, ldr, ei, ldi);
+  hipLaunchKernelGGL(k_scan, dim3(P.namp / SCAN_MODES), dim3(SCAN_MODES * SCAN_CHUNKS), 0, s, P, er, ldr, ei, ldi);
   return hipGetLastError();
 }
 
