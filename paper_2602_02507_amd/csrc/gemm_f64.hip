@@ -20,7 +20,7 @@
 // f64 MFMA 16x16x4 lane layout on gfx950 (checked on the device): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; result element (i, j) sits in
 // lane 16*(i%4) + j, accumulator register i/4.
-#include "mpole_internal.h"
+#include "device_util.h"
 
 namespace mpole {
 namespace {
@@ -29,13 +29,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, NTHREADS = 256;
 constexpr int LDS_LD = BM + 4;  // row stride of an LDS stage, in doubles
-
-// Linear workgroup id -> logical tile id such that XCD x (which receives
-// hardware ids w = x mod 8) owns logical ids [x*q + min(x, r), ...).
-__device__ inline int xcd_remap(int w, int g) {
-  const int q = g >> 3, r = g & 7, x = w & 7;
-  return x * q + min(x, r) + (w >> 3);
-}
 
 __device__ inline void mfma_stage(const double (*As)[LDS_LD], const double (*Bs)[LDS_LD], int wm, int wn,
                                   int lane, d4 acc[2][2]) {

@@ -25,7 +25,7 @@
 // 32x32x16 lane layout on gfx950 (checked on the device): lane l supplies
 // X[l%32][8(l/32) .. 8(l/32)+7] and Y[l%32][same k]; result register r of lane
 // l holds out[(r%4) + 8(r/4) + 4(l/32)][l%32].
-#include "mpole_internal.h"
+#include "device_util.h"
 
 namespace mpole {
 namespace {
@@ -36,11 +36,6 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 constexpr int TM = 128, TN = 128, TK = 16, NTH = 256;
-
-__device__ inline int xcd_remap(int w, int g) {
-  const int q = g >> 3, r = g & 7, x = w & 7;
-  return x * q + min(x, r) + (w >> 3);
-}
 
 template <int KIND>
 struct Split;
@@ -228,7 +223,7 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(PlanDev P, double *__restric
         for (int b = 0; b < 2; ++b) {
           const int blk = n0 + wn * 64 + b * 32 + (lane & 31);
           if (blk >= N) continue;
-          const double v = c0 * C.table[(size_t)blk * P.namp] + sc * (double)acc[a][b][r];
+          const double v = c0 * C.tcol0[blk] + sc * (double)acc[a][b][r];
           if (C.rect != nullptr) {
             const int4 q = C.rect[blk];
             for (int j = q.x; j < q.x + q.z; ++j)

@@ -10,6 +10,7 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kGaussNodes = 16;   // Gauss-Legendre points per theta sub-interval
 constexpr int kModePad = 16;      // nAM is padded to a multiple of this
 constexpr int kBlockPad = 16;     // block counts are padded to a multiple of this
+constexpr int kPackSpan = 1024;   // blocks of one shell per packing workgroup
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.
 struct GaussRule {
@@ -24,6 +25,7 @@ struct ClassDev {
   const int32_t *mem;    // [ncell] member fine-cell index j*nphi+k, ascending per block
   const int4 *rect;      // [nblocks] (j0, k0, nj, nk) when every block is a theta-phi rectangle, else null
   double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, zero padded
+  double *tcol0;         // [nblocks_pad] copy of the table's l = 0 column (contiguous)
   uint16_t *tplanes;     // [nplanes][nblocks_pad][namp] split planes of table (expansion operand)
   uint16_t *ttplanes;    // [nplanes][namp][nblocks_pad] split planes of the transposed table (moment operand)
   double *pack;          // [nrows][nblocks_pad] FP64 packed S*dOmega (FP64 path)
@@ -53,7 +55,9 @@ struct PlanDev {
   double *coef;      // [nr][namp] expansion coefficients
   uint16_t *cplanes; // [nplanes][nr][namp] split planes of coef
   double *cscale;    // [nr] row scales of coef
-  double *mono;      // [nr] FP64 monopole moments (split precisions), or null
+  double *mono_part; // [nr][mono_stride] FP64 partial monopole moments (split precisions), or null
+  double *max_part;  // [nr][mono_stride] partial row maxima of the packed source (FP16 x2)
+  int32_t mono_stride;
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
 };
 
@@ -63,6 +67,8 @@ enum SplitKind { kSplitBf16x3 = 1, kSplitFp16x2 = 2 };
 
 // ---- launchers (all asynchronous on `s`; return hipSuccess or the launch error)
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s);
+int pack_parts(const PlanDev &P, const ClassDev *host_classes);   // packing workgroups per shell
 hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g,
                          hipStream_t s);
 hipError_t launch_pack_f64(const PlanDev &P, const ClassDev *host_classes, const double *rho,
@@ -73,7 +79,8 @@ hipError_t launch_scan(const PlanDev &P, double *interior, double *exterior, hip
 hipError_t launch_expand_f64(const PlanDev &P, int total_wgs, double *phi, hipStream_t s);
 // split precisions
 hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, int kind, hipStream_t s);
-hipError_t launch_pack_split(const PlanDev &P, const double *rho, int kind, hipStream_t s);
+hipError_t launch_pack_split(const PlanDev &P, const ClassDev *host_classes, const double *rho, int kind,
+                             hipStream_t s);
 hipError_t launch_split_coef(const PlanDev &P, int kind, hipStream_t s);
 hipError_t launch_moment_split(const PlanDev &P, int total_wgs, int kind, hipStream_t s);
 hipError_t launch_expand_split(const PlanDev &P, int total_wgs, int kind, double *phi, hipStream_t s);

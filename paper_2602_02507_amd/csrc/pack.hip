@@ -1,52 +1,43 @@
 // Density streaming (the front of the solve): each coarsening block of each
-// shell gets its share of the source, sum over members of 4 pi G dOmega rho,
-// i.e. dOmega_b S_b with S_b the solid-angle weighted block mean (GenASiS II
-// Sec. 2.1 coarsening blocks; Eq. AngularMomentsDiscrete weights dOmega S).
-// One thread per (shell, block); consecutive threads take consecutive blocks
-// whose members are consecutive cells, so reads of rho stay coalesced.
+// shell gets its share of the source, the sum over members of
+// 4 pi G dOmega rho, i.e. dOmega_b S_b with S_b the solid-angle weighted block
+// mean (GenASiS II Sec. 2.1 coarsening blocks; Eq. AngularMomentsDiscrete
+// weights dOmega S).
+//
+// One thread per block of a shell, PACK_UNROLL blocks per thread spaced
+// PACK_THREADS apart; single-cell blocks (the common case) take a branch-free
+// path whose loads are all issued before any is consumed, so enough bytes are
+// in flight to stream rho at HBM rate.  Output by precision:
+//   FP64      the packed row in FP64 (operand of the f64 moment contraction);
+//   BF16 x3   the split planes directly (bfloat16 has the exponent range of
+//             FP32, so the row needs no scaling), plus per-workgroup partial
+//             sums of the FP64 monopole moment sum_b P_b T_b0;
+//   FP16 x2   the FP64 row, per-workgroup partial maxima and monopole sums; a
+//             second kernel scales and splits once the row maximum is known.
 #include <algorithm>
 
-#include "mpole_internal.h"
+#include "device_util.h"
+#include "split_util.h"
 
 namespace mpole {
 namespace {
 
-constexpr int PACK_THREADS = 256, PACK_UNROLL = 4;
+constexpr int PACK_THREADS = 256, PACK_UNROLL = 4, PACK_SPAN = PACK_THREADS * PACK_UNROLL;
+static_assert(PACK_SPAN == kPackSpan, "packing span");
 
-// dOmega S of block b of shell i: members in ascending cell order
-__device__ inline double block_source(const ClassDev &C, const double *__restrict__ w,
-                                      const double *__restrict__ src, int nphi, int b) {
-  double s = 0.0;
-  if (C.rect != nullptr) {
-    const int4 r = C.rect[b];
-    for (int j = r.x; j < r.x + r.z; ++j) {
-      const int q0 = j * nphi;
-      for (int k = r.y; k < r.y + r.w; ++k) s += w[q0 + k] * src[q0 + k];
-    }
-  } else {
-    for (int e = C.moff[b]; e < C.moff[b + 1]; ++e) {
-      const int q = C.mem[e];
-      s += w[q] * src[q];
-    }
-  }
-  return s;
-}
-
-// Each thread packs PACK_UNROLL blocks PACK_THREADS apart.  Single-cell
-// blocks (the common case) take a branch-free path whose loads are all
-// issued before any is consumed, so enough bytes are in flight to stream rho.
-__global__ __launch_bounds__(PACK_THREADS) void k_pack_f64(PlanDev P, const double *__restrict__ rho) {
+template <int MODE>   // 0 = FP64, kSplitBf16x3, kSplitFp16x2
+__global__ __launch_bounds__(PACK_THREADS) void k_pack(PlanDev P, const double *__restrict__ rho) {
+  __shared__ double red[PACK_THREADS / 64];
   const int i = blockIdx.y;
   const ClassDev C = P.classes[P.shell_class[i]];
-  const int b0 = blockIdx.x * (PACK_THREADS * PACK_UNROLL) + threadIdx.x;
-  if (b0 >= C.nblocks) return;
+  const int b0 = blockIdx.x * PACK_SPAN + threadIdx.x;
+  if (blockIdx.x * PACK_SPAN >= C.nblocks) return;   // whole workgroup idle for this class
   const int row = P.shell_row[i];
   const double *__restrict__ src = rho + (size_t)i * P.ncell;
   const double *__restrict__ w = P.weight;
-  double *__restrict__ dst = C.pack + (size_t)row * C.nblocks_pad;
+  double s[PACK_UNROLL];
   if (C.rect != nullptr) {
     int4 r[PACK_UNROLL];
-    double s[PACK_UNROLL];
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
@@ -60,26 +51,98 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack_f64(PlanDev P, const doub
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
-      if (b >= C.nblocks) continue;
-      if (r[u].z != 1 || r[u].w != 1) s[u] = block_source(C, w, src, P.nphi, b);
-      dst[b] = s[u];
+      if (b < C.nblocks && (r[u].z != 1 || r[u].w != 1)) s[u] = block_source(C, w, src, P.nphi, b);
     }
   } else {
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
-      if (b < C.nblocks) dst[b] = block_source(C, w, src, P.nphi, b);
+      s[u] = (b < C.nblocks) ? block_source(C, w, src, P.nphi, b) : 0.0;
+    }
+  }
+  double mono = 0.0, mx = 0.0;
+  if (MODE == kSplitBf16x3) {
+    // split into an LDS copy of this workgroup's 64 k-slab groups of 16
+    // blocks, [group][plane][16], then write each group's 96 contiguous bytes
+    __shared__ uint16_t stage[PACK_SPAN / 16][3][16];
+#pragma unroll
+    for (int u = 0; u < PACK_UNROLL; ++u) {
+      const int bl = threadIdx.x + u * PACK_THREADS;   // block within this workgroup
+      const int b = b0 + u * PACK_THREADS;
+      split_store<kSplitBf16x3>(b < C.nblocks ? s[u] : 0.0, &stage[bl >> 4][0][bl & 15], 16);
+    }
+    __syncthreads();
+    const int g0 = blockIdx.x * (PACK_SPAN / 16);                // first k slab of the workgroup
+    const int ngroups = min(PACK_SPAN / 16, C.nblocks_pad / 16 - g0);
+    const uint4 *st = reinterpret_cast<const uint4 *>(&stage[0][0][0]);
+    for (int v = threadIdx.x; v < ngroups * 6; v += PACK_THREADS) {   // 6 x 16 B per group
+      const int g = v / 6, part = v % 6;
+      uint4 *dst = reinterpret_cast<uint4 *>(C.ppacks + ((size_t)(g0 + g) * C.nrows + row) * 48);
+      dst[part] = st[g * 6 + part];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PACK_UNROLL; ++u) {
+    const int b = b0 + u * PACK_THREADS;
+    if (b >= C.nblocks) continue;
+    if (MODE != kSplitBf16x3) C.pack[(size_t)row * C.nblocks_pad + b] = s[u];
+    if (MODE != 0) {
+      mono += s[u] * C.tcol0[b];
+      mx = fmax(mx, fabs(s[u]));
+    }
+  }
+  if (MODE != 0) {
+    mono = block_sum(mono, red);
+    if (MODE == kSplitFp16x2) mx = block_max(mx, red);
+    if (threadIdx.x == 0) {
+      P.mono_part[(size_t)i * P.mono_stride + blockIdx.x] = mono;
+      if (MODE == kSplitFp16x2) P.max_part[(size_t)i * P.mono_stride + blockIdx.x] = mx;
     }
   }
 }
 
+// FP16 x2: per shell, the row's power-of-two scale from the partial maxima,
+// then the scaled split planes of the FP64 row.
+__global__ __launch_bounds__(256) void k_split_rows_fp16(PlanDev P) {
+  const int i = blockIdx.x;
+  const ClassDev C = P.classes[P.shell_class[i]];
+  const int row = P.shell_row[i];
+  const int nparts = (C.nblocks + PACK_SPAN - 1) / PACK_SPAN;
+  double mx = 0.0;
+  for (int q = 0; q < nparts; ++q) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);
+  const double scale = row_scale(mx);
+  const double inv = 1.0 / scale;   // exact: a power of two
+  const double *__restrict__ prow = C.pack + (size_t)row * C.nblocks_pad;
+  for (int b = threadIdx.x; b < C.nblocks; b += 256)
+    split_store<kSplitFp16x2>(prow[b] * inv, C.ppacks + slab_index<kSplitFp16x2>(row, b, C.nrows), 16);
+  if (threadIdx.x == 0) C.pscale[row] = scale;
+}
+
 }  // namespace
 
-hipError_t launch_pack_f64(const PlanDev &P, const ClassDev *host_classes, const double *rho, hipStream_t s) {
+int pack_parts(const PlanDev &P, const ClassDev *host_classes) {
   int maxb = 0;
   for (int c = 0; c < P.nclasses; ++c) maxb = std::max(maxb, host_classes[c].nblocks);
-  const int per = PACK_THREADS * PACK_UNROLL;
-  hipLaunchKernelGGL(k_pack_f64, dim3((maxb + per - 1) / per, P.nr), dim3(PACK_THREADS), 0, s, P, rho);
+  return (maxb + PACK_SPAN - 1) / PACK_SPAN;
+}
+
+hipError_t launch_pack_f64(const PlanDev &P, const ClassDev *host_classes, const double *rho, hipStream_t s) {
+  const dim3 g(pack_parts(P, host_classes), P.nr);
+  hipLaunchKernelGGL(k_pack<0>, g, dim3(PACK_THREADS), 0, s, P, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_split(const PlanDev &P, const ClassDev *host_classes, const double *rho, int kind,
+                             hipStream_t s) {
+  const dim3 g(pack_parts(P, host_classes), P.nr);
+  if (kind == kSplitBf16x3) {
+    hipLaunchKernelGGL(k_pack<kSplitBf16x3>, g, dim3(PACK_THREADS), 0, s, P, rho);
+  } else {
+    hipLaunchKernelGGL(k_pack<kSplitFp16x2>, g, dim3(PACK_THREADS), 0, s, P, rho);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_rows_fp16, dim3(P.nr), dim3(256), 0, s, P);
+  }
   return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ struct ClassHost {
   int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
   int m_tiles = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
   size_t off_rows = 0, off_moff = 0, off_mem = 0, off_table = 0, off_pack = 0, off_partial = 0;
-  size_t off_tplanes = 0, off_ttplanes = 0, off_ppacks = 0, off_pscale = 0;
+  size_t off_tplanes = 0, off_ttplanes = 0, off_ppacks = 0, off_pscale = 0, off_tcol0 = 0;
 };
 
 // planes of a split precision (0 for FP64)
@@ -96,7 +96,8 @@ struct mpole_plan_t {
   size_t ws_bytes = 0;
   size_t off_r = 0, off_th = 0, off_ph = 0, off_shell_class = 0, off_shell_row = 0, off_classes = 0;
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
-  size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0;
+  size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
+  int mono_stride = 1;
   int nplanes = 0, tile = 64;
   int wg_mom = 0, wg_exp = 0;
   GaussRule rule{};
@@ -283,7 +284,13 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->off_edge_i = take(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
   p->off_cplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * p->nr * p->namp);
   p->off_cscale = take(sizeof(double) * (size_t)p->nr);
-  p->off_mono = take(sizeof(double) * (size_t)p->nr);
+  {
+    int maxb = 0;
+    for (auto &C : p->cls) maxb = std::max(maxb, C.nblocks);
+    p->mono_stride = (maxb + kPackSpan - 1) / kPackSpan;
+  }
+  p->off_mono = take(sizeof(double) * (size_t)p->nr * p->mono_stride);
+  p->off_max = take(sizeof(double) * (size_t)p->nr * p->mono_stride);
   for (auto &C : p->cls) {
     const size_t nrows = C.rows.size();
     C.off_rows = take(sizeof(int32_t) * std::max<size_t>(nrows, 1));
@@ -291,6 +298,7 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     C.off_mem = take(sizeof(int32_t) * p->ncell);
     C.off_rect = take(sizeof(int32_t) * C.rect.size());
     C.off_table = take(sizeof(double) * (size_t)C.nblocks_pad * p->namp);
+    C.off_tcol0 = take(sizeof(double) * (size_t)C.nblocks_pad);
     C.off_pack = take(sizeof(double) * nrows * C.nblocks_pad);
     C.off_partial = take(sizeof(double) * (size_t)C.splits * nrows * p->namp);
     C.off_tplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
@@ -398,7 +406,9 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   D.edge_i = (double *)(ws + p->off_edge_i);
   D.cplanes = (uint16_t *)(ws + p->off_cplanes);
   D.cscale = (double *)(ws + p->off_cscale);
-  D.mono = p->nplanes ? (double *)(ws + p->off_mono) : nullptr;
+  D.mono_part = p->nplanes ? (double *)(ws + p->off_mono) : nullptr;
+  D.max_part = (double *)(ws + p->off_max);
+  D.mono_stride = p->mono_stride;
   p->cdev.assign(p->ncls, ClassDev{});
   for (int c = 0; c < p->ncls; ++c) {
     const ClassHost &H = p->cls[c];
@@ -408,6 +418,7 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
     C.mem = (const int32_t *)(ws + H.off_mem);
     C.rect = H.rect.empty() ? nullptr : (const int4 *)(ws + H.off_rect);
     C.table = (double *)(ws + H.off_table);
+    C.tcol0 = (double *)(ws + H.off_tcol0);
     C.pack = (double *)(ws + H.off_pack);
     C.partial = (double *)(ws + H.off_partial);
     C.tplanes = (uint16_t *)(ws + H.off_tplanes);
@@ -443,6 +454,9 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   }
   if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, s);
   if (e == hipSuccess && p->nplanes) e = launch_split_tables(D, p->cdev.data(), p->precision, s);
+  // unit row scales (BF16 x3 operands are not scaled; FP16 x2 rows overwrite theirs)
+  for (int c = 0; c < p->ncls && e == hipSuccess; ++c)
+    e = launch_fill_value(p->cdev[c].pscale, std::max<size_t>(p->cls[c].rows.size(), 1), 1.0, s);
   if (e != hipSuccess) {
     p->bound = false;
     return fail(MPOLE_ERR_DEVICE, "bind: %s", hipGetErrorString(e));
@@ -465,7 +479,7 @@ int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, doubl
     if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_f64(D, p->wg_mom, s); });
   } else {
     const int k = p->precision;
-    e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_split(D, rho, k, s); });
+    e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_split(D, p->cdev.data(), rho, k, s); });
     if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_split(D, p->wg_mom, k, s); });
   }
   if (e == hipSuccess) e = timed(p, MPOLE_PHASE_REDUCE, s, [&] { return launch_reduce(D, ang, s); });

@@ -31,8 +31,11 @@ __global__ __launch_bounds__(256) void k_reduce(PlanDev P, double *__restrict__ 
   const double *__restrict__ src = C.partial + (size_t)row * P.namp + n;
   const size_t stride = (size_t)C.nrows * P.namp;
   double s = 0.0;
-  if (n == 0 && P.mono != nullptr) {
-    s = P.mono[i];   // split precisions: the monopole moment summed in FP64
+  if (n == 0 && P.mono_part != nullptr) {
+    // split precisions: the monopole moment, summed in FP64 by the packing
+    // workgroups of this shell, in workgroup order
+    const int nparts = (C.nblocks + kPackSpan - 1) / kPackSpan;
+    for (int q = 0; q < nparts; ++q) s += P.mono_part[(size_t)i * P.mono_stride + q];
   } else {
     for (int q = 0; q < C.splits; ++q) s += src[q * stride];
   }

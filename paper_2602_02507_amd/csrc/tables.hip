@@ -122,6 +122,7 @@ __global__ void k_block_table(PlanDev P, ClassDev C) {
     v = num / den;
   }
   C.table[t] = v;
+  if (n == 0) C.tcol0[b] = v;
 }
 
 // b^p - a^p for 0 < a < b without cancellation for thin shells
@@ -160,6 +161,10 @@ __global__ void k_fill_zero(uint4 *p, size_t n16) {
     p[i] = make_uint4(0, 0, 0, 0);
 }
 
+__global__ void k_fill_value(double *p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 inline unsigned grid_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -170,6 +175,13 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
   if (n16 == 0) return hipSuccess;
   const unsigned g = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, (uint4 *)p, n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_value, dim3(g), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 
