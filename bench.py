@@ -44,11 +44,30 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path beside a split precision")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Plain copies of known size, so that the FETCH_SIZE / WRITE_SIZE counters
+    of one dispatch can be converted to bytes: each copy reads and writes
+    exactly mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy calibration: 5 copies of %d MiB" % mib, flush=True)
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.stderr.write("bench.py: this build runs on one GPU only; --gpus %d is not supported\n" % args.gpus)
         sys.exit(2)

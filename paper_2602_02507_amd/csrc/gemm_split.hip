@@ -233,12 +233,13 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(PlanDev P, double *__restric
           }
         }
       } else {
-        const double sc = C.pscale[row];
-        double *__restrict__ out = C.partial + ((size_t)split * M + row) * P.namp;
+        // FP32 partial sums (the accumulator type; the row scale is a power of two)
+        const float sc = (float)C.pscale[row];
+        float *__restrict__ out = reinterpret_cast<float *>(C.partial) + ((size_t)split * M + row) * P.namp;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const int col = n0 + wn * 64 + b * 32 + (lane & 31);
-          if (col < N) out[col] = sc * (double)acc[a][b][r];
+          if (col < N) out[col] = sc * acc[a][b][r];
         }
       }
     }

@@ -8,8 +8,9 @@ namespace mpole {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kGaussNodes = 16;   // Gauss-Legendre points per theta sub-interval
-constexpr int kModePad = 16;      // nAM is padded to a multiple of this
-constexpr int kBlockPad = 16;     // block counts are padded to a multiple of this
+// nAM and the block count of each class are padded to a multiple of the K
+// step of the contraction kernels (16 for both the f64 and the split kernels)
+constexpr int kPadF64 = 16;
 constexpr int kPackSpan = 1024;   // blocks of one shell per packing workgroup
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.

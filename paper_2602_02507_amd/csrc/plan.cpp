@@ -98,7 +98,7 @@ struct mpole_plan_t {
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
-  int nplanes = 0, tile = 64;
+  int nplanes = 0, tile_m = 64, tile_n = 64, kpad = 16;
   int wg_mom = 0, wg_exp = 0;
   GaussRule rule{};
   // per-phase timing events (host objects), recorded while timing is on
@@ -126,7 +126,7 @@ int check_edges(const char *name, const double *e, int n, double lo, double hi) 
 }
 
 // Split-K choice for the moment contraction: spread about `target` workgroups
-// over the classes in proportion to their work, at least one 16-wide K step
+// over the classes in proportion to their work, at least one K step (kpad)
 // per split.
 void choose_splits(mpole_plan_t &p, int target) {
   double total = 0.0;
@@ -135,8 +135,8 @@ void choose_splits(mpole_plan_t &p, int target) {
     const int tiles = c.m_tiles * c.n_tiles_mom;
     const double share = total > 0 ? target * (double)c.rows.size() * c.nblocks_pad / total : 1.0;
     int s = (int)std::lround(share / std::max(tiles, 1));
-    s = std::max(1, std::min(s, c.nblocks_pad / 16));
-    c.kchunk = round_up((c.nblocks_pad + s - 1) / s, 16);
+    s = std::max(1, std::min(s, c.nblocks_pad / p.kpad));
+    c.kchunk = round_up((c.nblocks_pad + s - 1) / s, p.kpad);
     c.splits = (c.nblocks_pad + c.kchunk - 1) / c.kchunk;
   }
 }
@@ -175,11 +175,14 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->np = m->nphi;
   p->L = m->lmax;
   p->nam = (m->lmax + 1) * (m->lmax + 1);
-  p->namp = round_up(p->nam, kModePad);
+  p->kpad = kPadF64;
+  p->namp = round_up(p->nam, p->kpad);
   p->ncell = (int)ncell;
   p->precision = m->precision;
   p->nplanes = n_planes(m->precision);
-  p->tile = p->nplanes ? 128 : 64;   // output tile edge of the contraction kernels
+  // output tiles of the contraction kernels: 64 x 64 (f64 MFMA), 128 x 128 (split)
+  p->tile_m = p->nplanes ? 128 : 64;
+  p->tile_n = p->nplanes ? 128 : 64;
   p->G = m->G;
   p->r.assign(m->r_edges, m->r_edges + m->nr + 1);
   p->th.assign(m->theta_edges, m->theta_edges + m->ntheta + 1);
@@ -214,7 +217,7 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     for (int b = 0; b < nb; ++b)
       if (count[b] == 0) return fail(MPOLE_ERR_INVALID, "class %d: block id %d unused (ids must be dense)", c, b);
     C.nblocks = nb;
-    C.nblocks_pad = round_up(nb, kBlockPad);
+    C.nblocks_pad = round_up(nb, p->kpad);
     C.moff.assign(nb + 1, 0);
     for (int b = 0; b < nb; ++b) C.moff[b + 1] = C.moff[b] + count[b];
     C.mem.assign(p->ncell, 0);
@@ -238,11 +241,12 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       C.rect[4 * b + 3] = k1 - k0 + 1;
     }
     if (!rect_ok) C.rect.clear();
-    C.m_tiles = std::max(1, ((int)C.rows.size() + p->tile - 1) / p->tile);
-    C.n_tiles_mom = (p->namp + p->tile - 1) / p->tile;
-    C.n_tiles_exp = (C.nblocks + p->tile - 1) / p->tile;
+    C.m_tiles = std::max(1, ((int)C.rows.size() + p->tile_m - 1) / p->tile_m);
+    C.n_tiles_mom = (p->namp + p->tile_n - 1) / p->tile_n;
+    C.n_tiles_exp = (C.nblocks + p->tile_n - 1) / p->tile_n;
   }
-  int target = 1024;
+  // about one full round of resident workgroups: 4 per CU (f64 kernel), 3 per CU (split kernel)
+  int target = p->nplanes ? 768 : 1024;
   if (const char *env = std::getenv("MPOLE_MOMENT_WGS")) target = std::max(1, std::atoi(env));
   choose_splits(*p, target);
   int wm = 0, we = 0;
@@ -300,7 +304,8 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     C.off_table = take(sizeof(double) * (size_t)C.nblocks_pad * p->namp);
     C.off_tcol0 = take(sizeof(double) * (size_t)C.nblocks_pad);
     C.off_pack = take(sizeof(double) * nrows * C.nblocks_pad);
-    C.off_partial = take(sizeof(double) * (size_t)C.splits * nrows * p->namp);
+    // split-K partials: FP64 for the f64 kernel, FP32 (the accumulator type) for split precisions
+    C.off_partial = take((p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp);
     C.off_tplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
     C.off_ttplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
     C.off_ppacks = take(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.nblocks_pad);

@@ -28,16 +28,20 @@ __global__ __launch_bounds__(256) void k_reduce(PlanDev P, double *__restrict__ 
   if (n >= P.namp) return;
   const ClassDev C = P.classes[P.shell_class[i]];
   const int row = P.shell_row[i];
-  const double *__restrict__ src = C.partial + (size_t)row * P.namp + n;
+  const size_t off = (size_t)row * P.namp + n;
   const size_t stride = (size_t)C.nrows * P.namp;
   double s = 0.0;
-  if (n == 0 && P.mono_part != nullptr) {
+  if (P.nplanes == 0) {
+    const double *__restrict__ src = C.partial + off;   // FP64 partials
+    for (int q = 0; q < C.splits; ++q) s += src[q * stride];
+  } else if (n == 0) {
     // split precisions: the monopole moment, summed in FP64 by the packing
     // workgroups of this shell, in workgroup order
     const int nparts = (C.nblocks + kPackSpan - 1) / kPackSpan;
     for (int q = 0; q < nparts; ++q) s += P.mono_part[(size_t)i * P.mono_stride + q];
   } else {
-    for (int q = 0; q < C.splits; ++q) s += src[q * stride];
+    const float *__restrict__ src = reinterpret_cast<const float *>(C.partial) + off;   // FP32 partials
+    for (int q = 0; q < C.splits; ++q) s += (double)src[q * stride];
   }
   P.ang[(size_t)i * P.namp + n] = s;
   if (ang_out != nullptr && n < P.nam) ang_out[(size_t)i * P.nam + n] = s;
