@@ -49,6 +49,34 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_NAMES = {("fp64", "moment"): "k_moment_f64", ("fp64", "expand"): "k_expand_f64"}
+
+
+def kernel_name(precision, phase):
+    if precision == "fp64":
+        return KERNEL_NAMES[(precision, phase)]
+    return "k_gemm_split<%s, %s>" % (precision, phase)
+
+
+def measured_traffic(workload, phase):
+    """HBM bytes per launch from the committed counter runs, or None when there
+    is none for this kernel or its source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    cal = data["copy_calibration"]
+    for e in data["entries"]:
+        if e["workload"] != workload or e["phase"] != phase:
+            continue
+        src = os.path.join(ROOT, e["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != e["sha256_16"]:
+            return None
+        return 1024.0 * (cal["fetch_factor"] * e["fetch_kib"] + cal["write_factor"] * e["write_kib"])
+    return None
+
+
 def copy_calibration(mib):
     """Plain copies of known size, so that the FETCH_SIZE / WRITE_SIZE counters
     of one dispatch can be converted to bytes: each copy reads and writes
@@ -137,9 +165,14 @@ def main():
     dtype = DTYPE[precision]
     peak, punit = PEAK[dtype]
     achieved = flops / (dom_ms * 1e-3)
-    roof = {"bound": "mfma", "kernel": "k_%s_%s" % (dom, "f64" if precision == "fp64" else precision),
+    # executed MFMA work: the split precisions run `products` narrow products per
+    # algorithmic multiply-add, over padded tiles
+    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
+    roof = {"bound": "mfma", "kernel": kernel_name(precision, dom),
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
-            "traffic": None, "launch_ms": dom_ms,
+            "traffic": measured_traffic(args.workload, dom), "launch_ms": dom_ms,
+            "algorithmic_flops_per_launch": flops, "narrow_products_per_madd": products,
+            "executed_frac_lower_bound": achieved * products / peak,
             "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
 
     result = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
