@@ -180,8 +180,48 @@ int mpole_plan_phase_ms(mpole_plan plan, double *total_ms, int64_t *launches);
  */
 int mpole_plan_work(mpole_plan plan, double *moment_flops, double *expand_flops, double *min_bytes);
 
+/*
+ * Tuning knob of the moment contraction (host only, before bind): the number
+ * of workgroups its K dimension is split over (0 = default, about one round of
+ * resident workgroups).  Changes mpole_plan_workspace_bytes.  Used by the
+ * autotuner.  mpole_plan_moment_wgs reports the resulting launch size.
+ */
+int mpole_plan_configure(mpole_plan plan, int32_t moment_wgs);
+int mpole_plan_moment_wgs(mpole_plan plan);
+
 /* Free the plan's host memory (the workspace stays the caller's). NULL is a no-op. */
 int mpole_plan_destroy(mpole_plan plan);
+
+/*
+ * Batched solve of many independent fields with uneven meshes and lmax (one
+ * plan per field, all with the same precision).  Every phase of the solve is
+ * ONE kernel launch covering all fields (workgroups are assigned to fields by
+ * prefix sums), so a batch solve is a fixed sequence of at most seven launches
+ * with no host synchronisation, allocation or memset: it can be captured in a
+ * HIP graph and replayed.
+ *
+ * mpole_batch_create: nfields in [1, 4096] meshes (host descriptors, copied);
+ *   MPOLE_ERR_INVALID if their precisions differ.
+ * mpole_batch_configure: optional per-field moment workgroup targets
+ *   ([nfields], 0 = default), before bind.
+ * mpole_batch_bind: binds one device workspace (256-byte aligned) holding all
+ *   fields' plans, builds every field's tables on hip_stream, and records the
+ *   fields' device I/O pointers rho[f] ([nr][ntheta][nphi] FP64 in) and
+ *   phi[f] (same shape, FP64 out); the two host arrays are copied.
+ * mpole_batch_solve: one solve of every field on hip_stream (asynchronous).
+ * mpole_batch_field_ms: after the caller has synchronised the stream, the
+ *   time from the start of the last batch solve to the completion of each
+ *   field's potential, in milliseconds (device wall clock), into ms[nfields].
+ */
+typedef struct mpole_batch_t *mpole_batch;
+int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *out);
+int mpole_batch_configure(mpole_batch batch, const int32_t *moment_wgs);
+size_t mpole_batch_workspace_bytes(mpole_batch batch);
+int mpole_batch_bind(mpole_batch batch, void *dev_workspace, size_t bytes, const double *const *rho,
+                     double *const *phi, void *hip_stream);
+int mpole_batch_solve(mpole_batch batch, void *hip_stream);
+int mpole_batch_field_ms(mpole_batch batch, double *ms);
+int mpole_batch_destroy(mpole_batch batch);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,43 @@ __device__ inline int xcd_remap(int w, int g) {
   return x * q + min(x, r) + (w >> 3);
 }
 
+// Field of workgroup wg in a launch of phase h (binary search of the prefix
+// sums; the searched values are uniform across the workgroup).
+__device__ inline int field_of(const BatchDev &B, int h, int wg) {
+  const int32_t *pre = B.prefix + h * (B.nf + 1);
+  int lo = 0, hi = B.nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= wg) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline SolveIO io_of(const BatchDev &B, int f) { return B.io ? B.io[f] : B.io1; }
+
+// A solve-time workgroup's field, its plan and its workgroup id within the field.
+struct Job {
+  PlanDev P;
+  SolveIO io;
+  int f, local;
+};
+__device__ inline Job job_of(const BatchDev &B, int h, int wg) {
+  Job j;
+  j.f = field_of(B, h, wg);
+  j.P = B.plans[j.f];
+  j.io = io_of(B, j.f);
+  j.local = wg - B.prefix[h * (B.nf + 1) + j.f];
+  return j;
+}
+
+// Completion stamp of a field (wall clock, constant rate), after the whole
+// workgroup has issued its stores.
+__device__ inline void stamp_done(const BatchDev &B, int f) {
+  if (B.stamps == nullptr) return;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&B.stamps[f], (unsigned long long)wall_clock64());
+}
+
 // dOmega_b S_b of block b of one shell: the sum over the block's member
 // cells, in ascending cell order, of 4 pi G dOmega_q rho_q.
 __device__ inline double block_source(const ClassDev &C, const double *__restrict__ w,

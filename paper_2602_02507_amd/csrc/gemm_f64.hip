@@ -57,14 +57,15 @@ __device__ inline void load4(const double *p, double v[4]) {
   v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_moment_f64(PlanDev P) {
+__global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
   __shared__ double As[2][BK][LDS_LD];
   __shared__ double Bs[2][BK][LDS_LD];
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const Job J = job_of(B, PH_MOMENT, xcd_remap(blockIdx.x, gridDim.x));
+  const PlanDev &P = J.P;
   int c = 0;
-  while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_mom_begin) ++c;
+  while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_mom_begin) ++c;
   const ClassDev C = P.classes[c];
-  const int local = wg - C.wg_mom_begin;
+  const int local = J.local - C.wg_mom_begin;
   const int mt = local % C.m_tiles;
   const int rest = local / C.m_tiles;
   const int nt = rest % C.n_tiles_mom;
@@ -134,14 +135,16 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(PlanDev P) {
       }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_expand_f64(PlanDev P, double *__restrict__ phi) {
+__global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
   __shared__ double As[2][BK][LDS_LD];
   __shared__ double Bs[2][BK][LDS_LD];
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const Job J = job_of(B, PH_EXPAND, xcd_remap(blockIdx.x, gridDim.x));
+  const PlanDev &P = J.P;
+  double *__restrict__ phi = J.io.phi;
   int c = 0;
-  while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_exp_begin) ++c;
+  while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_exp_begin) ++c;
   const ClassDev C = P.classes[c];
-  const int local = wg - C.wg_exp_begin;
+  const int local = J.local - C.wg_exp_begin;
   const int mt = local % C.m_tiles;
   const int nt = local / C.m_tiles;
   const int m0 = mt * BM, n0 = nt * BN;
@@ -215,19 +218,20 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(PlanDev P, double *__re
         }
       }
     }
+  stamp_done(B, J.f);
 }
 
 }  // namespace
 
-hipError_t launch_moment_f64(const PlanDev &P, int total_wgs, hipStream_t s) {
-  if (total_wgs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_moment_f64, dim3(total_wgs), dim3(NTHREADS), 0, s, P);
+hipError_t launch_moment_f64(const BatchDev &B, int wgs, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_moment_f64, dim3(wgs), dim3(NTHREADS), 0, s, B);
   return hipGetLastError();
 }
 
-hipError_t launch_expand_f64(const PlanDev &P, int total_wgs, double *phi, hipStream_t s) {
-  if (total_wgs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_expand_f64, dim3(total_wgs), dim3(NTHREADS), 0, s, P, phi);
+hipError_t launch_expand_f64(const BatchDev &B, int wgs, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_f64, dim3(wgs), dim3(NTHREADS), 0, s, B);
   return hipGetLastError();
 }
 

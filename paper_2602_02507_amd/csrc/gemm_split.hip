@@ -66,21 +66,23 @@ struct Operand {
 };
 
 template <int KIND, bool EXPAND>
-__global__ __launch_bounds__(NTH) void k_gemm_split(PlanDev P, double *__restrict__ phi) {
+__global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   using S = Split<KIND>;
   constexpr int NP = S::planes;
   __shared__ u4 Xs[2][NP][TM][2];   // [stage][plane][row][k half]: 16 narrow floats per row
   __shared__ u4 Ys[2][NP][TN][2];
 
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const Job J = job_of(B, EXPAND ? PH_EXPAND : PH_MOMENT, xcd_remap(blockIdx.x, gridDim.x));
+  const PlanDev &P = J.P;
+  double *__restrict__ phi = J.io.phi;
   int c = 0;
   if (EXPAND) {
-    while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_exp_begin) ++c;
+    while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_exp_begin) ++c;
   } else {
-    while (c + 1 < P.nclasses && wg >= P.classes[c + 1].wg_mom_begin) ++c;
+    while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_mom_begin) ++c;
   }
   const ClassDev C = P.classes[c];
-  const int local = wg - (EXPAND ? C.wg_exp_begin : C.wg_mom_begin);
+  const int local = J.local - (EXPAND ? C.wg_exp_begin : C.wg_mom_begin);
   const int mt = local % C.m_tiles;
   const int rest = local / C.m_tiles;
   int nt, split = 0;
@@ -243,26 +245,35 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(PlanDev P, double *__restric
         }
       }
     }
+  if (EXPAND) stamp_done(B, J.f);
 }
 
 }  // namespace
 
-hipError_t launch_moment_split(const PlanDev &P, int total_wgs, int kind, hipStream_t s) {
-  if (total_wgs <= 0) return hipSuccess;
+hipError_t launch_moment_split(const BatchDev &B, int wgs, int kind, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
   if (kind == kSplitBf16x3)
-    hipLaunchKernelGGL((k_gemm_split<kSplitBf16x3, false>), dim3(total_wgs), dim3(NTH), 0, s, P, nullptr);
+    hipLaunchKernelGGL((k_gemm_split<kSplitBf16x3, false>), dim3(wgs), dim3(NTH), 0, s, B);
   else
-    hipLaunchKernelGGL((k_gemm_split<kSplitFp16x2, false>), dim3(total_wgs), dim3(NTH), 0, s, P, nullptr);
+    hipLaunchKernelGGL((k_gemm_split<kSplitFp16x2, false>), dim3(wgs), dim3(NTH), 0, s, B);
   return hipGetLastError();
 }
 
-hipError_t launch_expand_split(const PlanDev &P, int total_wgs, int kind, double *phi, hipStream_t s) {
-  if (total_wgs <= 0) return hipSuccess;
+hipError_t launch_expand_split(const BatchDev &B, int wgs, int kind, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
   if (kind == kSplitBf16x3)
-    hipLaunchKernelGGL((k_gemm_split<kSplitBf16x3, true>), dim3(total_wgs), dim3(NTH), 0, s, P, phi);
+    hipLaunchKernelGGL((k_gemm_split<kSplitBf16x3, true>), dim3(wgs), dim3(NTH), 0, s, B);
   else
-    hipLaunchKernelGGL((k_gemm_split<kSplitFp16x2, true>), dim3(total_wgs), dim3(NTH), 0, s, P, phi);
+    hipLaunchKernelGGL((k_gemm_split<kSplitFp16x2, true>), dim3(wgs), dim3(NTH), 0, s, B);
   return hipGetLastError();
+}
+
+hipError_t launch_moment(const BatchDev &B, int precision, int wgs, hipStream_t s) {
+  return precision == 0 ? launch_moment_f64(B, wgs, s) : launch_moment_split(B, wgs, precision, s);
+}
+
+hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s) {
+  return precision == 0 ? launch_expand_f64(B, wgs, s) : launch_expand_split(B, wgs, precision, s);
 }
 
 }  // namespace mpole

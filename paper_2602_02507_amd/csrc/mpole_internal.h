@@ -59,7 +59,29 @@ struct PlanDev {
   double *mono_part; // [nr][mono_stride] FP64 partial monopole moments (split precisions), or null
   double *max_part;  // [nr][mono_stride] partial row maxima of the packed source (FP16 x2)
   int32_t mono_stride;
+  int32_t pack_parts;       // packing workgroups per shell
+  int32_t wg_mom, wg_exp;   // workgroups of the two contraction launches
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
+};
+
+// Phases of one solve; a launch of phase h covers the workgroups
+// [prefix[h][f], prefix[h][f+1]) of every field f of a batch.
+enum Phase { PH_PACK = 0, PH_SPLITROWS, PH_MOMENT, PH_REDUCE, PH_SCAN, PH_COEF, PH_EXPAND, PH_COUNT };
+
+// Per-field device pointers of one solve.
+struct SolveIO {
+  const double *rho;
+  double *phi, *ang, *interior, *exterior;
+};
+
+// What a solve-time kernel gets: one or more fields (plans) and their I/O.
+struct BatchDev {
+  const PlanDev *plans;        // [nf] device copies
+  const SolveIO *io;           // [nf] device array, or null: use io1 (single plan)
+  SolveIO io1;
+  const int32_t *prefix;       // [PH_COUNT][nf+1] workgroup prefix sums
+  int32_t nf;
+  unsigned long long *stamps;  // [nf+1]: per field, wall clock when its potential is done; [nf] batch start; or null
 };
 
 // Split precisions: operands are sums of nplanes narrow floats (hi + mid + lo),
@@ -67,23 +89,25 @@ struct PlanDev {
 enum SplitKind { kSplitBf16x3 = 1, kSplitFp16x2 = 2 };
 
 // ---- launchers (all asynchronous on `s`; return hipSuccess or the launch error)
+// bind time, per plan
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s);
-int pack_parts(const PlanDev &P, const ClassDev *host_classes);   // packing workgroups per shell
 hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g,
                          hipStream_t s);
-hipError_t launch_pack_f64(const PlanDev &P, const ClassDev *host_classes, const double *rho,
-                           hipStream_t s);
-hipError_t launch_moment_f64(const PlanDev &P, int total_wgs, hipStream_t s);
-hipError_t launch_reduce(const PlanDev &P, double *ang_out, hipStream_t s);
-hipError_t launch_scan(const PlanDev &P, double *interior, double *exterior, hipStream_t s);
-hipError_t launch_expand_f64(const PlanDev &P, int total_wgs, double *phi, hipStream_t s);
-// split precisions
 hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, int kind, hipStream_t s);
-hipError_t launch_pack_split(const PlanDev &P, const ClassDev *host_classes, const double *rho, int kind,
-                             hipStream_t s);
-hipError_t launch_split_coef(const PlanDev &P, int kind, hipStream_t s);
-hipError_t launch_moment_split(const PlanDev &P, int total_wgs, int kind, hipStream_t s);
-hipError_t launch_expand_split(const PlanDev &P, int total_wgs, int kind, double *phi, hipStream_t s);
+// solve time, one launch per phase covering every field of B; wgs = total workgroups
+// (prefix[h][nf]); precision = the fields' common precision (0 = FP64)
+hipError_t launch_stamp_reset(const BatchDev &B, hipStream_t s);
+hipError_t launch_pack(const BatchDev &B, int precision, int wgs, hipStream_t s);
+hipError_t launch_split_rows(const BatchDev &B, int wgs, hipStream_t s);   // FP16 x2 only
+hipError_t launch_moment(const BatchDev &B, int precision, int wgs, hipStream_t s);
+hipError_t launch_reduce(const BatchDev &B, int wgs, hipStream_t s);
+hipError_t launch_scan(const BatchDev &B, int wgs, hipStream_t s);
+hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStream_t s);
+hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
+
+hipError_t launch_moment_f64(const BatchDev &B, int wgs, hipStream_t s);
+hipError_t launch_expand_f64(const BatchDev &B, int wgs, hipStream_t s);
+
 
 }  // namespace mpole

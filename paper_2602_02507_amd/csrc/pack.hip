@@ -26,12 +26,17 @@ constexpr int PACK_THREADS = 256, PACK_UNROLL = 4, PACK_SPAN = PACK_THREADS * PA
 static_assert(PACK_SPAN == kPackSpan, "packing span");
 
 template <int MODE>   // 0 = FP64, kSplitBf16x3, kSplitFp16x2
-__global__ __launch_bounds__(PACK_THREADS) void k_pack(PlanDev P, const double *__restrict__ rho) {
+__global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   __shared__ double red[PACK_THREADS / 64];
-  const int i = blockIdx.y;
+  const Job J = job_of(B, PH_PACK, blockIdx.x);
+  const PlanDev &P = J.P;
+  // batch start: the first workgroup of the first launch of the solve
+  if (B.stamps != nullptr && blockIdx.x == 0 && threadIdx.x == 0) B.stamps[B.nf] = wall_clock64();
+  const int bx = J.local % P.pack_parts, i = J.local / P.pack_parts;   // (part, shell)
+  const double *__restrict__ rho = J.io.rho;
   const ClassDev C = P.classes[P.shell_class[i]];
-  const int b0 = blockIdx.x * PACK_SPAN + threadIdx.x;
-  if (blockIdx.x * PACK_SPAN >= C.nblocks) return;   // whole workgroup idle for this class
+  const int b0 = bx * PACK_SPAN + threadIdx.x;
+  if (bx * PACK_SPAN >= C.nblocks) return;   // whole workgroup idle for this class
   const int row = P.shell_row[i];
   const double *__restrict__ src = rho + (size_t)i * P.ncell;
   const double *__restrict__ w = P.weight;
@@ -72,7 +77,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(PlanDev P, const double *
       split_store<kSplitBf16x3>(b < C.nblocks ? s[u] : 0.0, &stage[bl >> 4][0][bl & 15], 16);
     }
     __syncthreads();
-    const int g0 = blockIdx.x * (PACK_SPAN / 16);                // first k slab of the workgroup
+    const int g0 = bx * (PACK_SPAN / 16);                        // first k slab of the workgroup
     const int ngroups = min(PACK_SPAN / 16, C.nblocks_pad / 16 - g0);
     const uint4 *st = reinterpret_cast<const uint4 *>(&stage[0][0][0]);
     for (int v = threadIdx.x; v < ngroups * 6; v += PACK_THREADS) {   // 6 x 16 B per group
@@ -95,16 +100,18 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(PlanDev P, const double *
     mono = block_sum(mono, red);
     if (MODE == kSplitFp16x2) mx = block_max(mx, red);
     if (threadIdx.x == 0) {
-      P.mono_part[(size_t)i * P.mono_stride + blockIdx.x] = mono;
-      if (MODE == kSplitFp16x2) P.max_part[(size_t)i * P.mono_stride + blockIdx.x] = mx;
+      P.mono_part[(size_t)i * P.mono_stride + bx] = mono;
+      if (MODE == kSplitFp16x2) P.max_part[(size_t)i * P.mono_stride + bx] = mx;
     }
   }
 }
 
 // FP16 x2: per shell, the row's power-of-two scale from the partial maxima,
 // then the scaled split planes of the FP64 row.
-__global__ __launch_bounds__(256) void k_split_rows_fp16(PlanDev P) {
-  const int i = blockIdx.x;
+__global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
+  const Job J = job_of(B, PH_SPLITROWS, blockIdx.x);
+  const PlanDev &P = J.P;
+  const int i = J.local;
   const ClassDev C = P.classes[P.shell_class[i]];
   const int row = P.shell_row[i];
   const int nparts = (C.nblocks + PACK_SPAN - 1) / PACK_SPAN;
@@ -120,29 +127,32 @@ __global__ __launch_bounds__(256) void k_split_rows_fp16(PlanDev P) {
 
 }  // namespace
 
-int pack_parts(const PlanDev &P, const ClassDev *host_classes) {
-  int maxb = 0;
-  for (int c = 0; c < P.nclasses; ++c) maxb = std::max(maxb, host_classes[c].nblocks);
-  return (maxb + PACK_SPAN - 1) / PACK_SPAN;
+__global__ void k_stamp_reset(unsigned long long *stamps, int nf) {
+  const int t = threadIdx.x;
+  if (t < nf) stamps[t] = 0ull;
+  if (t == nf) stamps[nf] = ~0ull;
 }
 
-hipError_t launch_pack_f64(const PlanDev &P, const ClassDev *host_classes, const double *rho, hipStream_t s) {
-  const dim3 g(pack_parts(P, host_classes), P.nr);
-  hipLaunchKernelGGL(k_pack<0>, g, dim3(PACK_THREADS), 0, s, P, rho);
+hipError_t launch_stamp_reset(const BatchDev &B, hipStream_t s) {
+  if (B.stamps == nullptr) return hipSuccess;
+  hipLaunchKernelGGL(k_stamp_reset, dim3(1), dim3(((B.nf + 1 + 63) / 64) * 64), 0, s, B.stamps, B.nf);
   return hipGetLastError();
 }
 
-hipError_t launch_pack_split(const PlanDev &P, const ClassDev *host_classes, const double *rho, int kind,
-                             hipStream_t s) {
-  const dim3 g(pack_parts(P, host_classes), P.nr);
-  if (kind == kSplitBf16x3) {
-    hipLaunchKernelGGL(k_pack<kSplitBf16x3>, g, dim3(PACK_THREADS), 0, s, P, rho);
-  } else {
-    hipLaunchKernelGGL(k_pack<kSplitFp16x2>, g, dim3(PACK_THREADS), 0, s, P, rho);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_split_rows_fp16, dim3(P.nr), dim3(256), 0, s, P);
-  }
+hipError_t launch_pack(const BatchDev &B, int precision, int wgs, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
+  if (precision == 0)
+    hipLaunchKernelGGL(k_pack<0>, dim3(wgs), dim3(PACK_THREADS), 0, s, B);
+  else if (precision == kSplitBf16x3)
+    hipLaunchKernelGGL(k_pack<kSplitBf16x3>, dim3(wgs), dim3(PACK_THREADS), 0, s, B);
+  else
+    hipLaunchKernelGGL(k_pack<kSplitFp16x2>, dim3(wgs), dim3(PACK_THREADS), 0, s, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_rows(const BatchDev &B, int wgs, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_rows_fp16, dim3(wgs), dim3(256), 0, s, B);
   return hipGetLastError();
 }
 

@@ -98,7 +98,8 @@ struct mpole_plan_t {
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
-  int nplanes = 0, tile_m = 64, tile_n = 64, kpad = 16;
+  int nplanes = 0, tile_m = 64, tile_n = 64, kpad = 16, moment_target = 0;
+  size_t off_plandev = 0, off_prefix = 0;
   int wg_mom = 0, wg_exp = 0;
   GaussRule rule{};
   // per-phase timing events (host objects), recorded while timing is on
@@ -111,6 +112,7 @@ struct mpole_plan_t {
   char *ws = nullptr;
   PlanDev dev{};
   std::vector<ClassDev> cdev;
+  std::vector<int32_t> prefix;   // [PH_COUNT][2] single-plan phase prefix sums
 };
 
 namespace {
@@ -140,6 +142,8 @@ void choose_splits(mpole_plan_t &p, int target) {
     c.splits = (c.nblocks_pad + c.kchunk - 1) / c.kchunk;
   }
 }
+
+void layout_plan(mpole_plan_t *p, int target);
 
 int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   if (!m) return fail(MPOLE_ERR_INVALID, "mesh is null");
@@ -245,9 +249,18 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     C.n_tiles_mom = (p->namp + p->tile_n - 1) / p->tile_n;
     C.n_tiles_exp = (C.nblocks + p->tile_n - 1) / p->tile_n;
   }
+  p->rule = make_gauss_rule();
   // about one full round of resident workgroups: 4 per CU (f64 kernel), 3 per CU (split kernel)
   int target = p->nplanes ? 768 : 1024;
   if (const char *env = std::getenv("MPOLE_MOMENT_WGS")) target = std::max(1, std::atoi(env));
+  layout_plan(p, target);
+  return MPOLE_OK;
+}
+
+// Split-K choice, workgroup counts and workspace layout for a moment
+// workgroup target (host only; may be redone before bind).
+void layout_plan(mpole_plan_t *p, int target) {
+  p->moment_target = target;
   choose_splits(*p, target);
   int wm = 0, we = 0;
   for (auto &C : p->cls) {
@@ -311,9 +324,10 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     C.off_ppacks = take(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.nblocks_pad);
     C.off_pscale = take(sizeof(double) * std::max<size_t>(nrows, 1));
   }
+  // the single-plan view of the batched kernels: one device plan, phase prefix sums
+  p->off_plandev = take(sizeof(PlanDev));
+  p->off_prefix = take(sizeof(int32_t) * PH_COUNT * 2);
   p->ws_bytes = off;
-  p->rule = make_gauss_rule();
-  return MPOLE_OK;
 }
 
 // Runs one phase launch, bracketed by timing events when timing is on.
@@ -372,7 +386,26 @@ size_t mpole_plan_workspace_bytes(mpole_plan p) { return p ? p->ws_bytes : 0; }
 
 int mpole_plan_nmodes(mpole_plan p) { return p ? p->nam : 0; }
 
-int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+int phase_wgs_host(const mpole_plan_t *p, int h) {
+  switch (h) {
+    case PH_PACK: return p->mono_stride * p->nr;
+    case PH_SPLITROWS: return p->precision == MPOLE_FP16X2 ? p->nr : 0;
+    case PH_MOMENT: return p->wg_mom;
+    case PH_REDUCE: return (p->namp + 255) / 256 * p->nr;
+    case PH_SCAN: return p->namp / 16;
+    case PH_COEF: return p->nplanes ? p->nr : 0;
+    case PH_EXPAND: return p->wg_exp;
+  }
+  return 0;
+}
+
+// Device view of a plan in workspace ws, table construction and the
+// single-plan batch view (device plan copy + prefix sums), all enqueued on s.
+int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
   if (!dev_ws) return fail(MPOLE_ERR_WORKSPACE, "workspace is null");
   if (((uintptr_t)dev_ws & 255) != 0) return fail(MPOLE_ERR_WORKSPACE, "workspace is not 256-byte aligned");
@@ -382,6 +415,9 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   char *ws = (char *)dev_ws;
   PlanDev &D = p->dev;
   D = PlanDev{};
+  D.pack_parts = p->mono_stride;
+  D.wg_mom = p->wg_mom;
+  D.wg_exp = p->wg_exp;
   D.nr = p->nr;
   D.ntheta = p->nt;
   D.nphi = p->np;
@@ -457,6 +493,11 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
     if (e == hipSuccess) e = upload(ws, H.off_mem, H.mem.data(), sizeof(int32_t) * H.mem.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_rect, H.rect.data(), sizeof(int32_t) * H.rect.size(), s);
   }
+  // single-plan batch view: the device plan and its phase prefix sums
+  p->prefix.assign(PH_COUNT * 2, 0);
+  for (int h = 0; h < PH_COUNT; ++h) p->prefix[2 * h + 1] = phase_wgs_host(p, h);
+  if (e == hipSuccess) e = upload(ws, p->off_plandev, &p->dev, sizeof(PlanDev), s);
+  if (e == hipSuccess) e = upload(ws, p->off_prefix, p->prefix.data(), sizeof(int32_t) * p->prefix.size(), s);
   if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, s);
   if (e == hipSuccess && p->nplanes) e = launch_split_tables(D, p->cdev.data(), p->precision, s);
   // unit row scales (BF16 x3 operands are not scaled; FP16 x2 rows overwrite theirs)
@@ -471,34 +512,63 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   return ok();
 }
 
+// The kernel sequence of one solve for a batch view B of fields sharing
+// `precision`; wgs[h] = total workgroups of phase h; phi == false skips the
+// potential (moments only).
+template <class Timer>
+hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, bool phi, hipStream_t s, Timer &&timed) {
+  const int k = precision;
+  hipError_t e = launch_stamp_reset(B, s);
+  if (e == hipSuccess) e = timed(MPOLE_PHASE_PACK, [&] {
+    hipError_t r = launch_pack(B, k, wgs[PH_PACK], s);
+    if (r == hipSuccess) r = launch_split_rows(B, wgs[PH_SPLITROWS], s);
+    return r;
+  });
+  if (e == hipSuccess) e = timed(MPOLE_PHASE_MOMENT, [&] { return launch_moment(B, k, wgs[PH_MOMENT], s); });
+  if (e == hipSuccess) e = timed(MPOLE_PHASE_REDUCE, [&] { return launch_reduce(B, wgs[PH_REDUCE], s); });
+  if (e == hipSuccess) e = timed(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], s); });
+  if (e == hipSuccess && phi && k != 0)
+    e = timed(MPOLE_PHASE_SPLIT, [&] { return launch_split_coef(B, k, wgs[PH_COEF], s); });
+  if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] { return launch_expand(B, k, wgs[PH_EXPAND], s); });
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpole_plan_configure(mpole_plan p, int32_t moment_wgs) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (moment_wgs < 0) return fail(MPOLE_ERR_INVALID, "moment_wgs < 0");
+  if (p->bound) return fail(MPOLE_ERR_INVALID, "configure before binding a workspace");
+  layout_plan(p, moment_wgs > 0 ? moment_wgs : (p->nplanes ? 768 : 1024));
+  return ok();
+}
+
+int mpole_plan_moment_wgs(mpole_plan p) { return p ? p->wg_mom : 0; }
+
+int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  return bind_plan(p, dev_ws, bytes, stream);
+}
+
 int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, double *interior, double *exterior,
                 void *stream) {
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
   if (!p->bound) return fail(MPOLE_ERR_WORKSPACE, "plan has no bound workspace");
   if (!rho) return fail(MPOLE_ERR_INVALID, "rho is null");
   hipStream_t s = (hipStream_t)stream;
-  const PlanDev &D = p->dev;
-  hipError_t e;
-  if (p->nplanes == 0) {
-    e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_f64(D, p->cdev.data(), rho, s); });
-    if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_f64(D, p->wg_mom, s); });
-  } else {
-    const int k = p->precision;
-    e = timed(p, MPOLE_PHASE_PACK, s, [&] { return launch_pack_split(D, p->cdev.data(), rho, k, s); });
-    if (e == hipSuccess) e = timed(p, MPOLE_PHASE_MOMENT, s, [&] { return launch_moment_split(D, p->wg_mom, k, s); });
-  }
-  if (e == hipSuccess) e = timed(p, MPOLE_PHASE_REDUCE, s, [&] { return launch_reduce(D, ang, s); });
-  if (e == hipSuccess) e = timed(p, MPOLE_PHASE_SCAN, s, [&] { return launch_scan(D, interior, exterior, s); });
-  if (e == hipSuccess && phi) {
-    if (p->nplanes == 0) {
-      e = timed(p, MPOLE_PHASE_EXPAND, s, [&] { return launch_expand_f64(D, p->wg_exp, phi, s); });
-    } else {
-      const int k = p->precision;
-      e = timed(p, MPOLE_PHASE_SPLIT, s, [&] { return launch_split_coef(D, k, s); });
-      if (e == hipSuccess)
-        e = timed(p, MPOLE_PHASE_EXPAND, s, [&] { return launch_expand_split(D, p->wg_exp, k, phi, s); });
-    }
-  }
+  BatchDev B{};
+  B.plans = (const PlanDev *)(p->ws + p->off_plandev);
+  B.io = nullptr;
+  B.io1 = SolveIO{rho, phi, ang, interior, exterior};
+  B.prefix = (const int32_t *)(p->ws + p->off_prefix);
+  B.nf = 1;
+  B.stamps = nullptr;
+  int wgs[PH_COUNT];
+  for (int h = 0; h < PH_COUNT; ++h) wgs[h] = p->prefix[2 * h + 1];
+  hipError_t e = run_solve(B, p->precision, wgs, phi != nullptr, s,
+                           [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
   return ok();
 }
@@ -555,6 +625,185 @@ int mpole_plan_work(mpole_plan p, double *moment_flops, double *expand_flops, do
   if (moment_flops) *moment_flops = f;
   if (expand_flops) *expand_flops = f;
   if (min_bytes) *min_bytes = 16.0 * (double)p->nr * p->ncell + tb;
+  return ok();
+}
+
+}  // extern "C"
+
+struct mpole_batch_t {
+  std::vector<mpole_plan_t *> plans;
+  std::vector<size_t> off;      // workspace offset of each field's plan
+  size_t off_plans = 0, off_io = 0, off_prefix = 0, off_stamps = 0, ws_bytes = 0;
+  int precision = 0;
+  std::vector<int32_t> prefix;  // [PH_COUNT][nf+1]
+  std::vector<SolveIO> io;
+  bool bound = false;
+  char *ws = nullptr;
+  double clock_khz = 0.0;
+  ~mpole_batch_t() {
+    for (auto *p : plans) delete p;
+  }
+};
+
+namespace {
+
+// Default per-field moment targets: one round of resident workgroups shared
+// in proportion to each field's moment work.
+void batch_layout(mpole_batch_t *b, const int32_t *targets) {
+  const int nf = (int)b->plans.size();
+  double total = 0.0;
+  std::vector<double> work(nf);
+  for (int f = 0; f < nf; ++f) {
+    const mpole_plan_t *p = b->plans[f];
+    double w = 0.0;
+    for (const auto &C : p->cls) w += (double)C.rows.size() * C.nblocks_pad * p->namp;
+    work[f] = w;
+    total += w;
+  }
+  const int round = b->precision ? 768 : 1024;
+  for (int f = 0; f < nf; ++f) {
+    int t = (targets && targets[f] > 0) ? targets[f] : (int)std::lround(round * work[f] / std::max(total, 1.0));
+    layout_plan(b->plans[f], std::max(t, 1));
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  b->off.assign(nf, 0);
+  for (int f = 0; f < nf; ++f) b->off[f] = take(b->plans[f]->ws_bytes);
+  b->off_plans = take(sizeof(PlanDev) * nf);
+  b->off_io = take(sizeof(SolveIO) * nf);
+  b->off_prefix = take(sizeof(int32_t) * PH_COUNT * (nf + 1));
+  b->off_stamps = take(sizeof(unsigned long long) * (nf + 1));
+  b->ws_bytes = off;
+  b->prefix.assign(PH_COUNT * (nf + 1), 0);
+  for (int h = 0; h < PH_COUNT; ++h)
+    for (int f = 0; f < nf; ++f)
+      b->prefix[h * (nf + 1) + f + 1] = b->prefix[h * (nf + 1) + f] + phase_wgs_host(b->plans[f], h);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *out) {
+  if (!out) return fail(MPOLE_ERR_INVALID, "out is null");
+  if (nfields < 1 || nfields > 4096) return fail(MPOLE_ERR_INVALID, "nfields %d outside [1, 4096]", nfields);
+  if (!meshes) return fail(MPOLE_ERR_INVALID, "meshes is null");
+  try {
+    mpole_batch_t *b = new mpole_batch_t();
+    for (int f = 0; f < nfields; ++f) {
+      if (meshes[f].precision != meshes[0].precision) {
+        delete b;
+        return fail(MPOLE_ERR_INVALID, "field %d: all fields of a batch need the same precision", f);
+      }
+      mpole_plan_t *p = new mpole_plan_t();
+      const int rc = build_plan(&meshes[f], p);
+      if (rc != MPOLE_OK) {
+        delete p;
+        delete b;
+        std::string msg = g_error;
+        return fail(rc, "field %d: %s", f, msg.c_str());
+      }
+      b->plans.push_back(p);
+    }
+    b->precision = meshes[0].precision;
+    batch_layout(b, nullptr);
+    *out = b;
+    return ok();
+  } catch (const std::bad_alloc &) {
+    return fail(MPOLE_ERR_INVALID, "host allocation failed");
+  } catch (...) {
+    return fail(MPOLE_ERR_INVALID, "unexpected host exception");
+  }
+}
+
+int mpole_batch_configure(mpole_batch b, const int32_t *moment_wgs) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (b->bound) return fail(MPOLE_ERR_INVALID, "configure before binding a workspace");
+  batch_layout(b, moment_wgs);
+  return ok();
+}
+
+size_t mpole_batch_workspace_bytes(mpole_batch b) { return b ? b->ws_bytes : 0; }
+
+int mpole_batch_bind(mpole_batch b, void *dev_ws, size_t bytes, const double *const *rho, double *const *phi,
+                     void *stream) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (!dev_ws) return fail(MPOLE_ERR_WORKSPACE, "workspace is null");
+  if (((uintptr_t)dev_ws & 255) != 0) return fail(MPOLE_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < b->ws_bytes)
+    return fail(MPOLE_ERR_WORKSPACE, "workspace has %zu bytes, batch needs %zu", bytes, b->ws_bytes);
+  if (!rho || !phi) return fail(MPOLE_ERR_INVALID, "rho and phi pointer arrays are required");
+  const int nf = (int)b->plans.size();
+  for (int f = 0; f < nf; ++f)
+    if (!rho[f] || !phi[f]) return fail(MPOLE_ERR_INVALID, "field %d: null rho or phi", f);
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)dev_ws;
+  for (int f = 0; f < nf; ++f) {
+    const int rc = bind_plan(b->plans[f], ws + b->off[f], b->plans[f]->ws_bytes, stream);
+    if (rc != MPOLE_OK) {
+      std::string msg = g_error;
+      return fail(rc, "field %d: %s", f, msg.c_str());
+    }
+  }
+  std::vector<PlanDev> devs(nf);
+  b->io.assign(nf, SolveIO{});
+  for (int f = 0; f < nf; ++f) {
+    devs[f] = b->plans[f]->dev;
+    b->io[f].rho = rho[f];
+    b->io[f].phi = phi[f];
+  }
+  hipError_t e = upload(ws, b->off_plans, devs.data(), sizeof(PlanDev) * nf, s);
+  if (e == hipSuccess) e = upload(ws, b->off_io, b->io.data(), sizeof(SolveIO) * nf, s);
+  if (e == hipSuccess) e = upload(ws, b->off_prefix, b->prefix.data(), sizeof(int32_t) * b->prefix.size(), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host arrays above are temporaries
+  int dev = 0, khz = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch bind: %s", hipGetErrorString(e));
+  b->clock_khz = khz;
+  b->ws = ws;
+  b->bound = true;
+  return ok();
+}
+
+int mpole_batch_solve(mpole_batch b, void *stream) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (!b->bound) return fail(MPOLE_ERR_WORKSPACE, "batch has no bound workspace");
+  const int nf = (int)b->plans.size();
+  BatchDev B{};
+  B.plans = (const PlanDev *)(b->ws + b->off_plans);
+  B.io = (const SolveIO *)(b->ws + b->off_io);
+  B.prefix = (const int32_t *)(b->ws + b->off_prefix);
+  B.nf = nf;
+  B.stamps = (unsigned long long *)(b->ws + b->off_stamps);
+  int wgs[PH_COUNT];
+  for (int h = 0; h < PH_COUNT; ++h) wgs[h] = b->prefix[h * (nf + 1) + nf];
+  hipError_t e = run_solve(B, b->precision, wgs, true, (hipStream_t)stream,
+                           [](int, auto &&launch) { return launch(); });
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch solve: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int mpole_batch_field_ms(mpole_batch b, double *ms) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (!ms) return fail(MPOLE_ERR_INVALID, "ms is null");
+  if (!b->bound) return fail(MPOLE_ERR_WORKSPACE, "batch has no bound workspace");
+  const int nf = (int)b->plans.size();
+  std::vector<unsigned long long> st(nf + 1);
+  hipError_t e = hipMemcpy(st.data(), b->ws + b->off_stamps, sizeof(unsigned long long) * (nf + 1),
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "field_ms: %s", hipGetErrorString(e));
+  for (int f = 0; f < nf; ++f)
+    ms[f] = (st[f] >= st[nf] && b->clock_khz > 0) ? (double)(st[f] - st[nf]) / b->clock_khz : -1.0;
+  return ok();
+}
+
+int mpole_batch_destroy(mpole_batch b) {
+  delete b;
   return ok();
 }
 

@@ -17,14 +17,18 @@
 // edges and coefficients.  Chunk-boundary edges are always the scanned totals
 // (never a thread's running sum), so the two chunks meeting at an edge use
 // bitwise the same value.
-#include "mpole_internal.h"
+#include "device_util.h"
 
 namespace mpole {
 namespace {
 
-__global__ __launch_bounds__(256) void k_reduce(PlanDev P, double *__restrict__ ang_out) {
-  const int i = blockIdx.y;
-  const int n = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
+  const Job J = job_of(B, PH_REDUCE, blockIdx.x);
+  const PlanDev &P = J.P;
+  double *__restrict__ ang_out = J.io.ang;
+  const int gx = (P.namp + 255) / 256;
+  const int i = J.local / gx;
+  const int n = (J.local % gx) * 256 + threadIdx.x;
   if (n >= P.namp) return;
   const ClassDev C = P.classes[P.shell_class[i]];
   const int row = P.shell_row[i];
@@ -50,13 +54,19 @@ __global__ __launch_bounds__(256) void k_reduce(PlanDev P, double *__restrict__ 
 constexpr int SCAN_MODES = 16;    // modes per workgroup (one 128-byte row segment)
 constexpr int SCAN_CHUNKS = 64;   // radial chunks per mode (one per lane of a wavefront)
 
-__global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(PlanDev P, double *__restrict__ er, int ld_r,
-                                                                  double *__restrict__ ei, int ld_i) {
+__global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
   __shared__ double tot_r[SCAN_CHUNKS][SCAN_MODES], tot_i[SCAN_CHUNKS][SCAN_MODES];
   __shared__ double base_r[SCAN_CHUNKS + 1][SCAN_MODES], base_i[SCAN_CHUNKS + 1][SCAN_MODES];
+  const Job J = job_of(B, PH_SCAN, blockIdx.x);
+  const PlanDev &P = J.P;
+  // edge moments go to the caller's [nr+1][nAM] buffers, or to the workspace
+  double *__restrict__ er = J.io.interior ? J.io.interior : P.edge_r;
+  double *__restrict__ ei = J.io.exterior ? J.io.exterior : P.edge_i;
+  const int ld_r = J.io.interior ? P.nam : P.namp;
+  const int ld_i = J.io.exterior ? P.nam : P.namp;
   const int t = threadIdx.x;
   const int mode = t % SCAN_MODES, c = t / SCAN_MODES;   // chunk c of mode n
-  const int n = blockIdx.x * SCAN_MODES + mode;
+  const int n = J.local * SCAN_MODES + mode;
   const int nr = P.nr, L1 = P.lmax + 1, namp = P.namp;
   const bool live = n < P.nam;
   int l = 0;
@@ -139,17 +149,15 @@ __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(PlanDev P, do
 
 }  // namespace
 
-hipError_t launch_reduce(const PlanDev &P, double *ang_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((P.namp + 255) / 256, P.nr), dim3(256), 0, s, P, ang_out);
+hipError_t launch_reduce(const BatchDev &B, int wgs, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(wgs), dim3(256), 0, s, B);
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const PlanDev &P, double *interior, double *exterior, hipStream_t s) {
-  double *er = interior ? interior : P.edge_r;
-  double *ei = exterior ? exterior : P.edge_i;
-  const int ldr = interior ? P.nam : P.namp;
-  const int ldi = exterior ? P.nam : P.namp;
-  hipLaunchKernelGGL(k_scan, dim3(P.namp / SCAN_MODES), dim3(SCAN_MODES * SCAN_CHUNKS), 0, s, P, er, ldr, ei, ldi);
+hipError_t launch_scan(const BatchDev &B, int wgs, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan, dim3(wgs), dim3(SCAN_MODES * SCAN_CHUNKS), 0, s, B);
   return hipGetLastError();
 }
 

@@ -23,9 +23,11 @@ __global__ __launch_bounds__(256) void k_split_tables(ClassDev C, int namp) {
 
 // One workgroup per shell: scale and split the expansion coefficients.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_split_coef(PlanDev P) {
+__global__ __launch_bounds__(256) void k_split_coef(BatchDev B) {
   __shared__ double red[256 / 64];
-  const int i = blockIdx.x;
+  const Job J = job_of(B, PH_COEF, blockIdx.x);
+  const PlanDev &P = J.P;
+  const int i = J.local;
   const double *__restrict__ c = P.coef + (size_t)i * P.namp;
   double mx = 0.0;
   for (int n = threadIdx.x + 1; n < P.nam; n += 256) mx = fmax(mx, fabs(c[n]));
@@ -54,11 +56,12 @@ hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, i
   return hipSuccess;
 }
 
-hipError_t launch_split_coef(const PlanDev &P, int kind, hipStream_t s) {
-  if (kind == kSplitBf16x3)
-    hipLaunchKernelGGL(k_split_coef<kSplitBf16x3>, dim3(P.nr), dim3(256), 0, s, P);
+hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStream_t s) {
+  if (wgs <= 0 || precision == 0) return hipSuccess;
+  if (precision == kSplitBf16x3)
+    hipLaunchKernelGGL(k_split_coef<kSplitBf16x3>, dim3(wgs), dim3(256), 0, s, B);
   else
-    hipLaunchKernelGGL(k_split_coef<kSplitFp16x2>, dim3(P.nr), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_split_coef<kSplitFp16x2>, dim3(wgs), dim3(256), 0, s, B);
   return hipGetLastError();
 }
 

@@ -22,7 +22,10 @@ STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE
 # every entry point include/mpole.h declares
 EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_plan_workspace_bytes",
            "mpole_plan_nmodes", "mpole_plan_bind", "mpole_solve", "mpole_plan_copy_table",
-           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_plan_destroy")
+           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_plan_configure",
+           "mpole_plan_moment_wgs", "mpole_plan_destroy",
+           "mpole_batch_create", "mpole_batch_configure", "mpole_batch_workspace_bytes", "mpole_batch_bind",
+           "mpole_batch_solve", "mpole_batch_field_ms", "mpole_batch_destroy")
 PHASES = ("pack", "moment", "reduce", "scan", "split", "expand")
 
 
@@ -72,7 +75,17 @@ def lib():
         L.mpole_plan_phase_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         dptr = ctypes.POINTER(ctypes.c_double)
         L.mpole_plan_work.argtypes = [vp, dptr, dptr, dptr]
+        L.mpole_plan_configure.argtypes = [vp, ctypes.c_int32]
+        L.mpole_plan_moment_wgs.argtypes = [vp]
         L.mpole_plan_destroy.argtypes = [vp]
+        L.mpole_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(MeshC), ctypes.POINTER(vp)]
+        L.mpole_batch_configure.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.mpole_batch_workspace_bytes.argtypes = [vp]
+        L.mpole_batch_workspace_bytes.restype = sz
+        L.mpole_batch_bind.argtypes = [vp, vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.mpole_batch_solve.argtypes = [vp, vp]
+        L.mpole_batch_field_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.mpole_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -90,35 +103,44 @@ def _dev_ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def make_mesh(r_edges, theta_edges, phi_edges, lmax, shell_class=None, class_block=None, G=1.0,
+              precision="fp64"):
+    """(MeshC, arrays to keep alive) for the C mesh descriptor."""
+    keep = [np.ascontiguousarray(r_edges, np.float64), np.ascontiguousarray(theta_edges, np.float64),
+            np.ascontiguousarray(phi_edges, np.float64)]
+    r, th, ph = keep
+    m = MeshC()
+    m.nr, m.ntheta, m.nphi, m.lmax = r.size - 1, th.size - 1, ph.size - 1, int(lmax)
+    m.r_edges, m.theta_edges, m.phi_edges = _ptr(r, ctypes.c_double), _ptr(th, ctypes.c_double), _ptr(ph, ctypes.c_double)
+    if class_block is not None:
+        cb = np.ascontiguousarray(class_block, np.int32).reshape(-1, m.ntheta * m.nphi)
+        sc = np.ascontiguousarray(shell_class, np.int32)
+        keep += [cb, sc]
+        m.nclasses = cb.shape[0]
+        m.shell_class, m.class_block = _ptr(sc, ctypes.c_int32), _ptr(cb, ctypes.c_int32)
+    else:
+        m.nclasses = 0
+    m.G = float(G)
+    m.precision = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return m, keep
+
+
 class HostPlan:
     """A validated plan without device state (mpole_plan_create only)."""
 
     def __init__(self, r_edges, theta_edges, phi_edges, lmax, shell_class=None, class_block=None,
-                 G=1.0, precision="fp64"):
-        self._keep = [np.ascontiguousarray(r_edges, np.float64), np.ascontiguousarray(theta_edges, np.float64),
-                      np.ascontiguousarray(phi_edges, np.float64)]
-        r, th, ph = self._keep
-        self.nr, self.ntheta, self.nphi = r.size - 1, th.size - 1, ph.size - 1
-        self.lmax = int(lmax)
-        prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        m = MeshC()
-        m.nr, m.ntheta, m.nphi, m.lmax = self.nr, self.ntheta, self.nphi, self.lmax
-        m.r_edges, m.theta_edges, m.phi_edges = _ptr(r, ctypes.c_double), _ptr(th, ctypes.c_double), _ptr(ph, ctypes.c_double)
-        if class_block is not None:
-            cb = np.ascontiguousarray(class_block, np.int32).reshape(-1, self.ntheta * self.nphi)
-            sc = np.ascontiguousarray(shell_class, np.int32)
-            self._keep += [cb, sc]
-            m.nclasses = cb.shape[0]
-            m.shell_class, m.class_block = _ptr(sc, ctypes.c_int32), _ptr(cb, ctypes.c_int32)
-        else:
-            m.nclasses = 0
-        m.G, m.precision = float(G), prec
+                 G=1.0, precision="fp64", moment_wgs=0):
+        m, self._keep = make_mesh(r_edges, theta_edges, phi_edges, lmax, shell_class, class_block, G, precision)
+        self.nr, self.ntheta, self.nphi, self.lmax = m.nr, m.ntheta, m.nphi, m.lmax
         self._mesh = m
         h = ctypes.c_void_p()
         _check(lib().mpole_plan_create(ctypes.byref(m), ctypes.byref(h)))
         self.handle = h
         self.nmodes = lib().mpole_plan_nmodes(h)
+        if moment_wgs:
+            _check(lib().mpole_plan_configure(h, int(moment_wgs)))
         self.workspace_bytes = lib().mpole_plan_workspace_bytes(h)
+        self.moment_wgs = lib().mpole_plan_moment_wgs(h)
 
     @classmethod
     def from_mesh(cls, mesh, precision="fp64"):
@@ -168,9 +190,9 @@ class Plan(HostPlan):
                                      ctypes.c_void_p(stream)))
 
     @classmethod
-    def from_mesh(cls, mesh, precision="fp64", device="cuda"):
+    def from_mesh(cls, mesh, precision="fp64", device="cuda", moment_wgs=0):
         return cls(mesh.r_edges, mesh.theta_edges, mesh.phi_edges, mesh.lmax, mesh.shell_class,
-                   mesh.class_block, mesh.G, precision=precision, device=device)
+                   mesh.class_block, mesh.G, precision=precision, device=device, moment_wgs=moment_wgs)
 
     @property
     def shape(self):
@@ -219,3 +241,64 @@ class Plan(HostPlan):
         _check(lib().mpole_plan_copy_table(self.handle, cls, out.ctypes.data_as(ctypes.c_void_p),
                                            ctypes.byref(n), ctypes.c_void_p(s)))
         return out
+
+
+class Batch:
+    """Many fields (uneven meshes, same precision) solved by one launch per phase.
+
+    `meshes` are workloads.Mesh-like objects; rho/phi are per-field float64
+    device tensors (phi allocated here when not given).  `solve()` enqueues one
+    batch solve on the current stream (graph-capturable); `field_ms()` gives
+    each field's completion time within the last solve after a sync."""
+
+    def __init__(self, meshes, precision="bf16x3", rho=None, device="cuda", moment_wgs=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("mpole needs a ROCm GPU; none is visible to torch")
+        self.n = len(meshes)
+        descs = (MeshC * self.n)()
+        self._keep = []
+        for f, mesh in enumerate(meshes):
+            m, keep = make_mesh(mesh.r_edges, mesh.theta_edges, mesh.phi_edges, mesh.lmax, mesh.shell_class,
+                                mesh.class_block, mesh.G, precision)
+            descs[f] = m
+            self._keep.append(keep)
+        h = ctypes.c_void_p()
+        _check(lib().mpole_batch_create(self.n, descs, ctypes.byref(h)))
+        self.handle = h
+        if moment_wgs is not None:
+            arr = (ctypes.c_int32 * self.n)(*[int(x) for x in moment_wgs])
+            _check(lib().mpole_batch_configure(h, arr))
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        self.shapes = [(m.nr, m.ntheta, m.nphi) for m in meshes]
+        self.rho = rho if rho is not None else [torch.empty(s, dtype=torch.float64, device=dev) for s in self.shapes]
+        self.phi = [torch.empty(s, dtype=torch.float64, device=dev) for s in self.shapes]
+        for t, s in zip(self.rho, self.shapes):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != s:
+                raise ValueError("rho tensors must be contiguous float64 of the mesh shapes")
+        self.workspace_bytes = lib().mpole_batch_workspace_bytes(h)
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        ws = (self.workspace.data_ptr() + 255) & ~255
+        rp = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in self.rho])
+        pp = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in self.phi])
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(lib().mpole_batch_bind(h, ctypes.c_void_p(ws), self.workspace_bytes, rp, pp, ctypes.c_void_p(stream)))
+
+    def solve(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_batch_solve(self.handle, ctypes.c_void_p(s)))
+
+    def field_ms(self):
+        out = (ctypes.c_double * self.n)()
+        _check(lib().mpole_batch_field_ms(self.handle, out))
+        return list(out)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mpole_batch_destroy(h)
+            self.handle = None

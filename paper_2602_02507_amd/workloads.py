@@ -240,6 +240,31 @@ def random_density(seed, shape, positive=True):
     return np.ascontiguousarray(x if positive else x - 0.5)
 
 
+def batch_meshes(nfields=64, seed0=4000, nr=(128, 1024), ntheta=(32, 256), lmax=(8, 32), merged=True):
+    """Uneven meshes of a batched solve: per field f (seed seed0 + f) draws, in
+    this order, nr ~ U{nr}, ntheta ~ U over multiples of 4 in ntheta,
+    nphi = 2 ntheta, lmax ~ U{lmax}; log-spaced shells on [1e-3, 1]; the
+    production coarsening rule (shells < 32 and 8 polar rows, scaled down
+    for small meshes)."""
+    meshes = []
+    for f in range(nfields):
+        rng = np.random.default_rng(seed0 + f)
+        n_r = int(rng.integers(nr[0], nr[1] + 1))
+        n_t = 4 * int(rng.integers(ntheta[0] // 4, ntheta[1] // 4 + 1))
+        L = int(rng.integers(lmax[0], lmax[1] + 1))
+        m = Mesh(log_edges(1e-3, 1.0, n_r), uniform_edges(0.0, np.pi, n_t), uniform_edges(0.0, 2 * np.pi, 2 * n_t),
+                 L, name="field%d" % f)
+        if merged:
+            m.shell_class, m.class_block = production_merge(n_r, n_t, 2 * n_t, inner_shells=min(32, n_r),
+                                                            polar_rows=min(8, n_t // 4))
+        meshes.append(m)
+    return meshes
+
+
+def batch_densities(meshes, seed0=4000):
+    return [production_density(m, seed=seed0 + f) for f, m in enumerate(meshes)]
+
+
 def workload(name):
     """(mesh, rho) of a named workload."""
     if name == "spheroid":
