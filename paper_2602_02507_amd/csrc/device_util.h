@@ -12,6 +12,29 @@ __device__ inline int xcd_remap(int w, int g) {
   return x * q + min(x, r) + (w >> 3);
 }
 
+// Plan descriptors (plans, classes, prefix sums, shell maps) are written
+// before a solve and only read by its kernels.  Reading them through the
+// constant address space lets workgroup-uniform loads go to scalar
+// registers instead of occupying vector registers for the whole kernel.
+template <class T>
+__device__ inline T ld_const(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor size");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  const cword *q = (const cword *)p;
+  T v;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+  return v;
+}
+
+// Device buffers reached through a descriptor are plain global memory; saying
+// so lets the compiler use global (not flat) loads and stores for them.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T *gmem(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 // Field of workgroup wg in a launch of phase h (binary search of the prefix
 // sums; the searched values are uniform across the workgroup).
 __device__ inline int field_of(const BatchDev &B, int h, int wg) {
@@ -19,12 +42,12 @@ __device__ inline int field_of(const BatchDev &B, int h, int wg) {
   int lo = 0, hi = B.nf - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (pre[mid] <= wg) lo = mid; else hi = mid - 1;
+    if (ld_const(pre + mid) <= wg) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
-__device__ inline SolveIO io_of(const BatchDev &B, int f) { return B.io ? B.io[f] : B.io1; }
+__device__ inline SolveIO io_of(const BatchDev &B, int f) { return B.io ? ld_const(B.io + f) : B.io1; }
 
 // A solve-time workgroup's field, its plan and its workgroup id within the field.
 struct Job {
@@ -35,9 +58,9 @@ struct Job {
 __device__ inline Job job_of(const BatchDev &B, int h, int wg) {
   Job j;
   j.f = field_of(B, h, wg);
-  j.P = B.plans[j.f];
+  j.P = ld_const(B.plans + j.f);
   j.io = io_of(B, j.f);
-  j.local = wg - B.prefix[h * (B.nf + 1) + j.f];
+  j.local = wg - ld_const(B.prefix + h * (B.nf + 1) + j.f);
   return j;
 }
 
@@ -51,18 +74,20 @@ __device__ inline void stamp_done(const BatchDev &B, int f) {
 
 // dOmega_b S_b of block b of one shell: the sum over the block's member
 // cells, in ascending cell order, of 4 pi G dOmega_q rho_q.
-__device__ inline double block_source(const ClassDev &C, const double *__restrict__ w,
-                                      const double *__restrict__ src, int nphi, int b) {
+__device__ inline double block_source(const ClassDev &C, const double *w_, const double *src_, int nphi, int b) {
+  const auto w = gmem(w_), src = gmem(src_);
   double s = 0.0;
   if (C.rect != nullptr) {
-    const int4 r = C.rect[b];
-    for (int j = r.x; j < r.x + r.z; ++j) {
+    const auto rect = gmem(reinterpret_cast<const int *>(C.rect));
+    const int j0 = rect[4 * b], k0 = rect[4 * b + 1], nj = rect[4 * b + 2], nk = rect[4 * b + 3];
+    for (int j = j0; j < j0 + nj; ++j) {
       const int q0 = j * nphi;
-      for (int k = r.y; k < r.y + r.w; ++k) s += w[q0 + k] * src[q0 + k];
+      for (int k = k0; k < k0 + nk; ++k) s += w[q0 + k] * src[q0 + k];
     }
   } else {
-    for (int e = C.moff[b]; e < C.moff[b + 1]; ++e) {
-      const int q = C.mem[e];
+    const auto moff = gmem(C.moff), mem = gmem(C.mem);
+    for (int e = moff[b]; e < moff[b + 1]; ++e) {
+      const int q = mem[e];
       s += w[q] * src[q];
     }
   }

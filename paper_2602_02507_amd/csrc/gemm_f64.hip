@@ -52,8 +52,9 @@ __device__ inline void mfma_stage(const double (*As)[LDS_LD], const double (*Bs)
 // and zero them when storing to LDS), so the compiler need not wait for it
 // before the store.
 __device__ inline void load4(const double *p, double v[4]) {
-  const double2 x = *reinterpret_cast<const double2 *>(p);
-  const double2 y = *reinterpret_cast<const double2 *>(p + 2);
+  typedef double g2 __attribute__((ext_vector_type(2)));
+  const auto q = gmem(reinterpret_cast<const g2 *>(p));
+  const g2 x = q[0], y = q[1];
   v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
 }
 
@@ -63,8 +64,8 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
   const Job J = job_of(B, PH_MOMENT, xcd_remap(blockIdx.x, gridDim.x));
   const PlanDev &P = J.P;
   int c = 0;
-  while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_mom_begin) ++c;
-  const ClassDev C = P.classes[c];
+  while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_mom_begin)) ++c;
+  const ClassDev C = ld_const(P.classes + c);
   const int local = J.local - C.wg_mom_begin;
   const int mt = local % C.m_tiles;
   const int rest = local / C.m_tiles;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
     __syncthreads();
   }
 
-  double *__restrict__ out = C.partial + (size_t)split * nrows * namp;
+  const auto out = gmem(C.partial) + (size_t)split * nrows * namp;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -142,8 +143,8 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
   const PlanDev &P = J.P;
   double *__restrict__ phi = J.io.phi;
   int c = 0;
-  while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_exp_begin) ++c;
-  const ClassDev C = P.classes[c];
+  while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_exp_begin)) ++c;
+  const ClassDev C = ld_const(P.classes + c);
   const int local = J.local - C.wg_exp_begin;
   const int mt = local % C.m_tiles;
   const int nt = local / C.m_tiles;
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
   // both operands are rows with the mode index contiguous: 64 rows x 16 modes
   const int lr = tid >> 2, lk = (tid & 3) * 4;
   const bool a_ok = (m0 + lr) < nrows;
-  const int shell_a = a_ok ? C.rows[m0 + lr] : 0;
+  const int shell_a = a_ok ? gmem(C.rows)[m0 + lr] : 0;
   const bool b_ok = (n0 + lr) < C.nblocks_pad;
   const double *arow = coef + (size_t)shell_a * namp;
   const double *brow = T + (size_t)(b_ok ? n0 + lr : 0) * namp;
@@ -202,19 +203,21 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
     for (int r = 0; r < 4; ++r) {
       const int row = m0 + wm * 32 + t * 16 + 4 * r + (lane >> 4);
       if (row >= nrows) continue;
-      double *__restrict__ dst = phi + (size_t)C.rows[row] * P.ncell;
+      const auto dst = gmem(phi) + (size_t)gmem(C.rows)[row] * P.ncell;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int b = n0 + wn * 32 + u * 16 + (lane & 15);
         if (b >= C.nblocks) continue;
         const double v = acc[t][u][r];
         if (C.rect != nullptr) {
-          const int4 q = C.rect[b];
-          for (int j = q.x; j < q.x + q.z; ++j)
-            for (int k = q.y; k < q.y + q.w; ++k) dst[j * P.nphi + k] = v;
+          const auto rect = gmem(reinterpret_cast<const int *>(C.rect));   // (j0, k0, nj, nk) per block
+          const int j0 = rect[4 * b], k0 = rect[4 * b + 1], nj = rect[4 * b + 2], nk = rect[4 * b + 3];
+          for (int j = j0; j < j0 + nj; ++j)
+            for (int k = k0; k < k0 + nk; ++k) dst[j * P.nphi + k] = v;
         } else {
-          const int e1 = C.moff[b + 1];
-          for (int e = C.moff[b]; e < e1; ++e) dst[C.mem[e]] = v;
+          const auto moff = gmem(C.moff), mem = gmem(C.mem);
+          const int e1 = moff[b + 1];
+          for (int e = moff[b]; e < e1; ++e) dst[mem[e]] = v;
         }
       }
     }

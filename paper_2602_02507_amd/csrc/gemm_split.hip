@@ -77,11 +77,11 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   double *__restrict__ phi = J.io.phi;
   int c = 0;
   if (EXPAND) {
-    while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_exp_begin) ++c;
+    while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_exp_begin)) ++c;
   } else {
-    while (c + 1 < P.nclasses && J.local >= P.classes[c + 1].wg_mom_begin) ++c;
+    while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_mom_begin)) ++c;
   }
-  const ClassDev C = P.classes[c];
+  const ClassDev C = ld_const(P.classes + c);
   const int local = J.local - (EXPAND ? C.wg_exp_begin : C.wg_mom_begin);
   const int mt = local % C.m_tiles;
   const int rest = local / C.m_tiles;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
     l_h[u] = ch & 1;
     x_ok[u] = (m0 + l_row[u]) < M;
     y_ok[u] = (n0 + l_row[u]) < yrow_max;
-    const int xr = EXPAND ? (x_ok[u] ? C.rows[m0 + l_row[u]] : 0) : (x_ok[u] ? m0 + l_row[u] : 0);
+    const int xr = EXPAND ? (x_ok[u] ? gmem(C.rows)[m0 + l_row[u]] : 0) : (x_ok[u] ? m0 + l_row[u] : 0);
     const int yr = y_ok[u] ? n0 + l_row[u] : 0;
     x_off[u] = (size_t)xr * (16 * NP) + 8 * ch;
     y_off[u] = (size_t)yr * (16 * NP) + 8 * ch;
@@ -210,6 +210,13 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   if (kt < nk) compute(0);   // odd stage count: the last stage sits in LDS 0
 
   // epilogue: undo the row scale in FP64
+  const auto rows = gmem(C.rows);
+  const auto rect = gmem(reinterpret_cast<const int *>(C.rect));   // (j0, k0, nj, nk) per block
+  const auto moff = gmem(C.moff), mem = gmem(C.mem);
+  const auto tcol0 = gmem(C.tcol0);
+  const auto cscale = gmem(P.cscale), coef = gmem(P.coef);
+  const auto pscale = gmem(C.pscale);
+  const auto part = gmem(reinterpret_cast<float *>(C.partial));
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -217,27 +224,27 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
       const int row = m0 + wm * 64 + a * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
       if (row >= M) continue;
       if (EXPAND) {
-        const int shell = C.rows[row];
-        const double sc = P.cscale[shell];
-        const double c0 = P.coef[(size_t)shell * P.namp];   // l = 0 coefficient, FP64
-        double *__restrict__ dst = phi + (size_t)shell * P.ncell;
+        const int shell = rows[row];
+        const double sc = cscale[shell];
+        const double c0 = coef[(size_t)shell * P.namp];   // l = 0 coefficient, FP64
+        const auto dst = gmem(phi + (size_t)shell * P.ncell);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const int blk = n0 + wn * 64 + b * 32 + (lane & 31);
           if (blk >= N) continue;
-          const double v = c0 * C.tcol0[blk] + sc * (double)acc[a][b][r];
+          const double v = c0 * tcol0[blk] + sc * (double)acc[a][b][r];
           if (C.rect != nullptr) {
-            const int4 q = C.rect[blk];
-            for (int j = q.x; j < q.x + q.z; ++j)
-              for (int k = q.y; k < q.y + q.w; ++k) dst[j * P.nphi + k] = v;
+            const int j0 = rect[4 * blk], k0 = rect[4 * blk + 1], nj = rect[4 * blk + 2], nk = rect[4 * blk + 3];
+            for (int j = j0; j < j0 + nj; ++j)
+              for (int k = k0; k < k0 + nk; ++k) dst[j * P.nphi + k] = v;
           } else {
-            for (int e = C.moff[blk]; e < C.moff[blk + 1]; ++e) dst[C.mem[e]] = v;
+            for (int e = moff[blk]; e < moff[blk + 1]; ++e) dst[mem[e]] = v;
           }
         }
       } else {
         // FP32 partial sums (the accumulator type; the row scale is a power of two)
-        const float sc = (float)C.pscale[row];
-        float *__restrict__ out = reinterpret_cast<float *>(C.partial) + ((size_t)split * M + row) * P.namp;
+        const float sc = (float)pscale[row];
+        const auto out = part + ((size_t)split * M + row) * P.namp;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const int col = n0 + wn * 64 + b * 32 + (lane & 31);

@@ -34,24 +34,27 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   if (B.stamps != nullptr && blockIdx.x == 0 && threadIdx.x == 0) B.stamps[B.nf] = wall_clock64();
   const int bx = J.local % P.pack_parts, i = J.local / P.pack_parts;   // (part, shell)
   const double *__restrict__ rho = J.io.rho;
-  const ClassDev C = P.classes[P.shell_class[i]];
+  const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   const int b0 = bx * PACK_SPAN + threadIdx.x;
   if (bx * PACK_SPAN >= C.nblocks) return;   // whole workgroup idle for this class
-  const int row = P.shell_row[i];
+  const int row = ld_const(P.shell_row + i);
   const double *__restrict__ src = rho + (size_t)i * P.ncell;
   const double *__restrict__ w = P.weight;
+  const auto srcg = gmem(src), wg = gmem(w);
   double s[PACK_UNROLL];
   if (C.rect != nullptr) {
-    int4 r[PACK_UNROLL];
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const auto rect = gmem(reinterpret_cast<const i4 *>(C.rect));   // (j0, k0, nj, nk) per block
+    i4 r[PACK_UNROLL];
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
-      r[u] = (b < C.nblocks) ? C.rect[b] : make_int4(0, 0, 0, 0);
+      r[u] = (b < C.nblocks) ? rect[b] : i4{0, 0, 0, 0};
     }
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int q = r[u].x * P.nphi + r[u].y;
-      s[u] = (r[u].z == 1 && r[u].w == 1) ? w[q] * src[q] : 0.0;
+      s[u] = (r[u].z == 1 && r[u].w == 1) ? wg[q] * srcg[q] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
@@ -79,10 +82,11 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     __syncthreads();
     const int g0 = bx * (PACK_SPAN / 16);                        // first k slab of the workgroup
     const int ngroups = min(PACK_SPAN / 16, C.nblocks_pad / 16 - g0);
-    const uint4 *st = reinterpret_cast<const uint4 *>(&stage[0][0][0]);
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 *st = reinterpret_cast<const u4 *>(&stage[0][0][0]);
     for (int v = threadIdx.x; v < ngroups * 6; v += PACK_THREADS) {   // 6 x 16 B per group
       const int g = v / 6, part = v % 6;
-      uint4 *dst = reinterpret_cast<uint4 *>(C.ppacks + ((size_t)(g0 + g) * C.nrows + row) * 48);
+      const auto dst = gmem(reinterpret_cast<u4 *>(C.ppacks + ((size_t)(g0 + g) * C.nrows + row) * 48));
       dst[part] = st[g * 6 + part];
     }
   }
@@ -90,9 +94,9 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   for (int u = 0; u < PACK_UNROLL; ++u) {
     const int b = b0 + u * PACK_THREADS;
     if (b >= C.nblocks) continue;
-    if (MODE != kSplitBf16x3) C.pack[(size_t)row * C.nblocks_pad + b] = s[u];
+    if (MODE != kSplitBf16x3) gmem(C.pack)[(size_t)row * C.nblocks_pad + b] = s[u];
     if (MODE != 0) {
-      mono += s[u] * C.tcol0[b];
+      mono += s[u] * gmem(C.tcol0)[b];
       mx = fmax(mx, fabs(s[u]));
     }
   }
@@ -112,8 +116,8 @@ __global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
   const Job J = job_of(B, PH_SPLITROWS, blockIdx.x);
   const PlanDev &P = J.P;
   const int i = J.local;
-  const ClassDev C = P.classes[P.shell_class[i]];
-  const int row = P.shell_row[i];
+  const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
+  const int row = ld_const(P.shell_row + i);
   const int nparts = (C.nblocks + PACK_SPAN - 1) / PACK_SPAN;
   double mx = 0.0;
   for (int q = 0; q < nparts; ++q) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);

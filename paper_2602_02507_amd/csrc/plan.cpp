@@ -130,6 +130,8 @@ int check_edges(const char *name, const double *e, int n, double lo, double hi) 
 // Split-K choice for the moment contraction: spread about `target` workgroups
 // over the classes in proportion to their work, at least one K step (kpad)
 // per split.
+constexpr int kMaxSplitChunk = 2048;
+
 void choose_splits(mpole_plan_t &p, int target) {
   double total = 0.0;
   for (auto &c : p.cls) total += (double)c.rows.size() * c.nblocks_pad;
@@ -137,6 +139,10 @@ void choose_splits(mpole_plan_t &p, int target) {
     const int tiles = c.m_tiles * c.n_tiles_mom;
     const double share = total > 0 ? target * (double)c.rows.size() * c.nblocks_pad / total : 1.0;
     int s = (int)std::lround(share / std::max(tiles, 1));
+    // FP32-accumulated contractions: no split longer than kMaxSplitChunk
+    // blocks, so the rounding of one accumulator chain stays bounded; the
+    // partials are summed in FP64
+    if (p.precision != MPOLE_FP64) s = std::max(s, (c.nblocks_pad + kMaxSplitChunk - 1) / kMaxSplitChunk);
     s = std::max(1, std::min(s, c.nblocks_pad / p.kpad));
     c.kchunk = round_up((c.nblocks_pad + s - 1) / s, p.kpad);
     c.splits = (c.nblocks_pad + c.kchunk - 1) / c.kchunk;

@@ -25,29 +25,29 @@ namespace {
 __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
   const Job J = job_of(B, PH_REDUCE, blockIdx.x);
   const PlanDev &P = J.P;
-  double *__restrict__ ang_out = J.io.ang;
+  const auto ang_out = gmem(J.io.ang);
   const int gx = (P.namp + 255) / 256;
   const int i = J.local / gx;
   const int n = (J.local % gx) * 256 + threadIdx.x;
   if (n >= P.namp) return;
-  const ClassDev C = P.classes[P.shell_class[i]];
-  const int row = P.shell_row[i];
+  const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
+  const int row = ld_const(P.shell_row + i);
   const size_t off = (size_t)row * P.namp + n;
   const size_t stride = (size_t)C.nrows * P.namp;
   double s = 0.0;
   if (P.nplanes == 0) {
-    const double *__restrict__ src = C.partial + off;   // FP64 partials
+    const auto src = gmem(C.partial) + off;   // FP64 partials
     for (int q = 0; q < C.splits; ++q) s += src[q * stride];
   } else if (n == 0) {
     // split precisions: the monopole moment, summed in FP64 by the packing
     // workgroups of this shell, in workgroup order
     const int nparts = (C.nblocks + kPackSpan - 1) / kPackSpan;
-    for (int q = 0; q < nparts; ++q) s += P.mono_part[(size_t)i * P.mono_stride + q];
+    for (int q = 0; q < nparts; ++q) s += gmem(P.mono_part)[(size_t)i * P.mono_stride + q];
   } else {
-    const float *__restrict__ src = reinterpret_cast<const float *>(C.partial) + off;   // FP32 partials
+    const auto src = gmem(reinterpret_cast<const float *>(C.partial)) + off;   // FP32 partials
     for (int q = 0; q < C.splits; ++q) s += (double)src[q * stride];
   }
-  P.ang[(size_t)i * P.namp + n] = s;
+  gmem(P.ang)[(size_t)i * P.namp + n] = s;
   if (ang_out != nullptr && n < P.nam) ang_out[(size_t)i * P.nam + n] = s;
 }
 
@@ -60,8 +60,10 @@ __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
   const Job J = job_of(B, PH_SCAN, blockIdx.x);
   const PlanDev &P = J.P;
   // edge moments go to the caller's [nr+1][nAM] buffers, or to the workspace
-  double *__restrict__ er = J.io.interior ? J.io.interior : P.edge_r;
-  double *__restrict__ ei = J.io.exterior ? J.io.exterior : P.edge_i;
+  const auto er = gmem(J.io.interior ? J.io.interior : P.edge_r);
+  const auto ei = gmem(J.io.exterior ? J.io.exterior : P.edge_i);
+  const auto coef = gmem(P.coef);
+  const auto rr = gmem(P.rr), ri = gmem(P.ri);
   const int ld_r = J.io.interior ? P.nam : P.namp;
   const int ld_i = J.io.exterior ? P.nam : P.namp;
   const int t = threadIdx.x;
@@ -77,9 +79,8 @@ __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
   }
   const int cs = (nr + SCAN_CHUNKS - 1) / SCAN_CHUNKS;
   const int i0 = min(nr, c * cs), i1 = min(nr, i0 + cs);
-  const double *__restrict__ A = P.ang;
-  const double *__restrict__ jr = P.jr;
-  const double *__restrict__ ji = P.ji;
+  const auto A = gmem(P.ang);
+  const auto jr = gmem(P.jr), ji = gmem(P.ji);
 
   // pass 1: chunk totals of the regular and irregular increments
   double sr = 0.0, si = 0.0;
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
   __syncthreads();
 
   if (!live) {
-    for (int i = i0; i < i1; ++i) P.coef[(size_t)i * namp + n] = 0.0;
+    for (int i = i0; i < i1; ++i) coef[(size_t)i * namp + n] = 0.0;
     return;
   }
   // pass 2a: outward edges i0 .. i1-1; chunk boundaries come from base_r only
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
     ei[(size_t)i * ld_i + n] = mi;
     const double mr_lo = er[(size_t)i * ld_r + n];
     const double mic = 0.5 * (mi + mi_hi), mrc = 0.5 * (mr_lo + mr_hi);
-    P.coef[(size_t)i * namp + n] = f * (P.rr[i * L1 + l] * mic + P.ri[i * L1 + l] * mrc);
+    coef[(size_t)i * namp + n] = f * (rr[i * L1 + l] * mic + ri[i * L1 + l] * mrc);
     mr_hi = mr_lo;
   }
 }
