@@ -36,6 +36,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 constexpr int TM = 128, TN = 128, TK = 16, NTH = 256;
+static_assert(TM == TN, "one LDS slot map serves both operands");
 
 template <int KIND>
 struct Split;
@@ -45,6 +46,7 @@ struct Split<kSplitBf16x3> {
   // (x plane, y plane) of each kept product
   static constexpr int px[6] = {0, 0, 1, 0, 2, 1};
   static constexpr int py[6] = {0, 1, 0, 2, 0, 1};
+  static constexpr int sig[6] = {0, 4, 3, 7, 2, 6};   // LDS row rotation per chunk
   __device__ static inline f16v mfma(u4 a, u4 b, f16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
   }
@@ -54,6 +56,7 @@ struct Split<kSplitFp16x2> {
   static constexpr int planes = 2, products = 3;
   static constexpr int px[3] = {0, 0, 1};
   static constexpr int py[3] = {0, 1, 0};
+  static constexpr int sig[4] = {0, 2, 4, 6};
   __device__ static inline f16v mfma(u4 a, u4 b, f16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
   }
@@ -69,8 +72,15 @@ template <int KIND, bool EXPAND>
 __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   using S = Split<KIND>;
   constexpr int NP = S::planes;
-  __shared__ u4 Xs[2][NP][TM][2];   // [stage][plane][row][k half]: 16 narrow floats per row
-  __shared__ u4 Ys[2][NP][TN][2];
+  // LDS stage layout: [chunk][row], chunk = 2 plane + k half, with the rows
+  // of each chunk rotated within aligned groups of 8 by SIG[chunk].  16-byte
+  // LDS accesses are served 8 lanes at a time over 128 bytes of banks, so a
+  // group of 8 lanes is conflict-free when it touches 8 distinct 16-byte slots
+  // mod 8.  MFMA fragment reads (8 consecutive rows of one chunk) are, for any
+  // rotation; the rotations are chosen so that the stores, where 8 consecutive
+  // lanes hold consecutive (row, chunk) pairs of the global slab, are too.
+  __shared__ u4 Xs[2][2 * NP][TM];
+  __shared__ u4 Ys[2][2 * NP][TN];
 
   const Job J = job_of(B, EXPAND ? PH_EXPAND : PH_MOMENT, xcd_remap(blockIdx.x, gridDim.x));
   const PlanDev &P = J.P;
@@ -114,11 +124,18 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
+  // this lane's fragment slot within a stage, per plane (rows 32 apart add 32)
+  int r_slot[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int ch = 2 * p + (lane >> 5);
+    r_slot[p] = ch * TM + (lane & 24) + ((lane + S::sig[ch]) & 7);
+  }
   // loader roles: a stage row is 2 NP chunks of 16 bytes (plane, k half);
   // thread t moves chunks t + 256 u, u < NP, of the 128-row tile
   constexpr int CH = 2 * NP;
   const int yrow_max = EXPAND ? C.nblocks_pad : P.namp;
-  int l_row[NP], l_pl[NP], l_h[NP];
+  int l_row[NP], l_slot[NP];
   bool x_ok[NP], y_ok[NP];
   size_t x_off[NP], y_off[NP];   // element offsets within a k slab
 #pragma unroll
@@ -126,8 +143,7 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
     const int j = tid + NTH * u;
     l_row[u] = j / CH;
     const int ch = j % CH;
-    l_pl[u] = ch >> 1;
-    l_h[u] = ch & 1;
+    l_slot[u] = ch * TM + (l_row[u] & ~7) + ((l_row[u] + S::sig[ch]) & 7);
     x_ok[u] = (m0 + l_row[u]) < M;
     y_ok[u] = (n0 + l_row[u]) < yrow_max;
     const int xr = EXPAND ? (x_ok[u] ? gmem(C.rows)[m0 + l_row[u]] : 0) : (x_ok[u] ? m0 + l_row[u] : 0);
@@ -163,8 +179,8 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
 #define LSTORE(XV, YV, BUF)                                                        \
   {                                                                                \
     _Pragma("unroll") for (int u = 0; u < NP; ++u) {                               \
-      Xs[BUF][l_pl[u]][l_row[u]][l_h[u]] = x_ok[u] ? XV[u] : zero;                 \
-      Ys[BUF][l_pl[u]][l_row[u]][l_h[u]] = y_ok[u] ? YV[u] : zero;                 \
+      (&Xs[BUF][0][0])[l_slot[u]] = x_ok[u] ? XV[u] : zero;                        \
+      (&Ys[BUF][0][0])[l_slot[u]] = y_ok[u] ? YV[u] : zero;                        \
     }                                                                              \
   }
   auto compute = [&](int buf) __attribute__((always_inline)) {
@@ -173,8 +189,8 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        fa[t][p] = Xs[buf][p][wm * 64 + t * 32 + (lane & 31)][lane >> 5];
-        fb[t][p] = Ys[buf][p][wn * 64 + t * 32 + (lane & 31)][lane >> 5];
+        fa[t][p] = (&Xs[buf][0][0])[r_slot[p] + wm * 64 + t * 32];
+        fb[t][p] = (&Ys[buf][0][0])[r_slot[p] + wn * 64 + t * 32];
       }
 #pragma unroll
     for (int q = 0; q < S::products; ++q)
