@@ -196,7 +196,27 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
     __syncthreads();
   }
 
-  // epilogue: the block potential goes to every member cell of the block
+  // epilogue: the block potential goes to every member cell of the block.
+  // This lane's two blocks are resolved once for all its rows (rect: first
+  // cell and extent; CSR: member range in bcell .. bnj).
+  bool bok[2];
+  int bcell[2] = {0, 0}, bnj[2] = {0, 0}, bnk[2] = {0, 0};
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int b = n0 + wn * 32 + u * 16 + (lane & 15);
+    bok[u] = b < C.nblocks;
+    if (!bok[u]) continue;
+    if (C.rect != nullptr) {
+      const auto rect = gmem(reinterpret_cast<const int *>(C.rect));   // (j0, k0, nj, nk) per block
+      bcell[u] = rect[4 * b] * P.nphi + rect[4 * b + 1];
+      bnj[u] = rect[4 * b + 2];
+      bnk[u] = rect[4 * b + 3];
+    } else {
+      bcell[u] = gmem(C.moff)[b];
+      bnj[u] = gmem(C.moff)[b + 1];
+    }
+  }
+  const auto mem = gmem(C.mem);
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -206,18 +226,17 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
       const auto dst = gmem(phi) + (size_t)gmem(C.rows)[row] * P.ncell;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int b = n0 + wn * 32 + u * 16 + (lane & 15);
-        if (b >= C.nblocks) continue;
+        if (!bok[u]) continue;
         const double v = acc[t][u][r];
         if (C.rect != nullptr) {
-          const auto rect = gmem(reinterpret_cast<const int *>(C.rect));   // (j0, k0, nj, nk) per block
-          const int j0 = rect[4 * b], k0 = rect[4 * b + 1], nj = rect[4 * b + 2], nk = rect[4 * b + 3];
-          for (int j = j0; j < j0 + nj; ++j)
-            for (int k = k0; k < k0 + nk; ++k) dst[j * P.nphi + k] = v;
+          if (bnj[u] == 1 && bnk[u] == 1) {
+            dst[bcell[u]] = v;
+          } else {
+            for (int j = 0; j < bnj[u]; ++j)
+              for (int k = 0; k < bnk[u]; ++k) dst[bcell[u] + j * P.nphi + k] = v;
+          }
         } else {
-          const auto moff = gmem(C.moff), mem = gmem(C.mem);
-          const int e1 = moff[b + 1];
-          for (int e = moff[b]; e < e1; ++e) dst[mem[e]] = v;
+          for (int e = bcell[u]; e < bnj[u]; ++e) dst[mem[e]] = v;
         }
       }
     }

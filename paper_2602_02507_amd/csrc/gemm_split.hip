@@ -233,6 +233,29 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   const auto cscale = gmem(P.cscale), coef = gmem(P.coef);
   const auto pscale = gmem(C.pscale);
   const auto part = gmem(reinterpret_cast<float *>(C.partial));
+  // this lane's two expansion blocks, read once for all its rows: l = 0
+  // table column and member cells (rect: first cell and extent; CSR: member
+  // range in bcell .. bnj)
+  bool bok[2] = {false, false};
+  double bt0[2] = {0.0, 0.0};
+  int bcell[2] = {0, 0}, bnj[2] = {0, 0}, bnk[2] = {0, 0};
+  if (EXPAND) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int blk = n0 + wn * 64 + b * 32 + (lane & 31);
+      bok[b] = blk < N;
+      if (!bok[b]) continue;
+      bt0[b] = tcol0[blk];
+      if (C.rect != nullptr) {
+        bcell[b] = rect[4 * blk] * P.nphi + rect[4 * blk + 1];
+        bnj[b] = rect[4 * blk + 2];
+        bnk[b] = rect[4 * blk + 3];
+      } else {
+        bcell[b] = moff[blk];
+        bnj[b] = moff[blk + 1];
+      }
+    }
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -246,15 +269,17 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
         const auto dst = gmem(phi + (size_t)shell * P.ncell);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          const int blk = n0 + wn * 64 + b * 32 + (lane & 31);
-          if (blk >= N) continue;
-          const double v = c0 * tcol0[blk] + sc * (double)acc[a][b][r];
+          if (!bok[b]) continue;
+          const double v = c0 * bt0[b] + sc * (double)acc[a][b][r];
           if (C.rect != nullptr) {
-            const int j0 = rect[4 * blk], k0 = rect[4 * blk + 1], nj = rect[4 * blk + 2], nk = rect[4 * blk + 3];
-            for (int j = j0; j < j0 + nj; ++j)
-              for (int k = k0; k < k0 + nk; ++k) dst[j * P.nphi + k] = v;
+            if (bnj[b] == 1 && bnk[b] == 1) {
+              dst[bcell[b]] = v;
+            } else {
+              for (int j = 0; j < bnj[b]; ++j)
+                for (int k = 0; k < bnk[b]; ++k) dst[bcell[b] + j * P.nphi + k] = v;
+            }
           } else {
-            for (int e = moff[blk]; e < moff[blk + 1]; ++e) dst[mem[e]] = v;
+            for (int e = bcell[b]; e < bnj[b]; ++e) dst[mem[e]] = v;
           }
         }
       } else {
