@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path beside a split precision")
+    ap.add_argument("--no-tune", action="store_true", help="default launch tuning instead of the autotuner's")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -119,10 +120,20 @@ def main():
     rho = torch.from_numpy(rho_h).to(dev)
     stream = torch.cuda.current_stream(dev)
 
+    # launch tuning from the autotuner (cached per device and mesh shape), outside the timed region
+    tunings, tune_s = {}, 0.0
+    if not args.no_tune:
+        from paper_2602_02507_amd import tune
+        t0 = time.perf_counter()
+        for prec in ([precision] if precision == "fp64" or args.no_fp64 else [precision, "fp64"]):
+            tunings[prec] = tune.tune_plan(mesh, prec, dev, log=lambda m: print("bench: " + m, file=sys.stderr,
+                                                                                   flush=True))
+        tune_s = time.perf_counter() - t0
+
     fp64 = None
     if precision != "fp64" and not args.no_fp64:
         # the plain FP64 GPU solve of the same workload, for the speedup figure
-        p64 = mpole.Plan.from_mesh(mesh, precision="fp64", device=dev)
+        p64 = mpole.Plan.from_mesh(mesh, precision="fp64", device=dev, tuning=tunings.get("fp64"))
         o64 = p64.empty_outputs()
         for _ in range(args.warmup):
             p64.solve_into(rho, **o64)
@@ -137,7 +148,11 @@ def main():
         del p64
         print("bench: fp64 path %.4f ms/solve" % fp64["ms_per_step"], file=sys.stderr, flush=True)
 
-    plan = mpole.Plan.from_mesh(mesh, precision=precision, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = mpole.Plan.from_mesh(mesh, precision=precision, device=dev, tuning=tunings.get(precision))
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t0)   # plan creation + table build (not part of a solve)
     out = plan.empty_outputs()
     for _ in range(args.warmup):
         plan.solve_into(rho, **out)
@@ -145,16 +160,17 @@ def main():
 
     plan.set_timing(True)
     plan.phase_ms()                     # clear
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for k in range(args.steps):
         plan.solve_into(rho, **out)
-    e1.record(stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
     phases = plan.phase_ms()
     plan.set_timing(False)
     print("bench: %.4f ms/solve (wall %.4f ms); phases %s" % (
@@ -186,7 +202,10 @@ def main():
               "config": {"workload": args.workload, "nr": mesh.nr, "ntheta": mesh.ntheta, "nphi": mesh.nphi,
                          "lmax": mesh.lmax, "precision": precision,
                          "coarsened": mesh.class_block is not None},
-              "roofline": roof}
+              "roofline": roof,
+              "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
+              "plan_ms": plan_ms,
+              "tuning": plan.tuning(), "autotuned": not args.no_tune, "tune_s": tune_s}
     if fp64 is not None:
         result["fp64_ms_per_step"] = fp64["ms_per_step"]
         result["speedup_vs_fp64"] = fp64["ms_per_step"] / ms
@@ -210,6 +229,17 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def _tuning_summary(tunings):
+    """Counts of the tile heights chosen over the fields and the moment workgroup total."""
+    if not tunings:
+        return None
+    out = {"moment_wgs_total": int(sum(t["moment_wgs"] for t in tunings))}
+    for k in ("moment_tile_m", "expand_tile_m"):
+        vals, counts = np.unique([t[k] for t in tunings], return_counts=True)
+        out[k] = {str(int(v)): int(c) for v, c in zip(vals, counts)}
+    return out
+
+
 def bench_batch(args, precision):
     """64 seeded fields of uneven size and lmax solved as one batch (one launch
     per phase, all fields), captured once in a HIP graph and replayed."""
@@ -224,8 +254,18 @@ def bench_batch(args, precision):
     cell_modes = float(sum(m.ncells * m.nmodes for m in meshes))
     stream = torch.cuda.current_stream(dev)
 
+    tunings, tune_info = {}, {}
+    if not args.no_tune:
+        from paper_2602_02507_amd import tune
+        for prec in ([precision] if precision == "fp64" or args.no_fp64 else [precision, "fp64"]):
+            print("bench: autotuning %s launches of the 64 fields" % prec, file=sys.stderr, flush=True)
+            tunings[prec], tune_info[prec] = tune.tune_batch(meshes, prec, dev, rho=rho)
+            print("bench: tuned %s in %.1f s (%d new shapes)" % (prec, tune_info[prec]["seconds"],
+                                                                 tune_info[prec]["field_shapes_tuned"]),
+                  file=sys.stderr, flush=True)
+
     def timed_batch(prec):
-        batch = mpole.Batch(meshes, precision=prec, rho=rho, device=dev)
+        batch = mpole.Batch(meshes, precision=prec, rho=rho, device=dev, tunings=tunings.get(prec))
         for _ in range(args.warmup):
             batch.solve()
         torch.cuda.synchronize()
@@ -258,7 +298,10 @@ def bench_batch(args, precision):
               "vs_baseline": None, "dtype": DTYPE[precision], "data": "synthetic",
               "config": {"workload": args.workload, "fields": len(meshes), "cells": int(sum(m.ncells for m in meshes)),
                          "cell_modes": cell_modes, "precision": precision, "hip_graph": True},
-              "field_ms_p50": float(np.percentile(field, 50)), "field_ms_p99": float(np.percentile(field, 99))}
+              "field_ms_p50": float(np.percentile(field, 50)), "field_ms_p99": float(np.percentile(field, 99)),
+              "autotuned": not args.no_tune,
+              "tuning_summary": _tuning_summary(tunings.get(precision)),
+              "tune_s": {k: v["seconds"] for k, v in tune_info.items()}}
     if fp64_ms is not None:
         result["fp64_ms_per_step"] = fp64_ms
         result["speedup_vs_fp64"] = fp64_ms / ms

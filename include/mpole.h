@@ -181,11 +181,30 @@ int mpole_plan_phase_ms(mpole_plan plan, double *total_ms, int64_t *launches);
 int mpole_plan_work(mpole_plan plan, double *moment_flops, double *expand_flops, double *min_bytes);
 
 /*
- * Tuning knob of the moment contraction (host only, before bind): the number
- * of workgroups its K dimension is split over (0 = default, about one round of
- * resident workgroups).  Changes mpole_plan_workspace_bytes.  Used by the
- * autotuner.  mpole_plan_moment_wgs reports the resulting launch size.
+ * Launch tuning of the two angular contractions (host only, before bind; the
+ * choice changes how the same sums are tiled and split, not what they are):
+ *   moment_wgs     workgroup target of the moment contraction, whose K (the
+ *                  blocks of a shell) is split over about that many
+ *                  workgroups; 0 = default (about one round of resident
+ *                  workgroups).  Split precisions also cap each split at 2048
+ *                  blocks, so their FP32 accumulation chains stay short.
+ *   moment_tile_m  output tile height (rows = shells) of the moment
+ *   expand_tile_m  and of the expansion contraction: 0 = default, 64, or 128
+ *                  (128 only for the split precisions; FP64 tiles are 64).
+ * mpole_plan_tune returns MPOLE_ERR_UNSUPPORTED for another tile height and
+ * MPOLE_ERR_INVALID after bind; it changes mpole_plan_workspace_bytes.
+ * mpole_plan_get_tuning reports the plan's current choice (moment_wgs = the
+ * target in use).  mpole_plan_configure(plan, w) is mpole_plan_tune with
+ * {w, 0, 0}; mpole_plan_moment_wgs reports the moment launch size.  These
+ * are the knobs the package's autotuner searches.
  */
+typedef struct {
+  int32_t moment_wgs;
+  int32_t moment_tile_m;
+  int32_t expand_tile_m;
+} mpole_tuning;
+int mpole_plan_tune(mpole_plan plan, const mpole_tuning *tuning);
+int mpole_plan_get_tuning(mpole_plan plan, mpole_tuning *tuning);
 int mpole_plan_configure(mpole_plan plan, int32_t moment_wgs);
 int mpole_plan_moment_wgs(mpole_plan plan);
 
@@ -202,8 +221,10 @@ int mpole_plan_destroy(mpole_plan plan);
  *
  * mpole_batch_create: nfields in [1, 4096] meshes (host descriptors, copied);
  *   MPOLE_ERR_INVALID if their precisions differ.
- * mpole_batch_configure: optional per-field moment workgroup targets
- *   ([nfields], 0 = default), before bind.
+ * mpole_batch_tune: optional per-field launch tuning ([nfields], see
+ *   mpole_plan_tune; a zero moment_wgs means the field's share of one round of
+ *   resident workgroups), before bind.  mpole_batch_configure(batch, w) is
+ *   mpole_batch_tune with {w[f], 0, 0} per field.
  * mpole_batch_bind: binds one device workspace (256-byte aligned) holding all
  *   fields' plans, builds every field's tables on hip_stream, and records the
  *   fields' device I/O pointers rho[f] ([nr][ntheta][nphi] FP64 in) and
@@ -215,6 +236,7 @@ int mpole_plan_destroy(mpole_plan plan);
  */
 typedef struct mpole_batch_t *mpole_batch;
 int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *out);
+int mpole_batch_tune(mpole_batch batch, const mpole_tuning *tunings);
 int mpole_batch_configure(mpole_batch batch, const int32_t *moment_wgs);
 size_t mpole_batch_workspace_bytes(mpole_batch batch);
 int mpole_batch_bind(mpole_batch batch, void *dev_workspace, size_t bytes, const double *const *rho,

@@ -67,8 +67,8 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
   while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_mom_begin)) ++c;
   const ClassDev C = ld_const(P.classes + c);
   const int local = J.local - C.wg_mom_begin;
-  const int mt = local % C.m_tiles;
-  const int rest = local / C.m_tiles;
+  const int mt = local % C.m_tiles_mom;
+  const int rest = local / C.m_tiles_mom;
   const int nt = rest % C.n_tiles_mom;
   const int split = rest / C.n_tiles_mom;
   const int m0 = mt * BM, n0 = nt * BN;
@@ -146,8 +146,8 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
   while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_exp_begin)) ++c;
   const ClassDev C = ld_const(P.classes + c);
   const int local = J.local - C.wg_exp_begin;
-  const int mt = local % C.m_tiles;
-  const int nt = local / C.m_tiles;
+  const int mt = local % C.m_tiles_exp;
+  const int nt = local / C.m_tiles_exp;
   const int m0 = mt * BM, n0 = nt * BN;
   const int nrows = C.nrows, namp = P.namp;
   const double *__restrict__ T = C.table;

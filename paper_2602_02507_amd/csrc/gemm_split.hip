@@ -13,8 +13,9 @@
 // terms hi.hi, hi.mid, mid.hi, hi.lo, lo.hi, mid.mid (the dropped ones are
 // below 2^-24 relative); with FP16 x2 the three terms hi.hi, hi.lo, lo.hi.
 //
-// Workgroup: 4 wavefronts in 2 x 2, tile 128 x 128, each wavefront 64 x 64 as
-// 2 x 2 MFMA 32x32 tiles; K advances 16 per LDS stage (one MFMA step),
+// Workgroup: 4 wavefronts in 2 x 2, tile TM x 128 (TM = 128 or 64), each
+// wavefront (TM/2) x 64 as (TM/64) x 2 MFMA 32x32 tiles; K advances 16 per LDS
+// stage (one MFMA step),
 // double-buffered in LDS with loads issued two stages ahead.  Accumulation is FP32.  The monopole (l = 0) carries most
 // of both sums for the near-spherical sources of interest, so it is taken out
 // of the FP32 sums and done in FP64 elsewhere: the monopole moment is summed in
@@ -35,8 +36,10 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));   // 16 raw bytes
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
-constexpr int TM = 128, TN = 128, TK = 16, NTH = 256;
-static_assert(TM == TN, "one LDS slot map serves both operands");
+// Tile width TN and the K stage are fixed; the tile height TM is 128 or 64,
+// chosen per plan and contraction (a tuning knob: 64 wastes less on short
+// row counts and doubles the workgroups, 128 reuses each fragment twice).
+constexpr int TMMAX = 128, TN = 128, TK = 16, NTH = 256;
 
 template <int KIND>
 struct Split;
@@ -68,33 +71,18 @@ struct Operand {
   int rows;
 };
 
-template <int KIND, bool EXPAND>
-__global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
+// One output tile of a contraction; LDS holds two stages of X (TMV rows)
+// and Y (TN rows) in the slot layout described in the kernel.
+template <int KIND, bool EXPAND, int TMV>
+__device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, const ClassDev &C,
+                                          double *__restrict__ phi, int local, u4 *lds) {
   using S = Split<KIND>;
-  constexpr int NP = S::planes;
-  // LDS stage layout: [chunk][row], chunk = 2 plane + k half, with the rows
-  // of each chunk rotated within aligned groups of 8 by SIG[chunk].  16-byte
-  // LDS accesses are served 8 lanes at a time over 128 bytes of banks, so a
-  // group of 8 lanes is conflict-free when it touches 8 distinct 16-byte slots
-  // mod 8.  MFMA fragment reads (8 consecutive rows of one chunk) are, for any
-  // rotation; the rotations are chosen so that the stores, where 8 consecutive
-  // lanes hold consecutive (row, chunk) pairs of the global slab, are too.
-  __shared__ u4 Xs[2][2 * NP][TM];
-  __shared__ u4 Ys[2][2 * NP][TN];
-
-  const Job J = job_of(B, EXPAND ? PH_EXPAND : PH_MOMENT, xcd_remap(blockIdx.x, gridDim.x));
-  const PlanDev &P = J.P;
-  double *__restrict__ phi = J.io.phi;
-  int c = 0;
-  if (EXPAND) {
-    while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_exp_begin)) ++c;
-  } else {
-    while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_mom_begin)) ++c;
-  }
-  const ClassDev C = ld_const(P.classes + c);
-  const int local = J.local - (EXPAND ? C.wg_exp_begin : C.wg_mom_begin);
-  const int mt = local % C.m_tiles;
-  const int rest = local / C.m_tiles;
+  constexpr int NP = S::planes, CH = 2 * NP, AT = TMV / 64;
+  u4 *Xs = lds;                       // [2][CH][TMV]
+  u4 *Ys = lds + 2 * CH * TMMAX;      // [2][CH][TN]
+  const int m_tiles = EXPAND ? C.m_tiles_exp : C.m_tiles_mom;
+  const int mt = local % m_tiles;
+  const int rest = local / m_tiles;
   int nt, split = 0;
   if (EXPAND) {
     nt = rest;
@@ -102,7 +90,7 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
     nt = rest % C.n_tiles_mom;
     split = rest / C.n_tiles_mom;
   }
-  const int m0 = mt * TM, n0 = nt * TN;
+  const int m0 = mt * TMV, n0 = nt * TN;
   const int M = C.nrows;
   const int N = EXPAND ? C.nblocks : P.namp;
   int kbeg, kend;
@@ -124,38 +112,40 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
-  // this lane's fragment slot within a stage, per plane (rows 32 apart add 32)
-  int r_slot[NP];
+  // this lane's fragment slots within a stage, per plane (rows 32 apart add 32)
+  int rx_slot[NP], ry_slot[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const int ch = 2 * p + (lane >> 5);
-    r_slot[p] = ch * TM + (lane & 24) + ((lane + S::sig[ch]) & 7);
+    const int low = (lane & 24) + ((lane + S::sig[ch]) & 7);
+    rx_slot[p] = ch * TMV + low;
+    ry_slot[p] = ch * TN + low;
   }
-  // loader roles: a stage row is 2 NP chunks of 16 bytes (plane, k half);
-  // thread t moves chunks t + 256 u, u < NP, of the 128-row tile
-  constexpr int CH = 2 * NP;
+  // loader roles: a stage row is CH chunks of 16 bytes (plane, k half).  The
+  // Y tile (128 rows) is moved by all threads, chunks t + 256 u; the X tile by
+  // the first 2 TMV threads, chunks t + 2 TMV u (u < NP).
+  const bool x_loader = tid < 2 * TMV;
   const int yrow_max = EXPAND ? C.nblocks_pad : P.namp;
-  int l_row[NP], l_slot[NP];
+  int lx_slot[NP], ly_slot[NP];
   bool x_ok[NP], y_ok[NP];
   size_t x_off[NP], y_off[NP];   // element offsets within a k slab
 #pragma unroll
   for (int u = 0; u < NP; ++u) {
-    const int j = tid + NTH * u;
-    l_row[u] = j / CH;
-    const int ch = j % CH;
-    l_slot[u] = ch * TM + (l_row[u] & ~7) + ((l_row[u] + S::sig[ch]) & 7);
-    x_ok[u] = (m0 + l_row[u]) < M;
-    y_ok[u] = (n0 + l_row[u]) < yrow_max;
-    const int xr = EXPAND ? (x_ok[u] ? gmem(C.rows)[m0 + l_row[u]] : 0) : (x_ok[u] ? m0 + l_row[u] : 0);
-    const int yr = y_ok[u] ? n0 + l_row[u] : 0;
-    x_off[u] = (size_t)xr * (16 * NP) + 8 * ch;
-    y_off[u] = (size_t)yr * (16 * NP) + 8 * ch;
+    const int jy = tid + NTH * u, ry = jy / CH, cy = jy % CH;
+    ly_slot[u] = cy * TN + (ry & ~7) + ((ry + S::sig[cy]) & 7);
+    y_ok[u] = (n0 + ry) < yrow_max;
+    y_off[u] = (size_t)(y_ok[u] ? n0 + ry : 0) * (16 * NP) + 8 * cy;
+    const int jx = tid + 2 * TMV * u, rx = jx / CH, cx = jx % CH;
+    lx_slot[u] = cx * TMV + (rx & ~7) + ((rx + S::sig[cx]) & 7);
+    x_ok[u] = x_loader && (m0 + rx) < M;
+    const int xr = EXPAND ? (x_ok[u] ? gmem(C.rows)[m0 + rx] : 0) : (x_ok[u] ? m0 + rx : 0);
+    x_off[u] = (size_t)xr * (16 * NP) + 8 * cx;
   }
   const size_t x_slab = (size_t)X.rows * 16 * NP, y_slab = (size_t)Y.rows * 16 * NP;
 
-  f16v acc[2][2];
+  f16v acc[AT][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AT; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
 
@@ -164,38 +154,39 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
   // each load has two stages of MFMA work to hide behind.  Loads are
   // unconditional (rows outside the operand read row 0 and are zeroed at the
   // LDS store) and go through global address-space pointers, so nothing waits
-  // on them before the store.
+  // on them before the store.  With TMV = 64 the second half of the threads
+  // loads no X chunks (a wave-uniform condition).
   typedef const __attribute__((address_space(1))) u4 *gptr;
   u4 xa[NP], ya[NP], xb[NP], yb[NP];
   const u4 zero = {0u, 0u, 0u, 0u};
-#define GLOAD(XV, YV, K)                                                           \
-  {                                                                                \
+#define GLOAD(XV, YV, K)                                                             \
+  {                                                                                  \
     const size_t kx_ = (size_t)((K) >> 4) * x_slab, ky_ = (size_t)((K) >> 4) * y_slab; \
-    _Pragma("unroll") for (int u = 0; u < NP; ++u) {                               \
-      XV[u] = *(gptr)(X.base + kx_ + x_off[u]);                                    \
-      YV[u] = *(gptr)(Y.base + ky_ + y_off[u]);                                    \
-    }                                                                              \
+    _Pragma("unroll") for (int u = 0; u < NP; ++u) {                                 \
+      if (TMV == TMMAX || x_loader) XV[u] = *(gptr)(X.base + kx_ + x_off[u]);        \
+      YV[u] = *(gptr)(Y.base + ky_ + y_off[u]);                                      \
+    }                                                                                \
   }
-#define LSTORE(XV, YV, BUF)                                                        \
-  {                                                                                \
-    _Pragma("unroll") for (int u = 0; u < NP; ++u) {                               \
-      (&Xs[BUF][0][0])[l_slot[u]] = x_ok[u] ? XV[u] : zero;                        \
-      (&Ys[BUF][0][0])[l_slot[u]] = y_ok[u] ? YV[u] : zero;                        \
-    }                                                                              \
+#define LSTORE(XV, YV, BUF)                                                          \
+  {                                                                                  \
+    _Pragma("unroll") for (int u = 0; u < NP; ++u) {                                 \
+      if (TMV == TMMAX || x_loader) Xs[(BUF) * CH * TMV + lx_slot[u]] = x_ok[u] ? XV[u] : zero; \
+      Ys[(BUF) * CH * TN + ly_slot[u]] = y_ok[u] ? YV[u] : zero;                      \
+    }                                                                                \
   }
   auto compute = [&](int buf) __attribute__((always_inline)) {
-    u4 fa[2][NP], fb[2][NP];
+    u4 fa[AT][NP], fb[2][NP];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        fa[t][p] = (&Xs[buf][0][0])[r_slot[p] + wm * 64 + t * 32];
-        fb[t][p] = (&Ys[buf][0][0])[r_slot[p] + wn * 64 + t * 32];
-      }
+      for (int t = 0; t < AT; ++t) fa[t][p] = Xs[buf * CH * TMV + rx_slot[p] + wm * (TMV / 2) + t * 32];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) fb[t][p] = Ys[buf * CH * TN + ry_slot[p] + wn * 64 + t * 32];
+    }
 #pragma unroll
     for (int q = 0; q < S::products; ++q)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < AT; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = S::mfma(fa[a][S::px[q]], fb[b][S::py[q]], acc[a][b]);
   };
@@ -257,10 +248,10 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
     }
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AT; ++a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = m0 + wm * 64 + a * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+      const int row = m0 + wm * (TMV / 2) + a * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
       if (row >= M) continue;
       if (EXPAND) {
         const int shell = rows[row];
@@ -293,6 +284,34 @@ __global__ __launch_bounds__(NTH) void k_gemm_split(BatchDev B) {
         }
       }
     }
+}
+
+template <int KIND, bool EXPAND>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_split(BatchDev B) {
+  constexpr int CH = 2 * Split<KIND>::planes;
+  // LDS stage layout: [chunk][row], chunk = 2 plane + k half, with the rows
+  // of each chunk rotated within aligned groups of 8 by sig[chunk].  16-byte
+  // LDS accesses are served 8 lanes at a time over 128 bytes of banks, so a
+  // group of 8 lanes is conflict-free when it touches 8 distinct 16-byte slots
+  // mod 8.  MFMA fragment reads (8 consecutive rows of one chunk) are, for any
+  // rotation; the rotations are chosen so that the stores, where 8 consecutive
+  // lanes hold consecutive (row, chunk) pairs of the global slab, are too.
+  __shared__ u4 lds[2 * CH * (TMMAX + TN)];
+
+  const Job J = job_of(B, EXPAND ? PH_EXPAND : PH_MOMENT, xcd_remap(blockIdx.x, gridDim.x));
+  const PlanDev &P = J.P;
+  int c = 0;
+  if (EXPAND) {
+    while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_exp_begin)) ++c;
+  } else {
+    while (c + 1 < P.nclasses && J.local >= ld_const(&P.classes[c + 1].wg_mom_begin)) ++c;
+  }
+  const ClassDev C = ld_const(P.classes + c);
+  const int local = J.local - (EXPAND ? C.wg_exp_begin : C.wg_mom_begin);
+  if ((EXPAND ? P.tm_exp : P.tm_mom) == 64)
+    gemm_tile<KIND, EXPAND, 64>(B, P, C, J.io.phi, local, lds);
+  else
+    gemm_tile<KIND, EXPAND, 128>(B, P, C, J.io.phi, local, lds);
   if (EXPAND) stamp_done(B, J.f);
 }
 

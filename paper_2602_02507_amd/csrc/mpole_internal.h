@@ -35,7 +35,7 @@ struct ClassDev {
   double *partial;       // [splits][nrows][namp] split-K partial moments
   int32_t nrows, nblocks, nblocks_pad;
   int32_t splits, kchunk;             // moment split-K: splits x kchunk >= nblocks_pad
-  int32_t m_tiles, n_tiles_mom, n_tiles_exp;
+  int32_t m_tiles_mom, m_tiles_exp, n_tiles_mom, n_tiles_exp;   // tiles of the contractions
   int32_t wg_mom_begin, wg_exp_begin;  // prefix sums over classes
 };
 
@@ -61,6 +61,7 @@ struct PlanDev {
   int32_t mono_stride;
   int32_t pack_parts;       // packing workgroups per shell
   int32_t wg_mom, wg_exp;   // workgroups of the two contraction launches
+  int32_t tm_mom, tm_exp;   // output tile heights of the two contractions
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
 };
 

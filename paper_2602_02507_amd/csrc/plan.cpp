@@ -75,7 +75,7 @@ struct ClassHost {
   std::vector<int32_t> rect;  // 4 per block when every block is a rectangle in (j, k)
   size_t off_rect = 0;
   int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
-  int m_tiles = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
+  int m_tiles_mom = 0, m_tiles_exp = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
   size_t off_rows = 0, off_moff = 0, off_mem = 0, off_table = 0, off_pack = 0, off_partial = 0;
   size_t off_tplanes = 0, off_ttplanes = 0, off_ppacks = 0, off_pscale = 0, off_tcol0 = 0;
 };
@@ -98,7 +98,7 @@ struct mpole_plan_t {
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
-  int nplanes = 0, tile_m = 64, tile_n = 64, kpad = 16, moment_target = 0;
+  int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
   size_t off_plandev = 0, off_prefix = 0;
   int wg_mom = 0, wg_exp = 0;
   GaussRule rule{};
@@ -136,7 +136,7 @@ void choose_splits(mpole_plan_t &p, int target) {
   double total = 0.0;
   for (auto &c : p.cls) total += (double)c.rows.size() * c.nblocks_pad;
   for (auto &c : p.cls) {
-    const int tiles = c.m_tiles * c.n_tiles_mom;
+    const int tiles = c.m_tiles_mom * c.n_tiles_mom;
     const double share = total > 0 ? target * (double)c.rows.size() * c.nblocks_pad / total : 1.0;
     int s = (int)std::lround(share / std::max(tiles, 1));
     // FP32-accumulated contractions: no split longer than kMaxSplitChunk
@@ -150,6 +150,7 @@ void choose_splits(mpole_plan_t &p, int target) {
 }
 
 void layout_plan(mpole_plan_t *p, int target);
+int default_target(const mpole_plan_t *p);
 
 int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   if (!m) return fail(MPOLE_ERR_INVALID, "mesh is null");
@@ -190,8 +191,9 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->ncell = (int)ncell;
   p->precision = m->precision;
   p->nplanes = n_planes(m->precision);
-  // output tiles of the contraction kernels: 64 x 64 (f64 MFMA), 128 x 128 (split)
-  p->tile_m = p->nplanes ? 128 : 64;
+  // output tiles of the contraction kernels: 64 x 64 (f64 MFMA); 128 x 128
+  // (split; the height may be tuned to 64)
+  p->tm_mom = p->tm_exp = p->nplanes ? 128 : 64;
   p->tile_n = p->nplanes ? 128 : 64;
   p->G = m->G;
   p->r.assign(m->r_edges, m->r_edges + m->nr + 1);
@@ -251,30 +253,56 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       C.rect[4 * b + 3] = k1 - k0 + 1;
     }
     if (!rect_ok) C.rect.clear();
-    C.m_tiles = std::max(1, ((int)C.rows.size() + p->tile_m - 1) / p->tile_m);
     C.n_tiles_mom = (p->namp + p->tile_n - 1) / p->tile_n;
     C.n_tiles_exp = (C.nblocks + p->tile_n - 1) / p->tile_n;
   }
   p->rule = make_gauss_rule();
   // about one full round of resident workgroups: 4 per CU (f64 kernel), 3 per CU (split kernel)
+  layout_plan(p, default_target(p));
+  return MPOLE_OK;
+}
+
+// Tuning validation: tile heights 0 (default), 64 or 128 for the split
+// contractions, 0 or 64 for the FP64 ones; moment workgroups >= 0.
+int check_tuning(const mpole_plan_t *p, const mpole_tuning *t) {
+  if (t->moment_wgs < 0) return fail(MPOLE_ERR_INVALID, "moment_wgs %d < 0", t->moment_wgs);
+  const int hs[2] = {t->moment_tile_m, t->expand_tile_m};
+  for (int h : hs) {
+    const bool okh = h == 0 || h == 64 || (h == 128 && p->nplanes > 0);
+    if (!okh) return fail(MPOLE_ERR_UNSUPPORTED, "tile height %d (64%s)", h, p->nplanes ? " or 128" : " only for FP64");
+  }
+  return MPOLE_OK;
+}
+
+int default_target(const mpole_plan_t *p) {
   int target = p->nplanes ? 768 : 1024;
   if (const char *env = std::getenv("MPOLE_MOMENT_WGS")) target = std::max(1, std::atoi(env));
+  return target;
+}
+
+void apply_tuning(mpole_plan_t *p, const mpole_tuning *t, int target) {
+  const int def = p->nplanes ? 128 : 64;
+  p->tm_mom = t->moment_tile_m ? t->moment_tile_m : def;
+  p->tm_exp = t->expand_tile_m ? t->expand_tile_m : def;
   layout_plan(p, target);
-  return MPOLE_OK;
 }
 
 // Split-K choice, workgroup counts and workspace layout for a moment
 // workgroup target (host only; may be redone before bind).
 void layout_plan(mpole_plan_t *p, int target) {
   p->moment_target = target;
+  for (auto &C : p->cls) {
+    C.m_tiles_mom = std::max(1, ((int)C.rows.size() + p->tm_mom - 1) / p->tm_mom);
+    C.m_tiles_exp = std::max(1, ((int)C.rows.size() + p->tm_exp - 1) / p->tm_exp);
+  }
   choose_splits(*p, target);
   int wm = 0, we = 0;
   for (auto &C : p->cls) {
     C.wg_mom_begin = wm;
     C.wg_exp_begin = we;
     if (!C.rows.empty()) {
-      wm += C.m_tiles * C.n_tiles_mom * C.splits;
-      we += C.m_tiles * C.n_tiles_exp;
+      wm += C.m_tiles_mom * C.n_tiles_mom * C.splits;
+      we += C.m_tiles_exp * C.n_tiles_exp;
     }
   }
   p->wg_mom = wm;
@@ -423,6 +451,8 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   D = PlanDev{};
   D.pack_parts = p->mono_stride;
   D.wg_mom = p->wg_mom;
+  D.tm_mom = p->tm_mom;
+  D.tm_exp = p->tm_exp;
   D.wg_exp = p->wg_exp;
   D.nr = p->nr;
   D.ntheta = p->nt;
@@ -477,7 +507,8 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     C.nblocks_pad = H.nblocks_pad;
     C.splits = H.splits;
     C.kchunk = H.kchunk;
-    C.m_tiles = H.m_tiles;
+    C.m_tiles_mom = H.m_tiles_mom;
+    C.m_tiles_exp = H.m_tiles_exp;
     C.n_tiles_mom = H.n_tiles_mom;
     C.n_tiles_exp = H.n_tiles_exp;
     C.wg_mom_begin = H.wg_mom_begin;
@@ -545,9 +576,26 @@ extern "C" {
 
 int mpole_plan_configure(mpole_plan p, int32_t moment_wgs) {
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
-  if (moment_wgs < 0) return fail(MPOLE_ERR_INVALID, "moment_wgs < 0");
-  if (p->bound) return fail(MPOLE_ERR_INVALID, "configure before binding a workspace");
-  layout_plan(p, moment_wgs > 0 ? moment_wgs : (p->nplanes ? 768 : 1024));
+  const mpole_tuning t = {moment_wgs, 0, 0};
+  return mpole_plan_tune(p, &t);
+}
+
+int mpole_plan_tune(mpole_plan p, const mpole_tuning *t) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!t) return fail(MPOLE_ERR_INVALID, "tuning is null");
+  if (p->bound) return fail(MPOLE_ERR_INVALID, "tune before binding a workspace");
+  int rc = check_tuning(p, t);
+  if (rc) return rc;
+  apply_tuning(p, t, t->moment_wgs > 0 ? t->moment_wgs : default_target(p));
+  return ok();
+}
+
+int mpole_plan_get_tuning(mpole_plan p, mpole_tuning *t) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!t) return fail(MPOLE_ERR_INVALID, "tuning is null");
+  t->moment_wgs = p->moment_target;
+  t->moment_tile_m = p->tm_mom;
+  t->expand_tile_m = p->tm_exp;
   return ok();
 }
 
@@ -655,7 +703,7 @@ namespace {
 
 // Default per-field moment targets: one round of resident workgroups shared
 // in proportion to each field's moment work.
-void batch_layout(mpole_batch_t *b, const int32_t *targets) {
+void batch_layout(mpole_batch_t *b, const mpole_tuning *tunings) {
   const int nf = (int)b->plans.size();
   double total = 0.0;
   std::vector<double> work(nf);
@@ -668,8 +716,10 @@ void batch_layout(mpole_batch_t *b, const int32_t *targets) {
   }
   const int round = b->precision ? 768 : 1024;
   for (int f = 0; f < nf; ++f) {
-    int t = (targets && targets[f] > 0) ? targets[f] : (int)std::lround(round * work[f] / std::max(total, 1.0));
-    layout_plan(b->plans[f], std::max(t, 1));
+    const mpole_tuning none = {0, 0, 0};
+    const mpole_tuning &tf = tunings ? tunings[f] : none;
+    const int t = tf.moment_wgs > 0 ? tf.moment_wgs : (int)std::lround(round * work[f] / std::max(total, 1.0));
+    apply_tuning(b->plans[f], &tf, std::max(t, 1));
   }
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -728,8 +778,24 @@ int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *o
 
 int mpole_batch_configure(mpole_batch b, const int32_t *moment_wgs) {
   if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
-  if (b->bound) return fail(MPOLE_ERR_INVALID, "configure before binding a workspace");
-  batch_layout(b, moment_wgs);
+  if (!moment_wgs) return mpole_batch_tune(b, nullptr);
+  std::vector<mpole_tuning> t(b->plans.size());
+  for (size_t f = 0; f < t.size(); ++f) t[f] = {moment_wgs[f], 0, 0};
+  return mpole_batch_tune(b, t.data());
+}
+
+int mpole_batch_tune(mpole_batch b, const mpole_tuning *tunings) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (b->bound) return fail(MPOLE_ERR_INVALID, "tune before binding a workspace");
+  if (tunings)
+    for (size_t f = 0; f < b->plans.size(); ++f) {
+      const int rc = check_tuning(b->plans[f], &tunings[f]);
+      if (rc) {
+        const std::string msg = g_error;
+        return fail(rc, "field %zu: %s", f, msg.c_str());
+      }
+    }
+  batch_layout(b, tunings);
   return ok();
 }
 

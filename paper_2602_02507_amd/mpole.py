@@ -22,11 +22,29 @@ STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE
 # every entry point include/mpole.h declares
 EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_plan_workspace_bytes",
            "mpole_plan_nmodes", "mpole_plan_bind", "mpole_solve", "mpole_plan_copy_table",
-           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_plan_configure",
-           "mpole_plan_moment_wgs", "mpole_plan_destroy",
-           "mpole_batch_create", "mpole_batch_configure", "mpole_batch_workspace_bytes", "mpole_batch_bind",
+           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_plan_tune",
+           "mpole_plan_get_tuning", "mpole_plan_configure", "mpole_plan_moment_wgs", "mpole_plan_destroy",
+           "mpole_batch_create", "mpole_batch_tune", "mpole_batch_configure", "mpole_batch_workspace_bytes",
+           "mpole_batch_bind",
            "mpole_batch_solve", "mpole_batch_field_ms", "mpole_batch_destroy")
 PHASES = ("pack", "moment", "reduce", "scan", "split", "expand")
+
+
+class Tuning(ctypes.Structure):
+    """Launch tuning of the two contractions (mpole_tuning); zeros mean defaults."""
+    _fields_ = [("moment_wgs", ctypes.c_int32), ("moment_tile_m", ctypes.c_int32),
+                ("expand_tile_m", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+    @classmethod
+    def of(cls, t):
+        """Tuning from a Tuning, a dict with some of the three keys, or None (defaults)."""
+        if isinstance(t, cls):
+            return t
+        t = dict(t or {})
+        return cls(int(t.get("moment_wgs", 0)), int(t.get("moment_tile_m", 0)), int(t.get("expand_tile_m", 0)))
 
 
 class MpoleError(RuntimeError):
@@ -75,10 +93,13 @@ def lib():
         L.mpole_plan_phase_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         dptr = ctypes.POINTER(ctypes.c_double)
         L.mpole_plan_work.argtypes = [vp, dptr, dptr, dptr]
+        L.mpole_plan_tune.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.mpole_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_plan_configure.argtypes = [vp, ctypes.c_int32]
         L.mpole_plan_moment_wgs.argtypes = [vp]
         L.mpole_plan_destroy.argtypes = [vp]
         L.mpole_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(MeshC), ctypes.POINTER(vp)]
+        L.mpole_batch_tune.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_batch_configure.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.mpole_batch_workspace_bytes.argtypes = [vp]
         L.mpole_batch_workspace_bytes.restype = sz
@@ -129,7 +150,7 @@ class HostPlan:
     """A validated plan without device state (mpole_plan_create only)."""
 
     def __init__(self, r_edges, theta_edges, phi_edges, lmax, shell_class=None, class_block=None,
-                 G=1.0, precision="fp64", moment_wgs=0):
+                 G=1.0, precision="fp64", moment_wgs=0, tuning=None):
         m, self._keep = make_mesh(r_edges, theta_edges, phi_edges, lmax, shell_class, class_block, G, precision)
         self.nr, self.ntheta, self.nphi, self.lmax = m.nr, m.ntheta, m.nphi, m.lmax
         self._mesh = m
@@ -139,13 +160,22 @@ class HostPlan:
         self.nmodes = lib().mpole_plan_nmodes(h)
         if moment_wgs:
             _check(lib().mpole_plan_configure(h, int(moment_wgs)))
+        if tuning is not None:
+            t = Tuning.of(tuning)
+            _check(lib().mpole_plan_tune(h, ctypes.byref(t)))
         self.workspace_bytes = lib().mpole_plan_workspace_bytes(h)
         self.moment_wgs = lib().mpole_plan_moment_wgs(h)
 
     @classmethod
-    def from_mesh(cls, mesh, precision="fp64"):
+    def from_mesh(cls, mesh, precision="fp64", tuning=None):
         return cls(mesh.r_edges, mesh.theta_edges, mesh.phi_edges, mesh.lmax, mesh.shell_class,
-                   mesh.class_block, mesh.G, precision)
+                   mesh.class_block, mesh.G, precision, tuning=tuning)
+
+    def tuning(self):
+        """The plan's launch tuning in use, as a dict."""
+        t = Tuning()
+        _check(lib().mpole_plan_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
 
     def work(self):
         """(moment flops, expansion flops, minimum HBM bytes) of one solve."""
@@ -190,9 +220,10 @@ class Plan(HostPlan):
                                      ctypes.c_void_p(stream)))
 
     @classmethod
-    def from_mesh(cls, mesh, precision="fp64", device="cuda", moment_wgs=0):
+    def from_mesh(cls, mesh, precision="fp64", device="cuda", moment_wgs=0, tuning=None):
         return cls(mesh.r_edges, mesh.theta_edges, mesh.phi_edges, mesh.lmax, mesh.shell_class,
-                   mesh.class_block, mesh.G, precision=precision, device=device, moment_wgs=moment_wgs)
+                   mesh.class_block, mesh.G, precision=precision, device=device, moment_wgs=moment_wgs,
+                   tuning=tuning)
 
     @property
     def shape(self):
@@ -251,7 +282,7 @@ class Batch:
     batch solve on the current stream (graph-capturable); `field_ms()` gives
     each field's completion time within the last solve after a sync."""
 
-    def __init__(self, meshes, precision="bf16x3", rho=None, device="cuda", moment_wgs=None):
+    def __init__(self, meshes, precision="bf16x3", rho=None, device="cuda", moment_wgs=None, tunings=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("mpole needs a ROCm GPU; none is visible to torch")
@@ -269,6 +300,11 @@ class Batch:
         if moment_wgs is not None:
             arr = (ctypes.c_int32 * self.n)(*[int(x) for x in moment_wgs])
             _check(lib().mpole_batch_configure(h, arr))
+        if tunings is not None:
+            if len(tunings) != self.n:
+                raise ValueError("one tuning per field")
+            arr = (Tuning * self.n)(*[Tuning.of(t) for t in tunings])
+            _check(lib().mpole_batch_tune(h, arr))
         dev = torch.device(device)
         if dev.index is None:
             dev = torch.device(dev.type, torch.cuda.current_device())

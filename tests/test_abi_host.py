@@ -91,3 +91,38 @@ def test_error_message_is_per_call():
     assert mpole.lib().mpole_last_error().decode() != ""
     mpole.HostPlan(**mk())
     assert mpole.lib().mpole_last_error().decode() == ""
+
+
+def test_tuning_knobs_validated_and_reported():
+    m = wl.production_mesh(16)
+    p = mpole.HostPlan.from_mesh(m, precision="bf16x3")
+    t0 = p.tuning()
+    assert t0["moment_tile_m"] == 128 and t0["expand_tile_m"] == 128 and t0["moment_wgs"] > 0
+    w0 = p.moment_wgs
+    lib = mpole.lib()
+    t = mpole.Tuning(0, 64, 64)
+    assert lib.mpole_plan_tune(p.handle, t) == 0
+    assert p.tuning() == {"moment_wgs": t0["moment_wgs"], "moment_tile_m": 64, "expand_tile_m": 64}
+    # half-height tiles double the moment tiles at the same split count or more
+    assert lib.mpole_plan_moment_wgs(p.handle) >= w0
+    for bad in (mpole.Tuning(0, 32, 0), mpole.Tuning(0, 0, 256), mpole.Tuning(-1, 0, 0)):
+        rc = lib.mpole_plan_tune(p.handle, bad)
+        assert rc in (1, 5), rc
+        assert lib.mpole_last_error()
+    # FP64 tiles are 64 high only
+    q = mpole.HostPlan.from_mesh(m, precision="fp64")
+    assert lib.mpole_plan_tune(q.handle, mpole.Tuning(0, 128, 0)) == 5
+    assert lib.mpole_plan_tune(q.handle, mpole.Tuning(2048, 64, 64)) == 0
+    assert q.tuning()["moment_wgs"] == 2048
+
+
+def test_split_chunk_cap_bounds_accumulation_chains():
+    # one workgroup requested: the split precisions still split K into chunks of
+    # at most 2048 blocks (FP32 accumulators), FP64 does not
+    m = wl.production_mesh(16)
+    outer_blocks = 128 * 256 - 16 * 256 + 16 * 256 // 4   # outer class: 8 polar rows per pole merged 1x4 in phi
+    b = mpole.HostPlan.from_mesh(m, precision="bf16x3", tuning={"moment_wgs": 1})
+    f = mpole.HostPlan.from_mesh(m, precision="fp64", tuning={"moment_wgs": 1})
+    n_tiles = (289 + 127) // 128
+    assert b.moment_wgs >= 4 * n_tiles * -(-outer_blocks // 2048)
+    assert f.moment_wgs == -(-480 // 64) * 5 + 1 * 5   # FP64: one split per 64 x 64 tile

@@ -47,6 +47,29 @@ def test_batch_matches_single_plans_and_oracle(precision, tol):
         assert rel <= tol, (f, rel)
 
 
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-6), ("fp16x2", 1e-6)])
+def test_batch_with_mixed_tile_heights(precision, tol):
+    """Per-field launch tunings (as the autotuner picks them) in one batch:
+    each field equals its single-plan solve under the same tuning, bitwise."""
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    meshes = small_batch(6, seed0=123)
+    rho = [torch.from_numpy(r).cuda() for r in wl.batch_densities(meshes, seed0=123)]
+    tun = [{"moment_wgs": w, "moment_tile_m": hm, "expand_tile_m": he}
+           for w, hm, he in [(3, 64, 64), (1, 128, 64), (6, 64, 128), (2, 128, 128), (9, 64, 64), (4, 128, 64)]]
+    batch = mpole.Batch(meshes, precision=precision, rho=rho, tunings=tun)
+    batch.solve()
+    torch.cuda.synchronize()
+    for f, m in enumerate(meshes):
+        plan = mpole.Plan.from_mesh(m, precision=precision, tuning=tun[f])
+        single = plan.solve(rho[f])["phi"]
+        torch.cuda.synchronize()
+        assert torch.equal(single, batch.phi[f]), f
+        ref = oracle.solve(rho=rho[f].cpu().numpy(), **m.oracle_kwargs())["phi"]
+        rel = np.max(np.abs(batch.phi[f].cpu().numpy() - ref) / np.abs(ref))
+        assert rel <= tol, (f, rel)
+
+
 def test_batch_graph_replay_matches_eager():
     torch = _torch()
     from paper_2602_02507_amd import mpole

@@ -13,12 +13,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-6
 
 
-def run(mesh, rho, precision):
+def run(mesh, rho, precision, tuning=None):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2602_02507_amd import mpole
-    plan = mpole.Plan.from_mesh(mesh, precision=precision)
+    plan = mpole.Plan.from_mesh(mesh, precision=precision, tuning=tuning)
     out = plan.solve(torch.from_numpy(np.ascontiguousarray(rho)).cuda())
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
@@ -77,3 +77,35 @@ def test_spheroid_mixed():
     ref = oracle.solve(rho=rho, **m.oracle_kwargs())
     rel = np.abs(got["phi"] - ref["phi"]) / np.abs(ref["phi"])
     assert rel.max() <= TOL, rel.max()
+
+
+TUNINGS = [
+    {"moment_tile_m": 64, "expand_tile_m": 64},
+    {"moment_tile_m": 64, "expand_tile_m": 128, "moment_wgs": 3000},
+    {"moment_tile_m": 128, "expand_tile_m": 64, "moment_wgs": 1},
+]
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x2"])
+@pytest.mark.parametrize("tuning", TUNINGS, ids=["h64", "h64_128_w3000", "h128_64_w1"])
+def test_tile_heights_and_splits_match_oracle(tuning, precision):
+    """Every launch tuning the autotuner may pick computes the same sums: the
+    half-height tiles (ragged row counts: 70 shells = 64 + 6, a 33-row class)
+    and extreme split-K targets stay within the bar."""
+    m = wl.random_mesh(77, 70, 12, 24, 14, r0=0.01)
+    m.shell_class, m.class_block = wl.random_merge(78, 70, 12, 24)
+    rho = wl.random_density(79, m.shape) + 0.5
+    got = run(m, rho, precision, tuning)
+    ref = oracle.solve(rho=rho, **m.oracle_kwargs())
+    ephi, eang = errors(m, rho, got, ref)
+    print(tuning, precision, "phi %.3e ang %.3e" % (ephi, eang))
+    assert ephi <= TOL and eang <= TOL, (ephi, eang)
+
+
+def test_tuned_production_l32_full():
+    """The benchmark workload under half-height tiles for both contractions."""
+    m, rho = wl.workload("production_l32")
+    got = run(m, rho, "bf16x3", {"moment_tile_m": 64, "expand_tile_m": 64})
+    ref = oracle.solve(rho=rho, **m.oracle_kwargs())
+    ephi, eang = errors(m, rho, got, ref)
+    assert ephi <= TOL and eang <= TOL, (ephi, eang)
