@@ -34,6 +34,10 @@ WORKLOADS = {
     # 64 uneven fields, one launch per phase, replayed from a HIP graph
     "batch64_bf16x3": ("batch64", "bf16x3"),
     "batch64_fp64": ("batch64", "fp64"),
+    # 2048 x 256 x 512, lmax 64: --steps consecutive solves (1000 for the full
+    # run) on a rotating density, density update + solve per step, one HIP graph
+    "large_fp16x2": ("large", "fp16x2"),
+    "large_bf16x3": ("large", "bf16x3"),
 }
 DEFAULT = "production_l32_bf16x3"
 
@@ -95,6 +99,27 @@ def copy_calibration(mib):
     print("copy calibration: 5 copies of %d MiB" % mib, flush=True)
 
 
+def roofline(plan, phases, precision, workload):
+    """Roofline position of the dominant contraction from the plan's per-phase
+    HIP event timings: algorithmic flops of one launch / its mean duration
+    against the MFMA peak of the arithmetic type."""
+    mflops, eflops, _ = plan.work()
+    dom = max(("moment", "expand"), key=lambda k: phases[k][0])
+    dom_ms = phases[dom][0] / max(phases[dom][1], 1)
+    flops = mflops if dom == "moment" else eflops
+    peak, punit = PEAK[DTYPE[precision]]
+    achieved = flops / (dom_ms * 1e-3)
+    # executed MFMA work: the split precisions run `products` narrow products per
+    # algorithmic multiply-add, over padded tiles
+    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
+    return {"bound": "mfma", "kernel": kernel_name(precision, dom),
+            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
+            "traffic": measured_traffic(workload, dom), "launch_ms": dom_ms,
+            "algorithmic_flops_per_launch": flops, "narrow_products_per_madd": products,
+            "executed_frac_lower_bound": achieved * products / peak,
+            "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -113,6 +138,8 @@ def main():
     key, precision = WORKLOADS[args.workload]
     if key == "batch64":
         return bench_batch(args, precision)
+    if key == "large":
+        return bench_large(args, precision)
     mesh, rho_h = wl.workload(key)
     dev = torch.device("cuda:0")
     print("bench: workload %s %dx%dx%d lmax %d precision %s" % (args.workload, mesh.nr, mesh.ntheta, mesh.nphi,
@@ -179,22 +206,8 @@ def main():
 
     cell_modes = float(mesh.ncells) * mesh.nmodes
     value = cell_modes / (ms * 1e-3)
-    mflops, eflops, min_bytes = plan.work()
-    dom = max(("moment", "expand"), key=lambda k: phases[k][0])
-    dom_ms = phases[dom][0] / max(phases[dom][1], 1)
-    flops = mflops if dom == "moment" else eflops
+    roof = roofline(plan, phases, precision, args.workload)
     dtype = DTYPE[precision]
-    peak, punit = PEAK[dtype]
-    achieved = flops / (dom_ms * 1e-3)
-    # executed MFMA work: the split precisions run `products` narrow products per
-    # algorithmic multiply-add, over padded tiles
-    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
-    roof = {"bound": "mfma", "kernel": kernel_name(precision, dom),
-            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
-            "traffic": measured_traffic(args.workload, dom), "launch_ms": dom_ms,
-            "algorithmic_flops_per_launch": flops, "narrow_products_per_madd": products,
-            "executed_frac_lower_bound": achieved * products / peak,
-            "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
 
     result = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -238,6 +251,130 @@ def _tuning_summary(tunings):
         vals, counts = np.unique([t[k] for t in tunings], return_counts=True)
         out[k] = {str(int(v)): int(c) for v, c in zip(vals, counts)}
     return out
+
+
+def bench_large(args, precision):
+    """Repeated solve on a large mesh: args.steps steps, each a density update
+    (the l <= 8 perturbation rotated by the next seeded rotation, written on the
+    device) and one solve, all captured in one HIP graph, with a copy of the
+    potential kept every 100th step.  After the timed replay each kept
+    potential is compared with the FP64 GPU solve of the same step's density."""
+    import torch
+    from paper_2602_02507_amd import devicegen, mpole
+    from paper_2602_02507_amd import workloads as wl
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    mesh = wl.large_mesh()
+    steps = args.steps
+    every = min(100, steps)
+    log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+    log("large workload %dx%dx%d lmax %d %s, %d steps" % (mesh.nr, mesh.ntheta, mesh.nphi, mesh.lmax, precision,
+                                                          steps))
+    coef = wl.real_ylm_coeffs(wl.LARGE_LPERT, wl.LARGE_SEED)
+    gen = devicegen.RotatedDensity(mesh, coef, wl.rotation_sequence(steps), wl.LARGE_EPS, device=dev)
+    rho = torch.empty(mesh.shape, dtype=torch.float64, device=dev)
+    phi = torch.empty_like(rho)
+    tuning, tune_s = None, 0.0
+    if not args.no_tune:
+        from paper_2602_02507_amd import tune
+        t0 = time.perf_counter()
+        tuning = tune.tune_plan(mesh, precision, dev, log=log)
+        tune_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = mpole.Plan.from_mesh(mesh, precision=precision, device=dev, tuning=tuning)
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t0)
+    log("plan built in %.0f ms (workspace %.2f GB)" % (plan_ms, plan.workspace_bytes / 1e9))
+    snaps = [torch.empty_like(rho) for _ in range(steps // every)]
+
+    # density generator alone, and the per-phase split of an eager solve
+    gen.write(rho, 0)
+    for _ in range(max(args.warmup, 1)):
+        plan.solve_into(rho, phi=phi)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for t in range(10):
+        gen.write(rho, t)
+    b.record(stream)
+    torch.cuda.synchronize()
+    density_ms = a.elapsed_time(b) / 10
+    gen.write(rho, 0)
+    plan.set_timing(True)
+    plan.phase_ms()
+    for _ in range(3):
+        plan.solve_into(rho, phi=phi)
+    torch.cuda.synchronize()
+    phases = plan.phase_ms()
+    plan.set_timing(False)
+
+    # one graph of `steps` consecutive steps
+    t0 = time.perf_counter()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for t in range(1, steps + 1):
+                gen.write(rho, t)
+                plan.solve_into(rho, phi=phi)
+                if t % every == 0:
+                    snaps[t // every - 1].copy_(phi)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    log("captured %d steps in %.1f s" % (steps, time.perf_counter() - t0))
+    a.record(stream)
+    g.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b)
+    solve_ms = graph_ms / steps - density_ms
+    log("graph %.1f ms: %.3f ms/step, density %.3f ms, solve %.3f ms" % (graph_ms, graph_ms / steps, density_ms,
+                                                                         solve_ms))
+    cell_modes = float(mesh.ncells) * mesh.nmodes
+    mflops, eflops, min_bytes = plan.work()
+    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
+    roof = roofline(plan, phases, precision, args.workload)
+    result = {"metric": METRIC, "value": cell_modes / (solve_ms * 1e-3), "unit": UNIT, "n_gpus": 1,
+              "steps": steps, "warmup": args.warmup, "ms_per_step": graph_ms / steps, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[precision], "data": "synthetic",
+              "config": {"workload": args.workload, "nr": mesh.nr, "ntheta": mesh.ntheta, "nphi": mesh.nphi,
+                         "lmax": mesh.lmax, "precision": precision, "hip_graph": True, "solves_per_graph": steps},
+              "roofline": roof, "graph_ms": graph_ms, "density_update_ms": density_ms, "solve_ms": solve_ms,
+              "solve_tflops_algorithmic": (mflops + eflops) / (solve_ms * 1e-3) / 1e12,
+              "solve_tflops_executed_lower_bound": products * (mflops + eflops) / (solve_ms * 1e-3) / 1e12,
+              "solve_min_hbm_gbs": min_bytes / (solve_ms * 1e-3) / 1e9,
+              "plan_ms": plan_ms, "tuning": plan.tuning(), "autotuned": not args.no_tune, "tune_s": tune_s}
+    # error against the FP64 GPU path every `every` steps
+    if not args.no_fp64:
+        p64 = mpole.Plan.from_mesh(mesh, precision="fp64", device=dev)
+        errs = {}
+        for k, snap in enumerate(snaps):
+            t = (k + 1) * every
+            gen.write(rho, t)
+            ref = p64.solve(rho, ang=False, interior=False, exterior=False)["phi"]
+            torch.cuda.synchronize()
+            errs[t] = float((snap - ref).abs().div(ref.abs()).max())
+            log("step %d: max rel err vs FP64 %.3e" % (t, errs[t]))
+            del ref
+        result["max_rel_err_vs_fp64_gpu_by_step"] = errs
+        result["max_rel_err_vs_fp64_gpu"] = max(errs.values()) if errs else None
+        del p64
+    if not args.no_cpu_baseline:
+        import oracle
+        # bounded sample: the oracle on the 40 innermost shells of the same
+        # angular mesh and lmax (merged like the full mesh), one solve
+        sub = wl.large_mesh(nr=40)
+        sub.shell_class, sub.class_block = wl.production_merge(40, mesh.ntheta, mesh.nphi, inner_shells=32)
+        rho_s = np.ascontiguousarray(wl.radial_profile(sub)[:, None, None]
+                                     * wl.rotated_angular_factor(sub, np.eye(3), coef)[None])
+        ref = oracle.solve(rho=rho_s, **sub.oracle_kwargs())
+        result["cpu_baseline"] = {"value": float(sub.ncells) * sub.nmodes / ref["seconds"][1], "unit": UNIT,
+                                  "cores": oracle.threads(), "kind": "oracle",
+                                  "sample": "one oracle solve of the 40 innermost shells of the same angular mesh and "
+                                            "lmax (tables %.1f s excluded; solve %.1f s)" % tuple(ref["seconds"])}
+    print(json.dumps(result), flush=True)
 
 
 def bench_batch(args, precision):

@@ -1,5 +1,7 @@
-"""Compile the gfx950 HIP library (C ABI of include/mpole.h) into
-paper_2602_02507_amd/_lib/libmpole.so with hipcc."""
+"""Compile the gfx950 HIP libraries with hipcc: the multipole solver (C ABI of
+include/mpole.h) into paper_2602_02507_amd/_lib/libmpole.so, and the device
+input generator of the repeated-solve workload (include/mpole_workload.h)
+into paper_2602_02507_amd/_lib/libmpole_workload.so."""
 import os
 import subprocess
 import sys
@@ -10,6 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libmpole.so")
 SOURCES = ["plan.cpp", "tables.hip", "pack.hip", "gemm_f64.hip", "scan.hip", "split.hip", "gemm_split.hip"]
+WL_LIB = os.path.join(LIBDIR, "libmpole_workload.so")
+WL_SOURCES = ["rotated_density.hip"]
 ARCH = "gfx950"
 
 
@@ -26,7 +30,7 @@ def build(verbose=False, jobs=8):
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
     procs, objs = [], []
-    for src in SOURCES:
+    for src in SOURCES + WL_SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc()] + flags + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -46,12 +50,14 @@ def build(verbose=False, jobs=8):
             print("\n".join(lines))
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    for lib, srcs in ((LIB, SOURCES), (WL_LIB, WL_SOURCES)):
+        tmp = lib + ".tmp%d" % os.getpid()
+        lobjs = [o for o, src in zip(objs, SOURCES + WL_SOURCES) if src in srcs]
+        cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + lobjs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, lib)
     return LIB
 
 

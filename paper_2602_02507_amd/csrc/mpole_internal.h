@@ -12,6 +12,8 @@ constexpr int kGaussNodes = 16;   // Gauss-Legendre points per theta sub-interva
 // step of the contraction kernels (16 for both the f64 and the split kernels)
 constexpr int kPadF64 = 16;
 constexpr int kPackSpan = 1024;   // blocks of one shell per packing workgroup
+constexpr int kTsumChunks = 64;   // block chunks of the bind-time column sums of a table
+constexpr int kShiftSamples = 4;  // blocks sampled per shell for its mean source density
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.
 struct GaussRule {
@@ -33,6 +35,8 @@ struct ClassDev {
   uint16_t *ppacks;      // [nplanes][nrows][nblocks_pad] split planes of the packed source
   double *pscale;        // [nrows] power-of-two row scales of the packed source
   double *partial;       // [splits][nrows][namp] split-K partial moments
+  double *wsum;          // [nblocks_pad] 4 pi G dOmega of each block (sum over its cells)
+  double *tsum;          // [namp] sum_b wsum[b] table[b][n], summed over b in order
   int32_t nrows, nblocks, nblocks_pad;
   int32_t splits, kchunk;             // moment split-K: splits x kchunk >= nblocks_pad
   int32_t m_tiles_mom, m_tiles_exp, n_tiles_mom, n_tiles_exp;   // tiles of the contractions
@@ -63,6 +67,8 @@ struct PlanDev {
   int32_t wg_mom, wg_exp;   // workgroups of the two contraction launches
   int32_t tm_mom, tm_exp;   // output tile heights of the two contractions
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
+  double *shift;            // [nr] per-shell mean source density removed before splitting (split precisions)
+  double *tsum_part;        // [kTsumChunks][namp] bind-time partial sums of tsum
 };
 
 // Phases of one solve; a launch of phase h covers the workgroups

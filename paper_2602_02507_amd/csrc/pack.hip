@@ -9,11 +9,13 @@
 // path whose loads are all issued before any is consumed, so enough bytes are
 // in flight to stream rho at HBM rate.  Output by precision:
 //   FP64      the packed row in FP64 (operand of the f64 moment contraction);
-//   BF16 x3   the split planes directly (bfloat16 has the exponent range of
-//             FP32, so the row needs no scaling), plus per-workgroup partial
-//             sums of the FP64 monopole moment sum_b P_b T_b0;
-//   FP16 x2   the FP64 row, per-workgroup partial maxima and monopole sums; a
-//             second kernel scales and splits once the row maximum is known.
+//   BF16 x3   the split planes of the deviation from the shell's mean
+//             (below; bfloat16 has the exponent range of FP32, so the row
+//             needs no scaling), plus per-workgroup partial sums of the FP64
+//             monopole moment sum_b P_b T_b0;
+//   FP16 x2   the FP64 deviation row, per-workgroup partial maxima and
+//             monopole sums; a second kernel scales and splits once the row
+//             maximum is known.
 #include <algorithm>
 
 #include "device_util.h"
@@ -41,7 +43,30 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   const double *__restrict__ src = rho + (size_t)i * P.ncell;
   const double *__restrict__ w = P.weight;
   const auto srcg = gmem(src), wg = gmem(w);
-  double s[PACK_UNROLL];
+  // Split precisions carry only the deviation of the source from c times the
+  // block weight, c a per-shell reference density (exact identity, l >= 1):
+  //   sum_b P_b T_bn = sum_b (P_b - c W_b) T_bn + c sum_b W_b T_bn,
+  // with W_b the block's 4 pi G dOmega; the last sum is a bind-time FP64
+  // constant (zero for l >= 1 up to quadrature error) added back by the
+  // reduction.  For a near-spherical source the deviation is a small
+  // fraction of P, and so are the rounding errors of the narrow operands and
+  // of the FP32 accumulation; any c keeps the sums exact.  c is the
+  // weight-averaged density of kShiftSamples cells at spread-out theta (phi
+  // index 0), read with uniform loads by every thread of every workgroup of
+  // the shell and combined in the same order, so all agree bitwise; the
+  // monopole sums below use P itself.
+  double shift = 0.0;
+  if (MODE != 0) {
+    double a = 0.0, wsm = 0.0;
+#pragma unroll
+    for (int k = 0; k < kShiftSamples; ++k) {
+      const int q = (int)(((2L * k + 1) * P.ntheta) / (2 * kShiftSamples)) * P.nphi;
+      a += wg[q] * srcg[q];
+      wsm += wg[q];
+    }
+    shift = wsm > 0.0 ? a / wsm : 0.0;   // stored at the end: no store ahead of the loads
+  }
+  double s[PACK_UNROLL], wb[PACK_UNROLL];   // block source and block weight
   if (C.rect != nullptr) {
     typedef int i4 __attribute__((ext_vector_type(4)));
     const auto rect = gmem(reinterpret_cast<const i4 *>(C.rect));   // (j0, k0, nj, nk) per block
@@ -54,20 +79,29 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int q = r[u].x * P.nphi + r[u].y;
-      s[u] = (r[u].z == 1 && r[u].w == 1) ? wg[q] * srcg[q] : 0.0;
+      const bool one = r[u].z == 1 && r[u].w == 1;
+      wb[u] = one ? wg[q] : 0.0;
+      s[u] = one ? wb[u] * srcg[q] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
-      if (b < C.nblocks && (r[u].z != 1 || r[u].w != 1)) s[u] = block_source(C, w, src, P.nphi, b);
+      if (b < C.nblocks && (r[u].z != 1 || r[u].w != 1)) {
+        s[u] = block_source(C, w, src, P.nphi, b);
+        wb[u] = gmem(C.wsum)[b];
+      }
     }
   } else {
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
       s[u] = (b < C.nblocks) ? block_source(C, w, src, P.nphi, b) : 0.0;
+      wb[u] = (b < C.nblocks && MODE != 0) ? gmem(C.wsum)[b] : 0.0;
     }
   }
+  double dev[PACK_UNROLL];
+#pragma unroll
+  for (int u = 0; u < PACK_UNROLL; ++u) dev[u] = MODE != 0 ? s[u] - shift * wb[u] : s[u];
   double mono = 0.0, mx = 0.0;
   if (MODE == kSplitBf16x3) {
     // split into an LDS copy of this workgroup's 64 k-slab groups of 16
@@ -77,7 +111,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int bl = threadIdx.x + u * PACK_THREADS;   // block within this workgroup
       const int b = b0 + u * PACK_THREADS;
-      split_store<kSplitBf16x3>(b < C.nblocks ? s[u] : 0.0, &stage[bl >> 4][0][bl & 15], 16);
+      split_store<kSplitBf16x3>(b < C.nblocks ? dev[u] : 0.0, &stage[bl >> 4][0][bl & 15], 16);
     }
     __syncthreads();
     const int g0 = bx * (PACK_SPAN / 16);                        // first k slab of the workgroup
@@ -94,13 +128,14 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   for (int u = 0; u < PACK_UNROLL; ++u) {
     const int b = b0 + u * PACK_THREADS;
     if (b >= C.nblocks) continue;
-    if (MODE != kSplitBf16x3) gmem(C.pack)[(size_t)row * C.nblocks_pad + b] = s[u];
+    if (MODE != kSplitBf16x3) gmem(C.pack)[(size_t)row * C.nblocks_pad + b] = dev[u];
     if (MODE != 0) {
       mono += s[u] * gmem(C.tcol0)[b];
-      mx = fmax(mx, fabs(s[u]));
+      mx = fmax(mx, fabs(dev[u]));
     }
   }
   if (MODE != 0) {
+    if (bx == 0 && threadIdx.x == 0) gmem(P.shift)[i] = shift;
     mono = block_sum(mono, red);
     if (MODE == kSplitFp16x2) mx = block_max(mx, red);
     if (threadIdx.x == 0) {

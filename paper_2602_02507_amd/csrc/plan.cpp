@@ -77,7 +77,7 @@ struct ClassHost {
   int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
   int m_tiles_mom = 0, m_tiles_exp = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
   size_t off_rows = 0, off_moff = 0, off_mem = 0, off_table = 0, off_pack = 0, off_partial = 0;
-  size_t off_tplanes = 0, off_ttplanes = 0, off_ppacks = 0, off_pscale = 0, off_tcol0 = 0;
+  size_t off_tplanes = 0, off_ttplanes = 0, off_ppacks = 0, off_pscale = 0, off_tcol0 = 0, off_wsum = 0, off_tsum = 0;
 };
 
 // planes of a split precision (0 for FP64)
@@ -98,6 +98,7 @@ struct mpole_plan_t {
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
+  size_t off_shift = 0, off_tsum_part = 0;
   int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
   size_t off_plandev = 0, off_prefix = 0;
   int wg_mom = 0, wg_exp = 0;
@@ -342,6 +343,8 @@ void layout_plan(mpole_plan_t *p, int target) {
   }
   p->off_mono = take(sizeof(double) * (size_t)p->nr * p->mono_stride);
   p->off_max = take(sizeof(double) * (size_t)p->nr * p->mono_stride);
+  p->off_shift = take(sizeof(double) * (size_t)p->nr);
+  p->off_tsum_part = take(sizeof(double) * (size_t)kTsumChunks * p->namp);
   for (auto &C : p->cls) {
     const size_t nrows = C.rows.size();
     C.off_rows = take(sizeof(int32_t) * std::max<size_t>(nrows, 1));
@@ -350,6 +353,8 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_rect = take(sizeof(int32_t) * C.rect.size());
     C.off_table = take(sizeof(double) * (size_t)C.nblocks_pad * p->namp);
     C.off_tcol0 = take(sizeof(double) * (size_t)C.nblocks_pad);
+    C.off_wsum = take(sizeof(double) * (size_t)C.nblocks_pad);
+    C.off_tsum = take(sizeof(double) * (size_t)p->namp);
     C.off_pack = take(sizeof(double) * nrows * C.nblocks_pad);
     // split-K partials: FP64 for the f64 kernel, FP32 (the accumulator type) for split precisions
     C.off_partial = take((p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp);
@@ -486,6 +491,8 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   D.mono_part = p->nplanes ? (double *)(ws + p->off_mono) : nullptr;
   D.max_part = (double *)(ws + p->off_max);
   D.mono_stride = p->mono_stride;
+  D.shift = (double *)(ws + p->off_shift);
+  D.tsum_part = (double *)(ws + p->off_tsum_part);
   p->cdev.assign(p->ncls, ClassDev{});
   for (int c = 0; c < p->ncls; ++c) {
     const ClassHost &H = p->cls[c];
@@ -496,6 +503,8 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     C.rect = H.rect.empty() ? nullptr : (const int4 *)(ws + H.off_rect);
     C.table = (double *)(ws + H.off_table);
     C.tcol0 = (double *)(ws + H.off_tcol0);
+    C.wsum = (double *)(ws + H.off_wsum);
+    C.tsum = (double *)(ws + H.off_tsum);
     C.pack = (double *)(ws + H.off_pack);
     C.partial = (double *)(ws + H.off_partial);
     C.tplanes = (uint16_t *)(ws + H.off_tplanes);

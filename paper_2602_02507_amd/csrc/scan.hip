@@ -2,7 +2,9 @@
 // recurrences after Eq. Solution):
 //
 //   k_reduce  angular moments A[i][n] = fixed-order sum of the split-K
-//             partials of the moment contraction
+//             partials of the moment contraction (split precisions: plus the
+//             FP64 term of the mean source density the packing removed, and
+//             the FP64 monopole from the packing kernel)
 //   k_scan    regular moments by outward integration, M^R_0 = 0,
 //             M^R_{i+1} = M^R_i + JR_l(i) A[i][n]; irregular moments by
 //             inward integration, M^I_nr = 0, M^I_i = M^I_{i+1} + JI_l(i) A[i][n];
@@ -46,6 +48,8 @@ __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
   } else {
     const auto src = gmem(reinterpret_cast<const float *>(C.partial)) + off;   // FP32 partials
     for (int q = 0; q < C.splits; ++q) s += (double)src[q * stride];
+    // the mean source density removed by the packing, times the column sum
+    s += gmem(P.shift)[i] * gmem(C.tsum)[n];
   }
   gmem(P.ang)[(size_t)i * P.namp + n] = s;
   if (ang_out != nullptr && n < P.nam) ang_out[(size_t)i * P.nam + n] = s;

@@ -125,6 +125,38 @@ __global__ void k_block_table(PlanDev P, ClassDev C) {
   if (n == 0) C.tcol0[b] = v;
 }
 
+// 4 pi G dOmega of each block: the cell weights of its members, in CSR order.
+__global__ void k_block_wsum(PlanDev P, ClassDev C) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= C.nblocks) return;
+  double w = 0.0;
+  for (int e = C.moff[b]; e < C.moff[b + 1]; ++e) w += P.weight[C.mem[e]];
+  C.wsum[b] = w;
+}
+
+// Column sums tsum[n] = sum_b wsum[b] table[b][n] (the integral of each
+// kernel over the sphere, 4 pi G sqrt(4 pi) for n = 0 and 0 otherwise up to
+// quadrature error), in two fixed-order passes: kTsumChunks contiguous block
+// ranges, then the chunk totals in chunk order.
+__global__ void k_tsum_part(PlanDev P, ClassDev C) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= P.namp) return;
+  const int ch = blockIdx.y;
+  const int span = (C.nblocks + kTsumChunks - 1) / kTsumChunks;
+  const int b0 = ch * span, b1 = min(C.nblocks, b0 + span);
+  double s = 0.0;
+  for (int b = b0; b < b1; ++b) s += C.wsum[b] * C.table[(size_t)b * P.namp + n];
+  P.tsum_part[(size_t)ch * P.namp + n] = s;
+}
+
+__global__ void k_tsum_final(PlanDev P, ClassDev C) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= P.namp) return;
+  double s = 0.0;
+  for (int ch = 0; ch < kTsumChunks; ++ch) s += P.tsum_part[(size_t)ch * P.namp + n];
+  C.tsum[n] = s;
+}
+
 // b^p - a^p for 0 < a < b without cancellation for thin shells
 __device__ double pow_span(double a, double b, double p) {
   const double lr = log1p((b - a) / a);
@@ -196,6 +228,9 @@ hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const G
   for (int c = 0; c < P.nclasses; ++c) {
     const ClassDev &C = host_classes[c];
     hipLaunchKernelGGL(k_block_table, dim3(grid_for((long)C.nblocks_pad * P.namp, 256)), dim3(256), 0, s, P, C);
+    hipLaunchKernelGGL(k_block_wsum, dim3(grid_for(C.nblocks, 256)), dim3(256), 0, s, P, C);
+    hipLaunchKernelGGL(k_tsum_part, dim3(grid_for(P.namp, 256), kTsumChunks), dim3(256), 0, s, P, C);
+    hipLaunchKernelGGL(k_tsum_final, dim3(grid_for(P.namp, 256)), dim3(256), 0, s, P, C);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -265,6 +265,68 @@ def batch_densities(meshes, seed0=4000):
     return [production_density(m, seed=seed0 + f) for f, m in enumerate(meshes)]
 
 
+def large_mesh(nr=2048, ntheta=256, nphi=512, lmax=64):
+    """Mesh of the repeated-solve workload: log-spaced shells on [1e-3, 1],
+    uniform angles, the production coarsening rule."""
+    mesh = Mesh(log_edges(1e-3, 1.0, nr), uniform_edges(0.0, np.pi, ntheta), uniform_edges(0.0, 2 * np.pi, nphi),
+                lmax, name="large")
+    mesh.shell_class, mesh.class_block = production_merge(nr, ntheta, nphi)
+    return mesh
+
+
+LARGE_LPERT, LARGE_SEED, LARGE_EPS, LARGE_RC, LARGE_MAX_ANGLE = 8, 5, 0.01, 0.05, 0.05
+
+
+def radial_profile(mesh, rc=0.05):
+    r = 0.5 * (mesh.r_edges[:-1] + mesh.r_edges[1:])
+    return np.ascontiguousarray((1.0 + (r / rc) ** 2) ** -1.5)
+
+
+def axis_angle(axis, angle):
+    """Rotation matrix by `angle` about the unit vector `axis` (Rodrigues)."""
+    x, y, z = axis
+    K = np.array([[0.0, -z, y], [z, 0.0, -x], [-y, x, 0.0]])
+    return np.eye(3) + np.sin(angle) * K + (1.0 - np.cos(angle)) * (K @ K)
+
+
+def rotation_sequence(nsteps, seed=LARGE_SEED, max_angle=LARGE_MAX_ANGLE):
+    """R_0 = I and R_t = Q_t R_{t-1} for t = 1..nsteps, Q_t a rotation by an
+    angle ~ U[0, max_angle] about an axis uniform on the sphere (normalised
+    Gaussian triple), all drawn from one seeded generator in step order.
+    Returns [nsteps+1][3][3]."""
+    rng = np.random.default_rng(seed + 1)
+    R = np.eye(3)
+    out = [R]
+    for _ in range(nsteps):
+        a = rng.standard_normal(3)
+        a /= np.linalg.norm(a)
+        R = axis_angle(a, rng.uniform(0.0, max_angle)) @ R
+        out.append(R)
+    return np.ascontiguousarray(np.array(out))
+
+
+def perturbation_at(theta, phi, coeffs, lmax):
+    """sum_n coeffs[n] Y_n(theta, phi) at arbitrary points (arrays of one shape)."""
+    s = np.zeros_like(theta, dtype=np.float64)
+    for c, (l, m, a) in zip(coeffs, _modes(lmax)):
+        s += c * real_ylm(l, m, a, theta, phi)
+    return s
+
+
+def rotated_angular_factor(mesh, R, coeffs, lpert=LARGE_LPERT, eps=LARGE_EPS):
+    """Host value of 1 + eps * perturbation(R^T u) at every cell centre
+    direction u, [ntheta][nphi] (the angular factor of the repeated-solve
+    density at rotation R)."""
+    th = 0.5 * (mesh.theta_edges[:-1] + mesh.theta_edges[1:])
+    ph = 0.5 * (mesh.phi_edges[:-1] + mesh.phi_edges[1:])
+    tt, pp = np.meshgrid(th, ph, indexing="ij")
+    u = np.stack([np.sin(tt) * np.cos(pp), np.sin(tt) * np.sin(pp), np.cos(tt)], axis=-1)
+    v = u @ R          # rows of u times R = (R^T u)^T
+    t2 = np.arccos(np.clip(v[..., 2], -1.0, 1.0))
+    p2 = np.arctan2(v[..., 1], v[..., 0])
+    return 1.0 + eps * perturbation_at(t2, p2, coeffs, lpert)
+
+
 def workload(name):
     """(mesh, rho) of a named workload."""
     if name == "spheroid":

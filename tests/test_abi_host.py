@@ -126,3 +126,18 @@ def test_split_chunk_cap_bounds_accumulation_chains():
     n_tiles = (289 + 127) // 128
     assert b.moment_wgs >= 4 * n_tiles * -(-outer_blocks // 2048)
     assert f.moment_wgs == -(-480 // 64) * 5 + 1 * 5   # FP64: one split per 64 x 64 tile
+
+
+def test_workload_library_exports_its_header():
+    from paper_2602_02507_amd import devicegen
+    text = open(os.path.join(os.path.dirname(HEADER), "mpole_workload.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(mpole_[a-z_0-9]+)\s*\(", text))
+    assert names == {"mpole_wl_rotated_density"}
+    L = devicegen.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # invalid arguments are rejected before any launch (no GPU touched)
+    assert L.mpole_wl_rotated_density(0, 1, 1, 1, 1, 1, 0, 1, 0.0, 1, 1, None) == 1
+    assert L.mpole_wl_rotated_density(1, 1, 1, 1, 1, 1, 17, 1, 0.0, 1, 1, None) == 1
+    assert L.mpole_wl_rotated_density(1, 1, 1, None, 1, 1, 0, 1, 0.0, 1, 1, None) == 1
