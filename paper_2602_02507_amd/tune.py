@@ -18,7 +18,7 @@ candidates are timed on a constant density.
 For a batch, each field's tile heights come from tuning that field alone;
 the moment targets, which matter for how the fields share the GPU, are then
 chosen by timing the whole batch at a few multiples of each field's share of
-one round of resident workgroups.
+one round of resident workgroups (cached per device and set of field shapes).
 """
 import json
 import os
@@ -72,8 +72,11 @@ def shape_key(mesh, precision, device_name):
 
 
 def _device_name(device):
+    """Architecture and compute-unit count of the device (stable key part)."""
     import torch
-    return torch.cuda.get_device_name(device).replace("|", "/")
+    p = torch.cuda.get_device_properties(device)
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return ("%s/%dcu" % (arch.split(":")[0], p.multi_processor_count)).replace("|", "/")
 
 
 def candidates(precision):
@@ -174,27 +177,37 @@ def tune_batch(meshes, precision="bf16x3", device="cuda", rho=None, warmup=1, re
         dev = torch.device(dev.type, torch.cuda.current_device())
     t0 = time.perf_counter()
     cache = load_cache()
-    n_before = len(cache)
+    n_before = sum(1 for k in cache if not k.startswith("batch|"))
     tiles = [tune_plan(m, precision, dev, warmup, reps, cache=cache, log=log) for m in meshes]
     save_cache(cache)
     t_fields = time.perf_counter() - t0
     if rho is None:
         rho = [torch.ones((m.nr, m.ntheta, m.nphi), dtype=torch.float64, device=dev) for m in meshes]
-    # default shares of the moment workgroups, read back from a host batch
+    # default shares of the moment workgroups (as the library computes them)
     shares = _default_shares(meshes, precision)
-    best, best_ms, trials = None, float("inf"), []
-    for mult in (1, 2, 4):
-        tun = [{"moment_wgs": max(1, int(round(mult * s))), "moment_tile_m": t["moment_tile_m"],
-                "expand_tile_m": t["expand_tile_m"]} for s, t in zip(shares, tiles)]
-        ms = _time_batch(meshes, precision, rho, dev, tun, warmup, reps)
-        trials.append((mult, ms))
-        if log:
-            log("tune batch: moment share x%d -> %.3f ms" % (mult, ms))
-        if ms < best_ms:
-            best, best_ms = tun, ms
-    info = {"field_shapes_tuned": len(cache) - n_before, "field_shapes": len(meshes),
-            "field_tuning_s": t_fields, "batch_trials_ms": trials, "seconds": time.perf_counter() - t0,
-            "cache": cache_path()}
+    import hashlib
+    bkey = "batch|%s|%s|%s" % (_device_name(dev), precision, hashlib.sha1(
+        "\n".join(shape_key(m, precision, "") for m in meshes).encode()).hexdigest()[:16])
+    make = lambda mult: [{"moment_wgs": max(1, int(round(mult * s))), "moment_tile_m": t["moment_tile_m"],
+                          "expand_tile_m": t["expand_tile_m"]} for s, t in zip(shares, tiles)]
+    trials = []
+    if bkey in cache:
+        best = make(cache[bkey]["mult"])
+    else:
+        best_mult, best_ms = None, float("inf")
+        for mult in (1, 2, 4):
+            ms = _time_batch(meshes, precision, rho, dev, make(mult), warmup, reps)
+            trials.append((mult, ms))
+            if log:
+                log("tune batch: moment share x%d -> %.3f ms" % (mult, ms))
+            if ms < best_ms:
+                best_mult, best_ms = mult, ms
+        best = make(best_mult)
+        cache[bkey] = {"mult": best_mult, "batch_ms": best_ms, "trials_ms": trials}
+        save_cache(cache)
+    info = {"field_shapes_tuned": sum(1 for k in cache if not k.startswith("batch|")) - n_before,
+            "field_shapes": len(meshes), "field_tuning_s": t_fields, "batch_trials_ms": trials,
+            "seconds": time.perf_counter() - t0, "cache": cache_path()}
     return best, info
 
 
