@@ -11,6 +11,16 @@
 // wave owning a 32 x 32 corner as 2 x 2 MFMA 16x16 tiles; K advances 16 per
 // LDS stage, double-buffered with register prefetch of the next stage.
 //
+// LDS layouts are chosen so that neither the stores of a stage nor the MFMA
+// operand reads conflict on banks (8-byte accesses are served 16 lanes at a
+// time over 128 bytes of banks): an operand whose rows are loaded with k
+// contiguous is kept row-major with a pitch of BK + 1 doubles (16 lanes
+// reading one k of 16 rows hit 16 distinct bank pairs, and a thread's 4
+// consecutive k land in distinct banks from its 15 neighbours'); the moment
+// table, loaded with n contiguous, is kept k-major and each lane loads and
+// stores the n columns 16 apart, so 16 lanes always touch 128 contiguous
+// bytes.
+//
 // The moment contraction is skinny (M = shells, N = modes, K = blocks up to
 // ~1e5), so K is split across workgroups; each split writes its own FP64
 // partial and a separate pass sums them in a fixed order (deterministic, no
@@ -28,18 +38,27 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, NTHREADS = 256;
-constexpr int LDS_LD = BM + 4;  // row stride of an LDS stage, in doubles
+constexpr int RK = BK + 1;      // pitch of a row-major [row][k] stage, in doubles
+constexpr int KR = BM + 4;      // pitch of a k-major [k][row] stage, in doubles
+constexpr int STAGE = BM * RK;  // doubles per stage (both layouts)
+static_assert(BK * KR == STAGE, "stage sizes");
 
-__device__ inline void mfma_stage(const double (*As)[LDS_LD], const double (*Bs)[LDS_LD], int wm, int wn,
-                                  int lane, d4 acc[2][2]) {
+// Element (row, k) of a stage in either layout.
+template <bool ROWMAJOR>
+__device__ inline double lds_at(const double *S, int row, int k) {
+  return ROWMAJOR ? S[row * RK + k] : S[k * KR + row];
+}
+
+template <bool A_ROWMAJOR, bool B_ROWMAJOR>
+__device__ inline void mfma_stage(const double *As, const double *Bs, int wm, int wn, int lane, d4 acc[2][2]) {
 #pragma unroll
   for (int kk = 0; kk < BK / 4; ++kk) {
     const int kr = kk * 4 + (lane >> 4);
     const int c = lane & 15;
-    const double a0 = As[kr][wm * 32 + c];
-    const double a1 = As[kr][wm * 32 + 16 + c];
-    const double b0 = Bs[kr][wn * 32 + c];
-    const double b1 = Bs[kr][wn * 32 + 16 + c];
+    const double a0 = lds_at<A_ROWMAJOR>(As, wm * 32 + c, kr);
+    const double a1 = lds_at<A_ROWMAJOR>(As, wm * 32 + 16 + c, kr);
+    const double b0 = lds_at<B_ROWMAJOR>(Bs, wn * 32 + c, kr);
+    const double b1 = lds_at<B_ROWMAJOR>(Bs, wn * 32 + 16 + c, kr);
     acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
     acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
     acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -59,8 +78,8 @@ __device__ inline void load4(const double *p, double v[4]) {
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
-  __shared__ double As[2][BK][LDS_LD];
-  __shared__ double Bs[2][BK][LDS_LD];
+  __shared__ double As[2][STAGE];   // packed source, [row][k]
+  __shared__ double Bs[2][STAGE];   // table, [k][n]
   const Job J = job_of(B, PH_MOMENT, xcd_remap(blockIdx.x, gridDim.x));
   const PlanDev &P = J.P;
   int c = 0;
@@ -80,13 +99,17 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
-  // loader roles: A rows (k contiguous) and B rows (n contiguous)
+  // loader roles: A rows (4 consecutive k of row ar); B row bk, columns
+  // bn + 16 e (e < 4).  namp is a multiple of 16, so the column test is
+  // uniform over each group of 16 lanes.
   const int ar = tid >> 2, ak = (tid & 3) * 4;
-  const int bk = tid >> 4, bn = (tid & 15) * 4;
+  const int bk = tid >> 4, bn = tid & 15;
   const bool a_ok = (m0 + ar) < nrows;
-  const bool b_ok = (n0 + bn) < namp;
+  bool b_ok[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) b_ok[e] = (n0 + bn + 16 * e) < namp;
   const double *abase = Pk + (size_t)(a_ok ? m0 + ar : 0) * ldp + ak;
-  const double *bbase = T + (size_t)bk * namp + (b_ok ? n0 + bn : 0);
+  const auto bbase = gmem(T) + (size_t)bk * namp;
 
   d4 acc[2][2];
 #pragma unroll
@@ -95,14 +118,21 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
     for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
 
   double av[4], bv[4];
+  auto load_b = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bv[e] = bbase[(size_t)k * namp + (b_ok[e] ? n0 + bn + 16 * e : 0)];
+  };
+  auto store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) As[buf][ar * RK + ak + e] = a_ok ? av[e] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Bs[buf][bk * KR + bn + 16 * e] = b_ok[e] ? bv[e] : 0.0;
+  };
   const int nk = (kend - kbeg) / BK;
   if (nk > 0) {
     load4(abase + kbeg, av);
-    load4(bbase + (size_t)kbeg * namp, bv);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) As[0][ak + e][ar] = a_ok ? av[e] : 0.0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) Bs[0][bk][bn + e] = b_ok ? bv[e] : 0.0;
+    load_b(kbeg);
+    store(0);
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
@@ -111,15 +141,10 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
     if (more) {
       const int k = kbeg + (kt + 1) * BK;
       load4(abase + k, av);
-      load4(bbase + (size_t)k * namp, bv);
+      load_b(k);
     }
-    mfma_stage(As[cur], Bs[cur], wm, wn, lane, acc);
-    if (more) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) As[cur ^ 1][ak + e][ar] = a_ok ? av[e] : 0.0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][bk][bn + e] = b_ok ? bv[e] : 0.0;
-    }
+    mfma_stage<true, false>(As[cur], Bs[cur], wm, wn, lane, acc);
+    if (more) store(cur ^ 1);
     __syncthreads();
   }
 
@@ -137,8 +162,8 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
-  __shared__ double As[2][BK][LDS_LD];
-  __shared__ double Bs[2][BK][LDS_LD];
+  __shared__ double As[2][STAGE];   // coefficients, [shell row][k]
+  __shared__ double Bs[2][STAGE];   // table, [block][k]
   const Job J = job_of(B, PH_EXPAND, xcd_remap(blockIdx.x, gridDim.x));
   const PlanDev &P = J.P;
   double *__restrict__ phi = J.io.phi;
@@ -174,9 +199,9 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
   load4(arow + lk, av);
   load4(brow + lk, bv);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) As[0][lk + e][lr] = a_ok ? av[e] : 0.0;
+  for (int e = 0; e < 4; ++e) As[0][lr * RK + lk + e] = a_ok ? av[e] : 0.0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) Bs[0][lk + e][lr] = b_ok ? bv[e] : 0.0;
+  for (int e = 0; e < 4; ++e) Bs[0][lr * RK + lk + e] = b_ok ? bv[e] : 0.0;
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
@@ -186,12 +211,12 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
       load4(arow + k + lk, av);
       load4(brow + k + lk, bv);
     }
-    mfma_stage(As[cur], Bs[cur], wm, wn, lane, acc);
+    mfma_stage<true, true>(As[cur], Bs[cur], wm, wn, lane, acc);
     if (more) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[cur ^ 1][lk + e][lr] = a_ok ? av[e] : 0.0;
+      for (int e = 0; e < 4; ++e) As[cur ^ 1][lr * RK + lk + e] = a_ok ? av[e] : 0.0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][lk + e][lr] = b_ok ? bv[e] : 0.0;
+      for (int e = 0; e < 4; ++e) Bs[cur ^ 1][lr * RK + lk + e] = b_ok ? bv[e] : 0.0;
     }
     __syncthreads();
   }

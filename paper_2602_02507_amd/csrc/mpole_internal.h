@@ -27,6 +27,7 @@ struct ClassDev {
   const int32_t *moff;   // [nblocks+1] CSR offsets of block members
   const int32_t *mem;    // [ncell] member fine-cell index j*nphi+k, ascending per block
   const int4 *rect;      // [nblocks] (j0, k0, nj, nk) when every block is a theta-phi rectangle, else null
+  const int32_t *span0;  // [ceil(nblocks / kPackSpan)] first cell of a packing span of consecutive single cells, else -1
   double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, zero padded
   double *tcol0;         // [nblocks_pad] copy of the table's l = 0 column (contiguous)
   uint16_t *tplanes;     // [nplanes][nblocks_pad][namp] split planes of table (expansion operand)

@@ -67,7 +67,18 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     shift = wsm > 0.0 ? a / wsm : 0.0;   // stored at the end: no store ahead of the loads
   }
   double s[PACK_UNROLL], wb[PACK_UNROLL];   // block source and block weight
-  if (C.rect != nullptr) {
+  const int run0 = ld_const(C.span0 + bx);
+  if (run0 >= 0) {
+    // the span is a run of single-cell blocks at consecutive cells: coalesced
+    // loads, no block descriptors
+#pragma unroll
+    for (int u = 0; u < PACK_UNROLL; ++u) {
+      const int b = b0 + u * PACK_THREADS;
+      const int q = run0 + threadIdx.x + u * PACK_THREADS;
+      wb[u] = (b < C.nblocks) ? wg[q] : 0.0;
+      s[u] = (b < C.nblocks) ? wb[u] * srcg[q] : 0.0;
+    }
+  } else if (C.rect != nullptr) {
     typedef int i4 __attribute__((ext_vector_type(4)));
     const auto rect = gmem(reinterpret_cast<const i4 *>(C.rect));   // (j0, k0, nj, nk) per block
     i4 r[PACK_UNROLL];

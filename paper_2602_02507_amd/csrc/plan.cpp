@@ -73,6 +73,8 @@ GaussRule make_gauss_rule() {
 struct ClassHost {
   std::vector<int32_t> rows, moff, mem;
   std::vector<int32_t> rect;  // 4 per block when every block is a rectangle in (j, k)
+  std::vector<int32_t> span0; // per packing span: first cell when the span is a run of single cells, else -1
+  size_t off_span0 = 0;
   size_t off_rect = 0;
   int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
   int m_tiles_mom = 0, m_tiles_exp = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
@@ -254,6 +256,18 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       C.rect[4 * b + 3] = k1 - k0 + 1;
     }
     if (!rect_ok) C.rect.clear();
+    // packing spans whose blocks are single cells at consecutive cell indices:
+    // span0[s] = cell of the span's first block, else -1
+    const int nspan = (nb + kPackSpan - 1) / kPackSpan;
+    C.span0.assign(nspan, -1);
+    for (int sp = 0; sp < nspan; ++sp) {
+      const int bb = sp * kPackSpan, be = std::min(nb, bb + kPackSpan);
+      const int first = C.mem[C.moff[bb]];
+      bool affine = true;
+      for (int b = bb; b < be && affine; ++b)
+        affine = C.moff[b + 1] - C.moff[b] == 1 && C.mem[C.moff[b]] == first + (b - bb);
+      if (affine) C.span0[sp] = first;
+    }
     C.n_tiles_mom = (p->namp + p->tile_n - 1) / p->tile_n;
     C.n_tiles_exp = (C.nblocks + p->tile_n - 1) / p->tile_n;
   }
@@ -351,6 +365,7 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_moff = take(sizeof(int32_t) * (C.nblocks + 1));
     C.off_mem = take(sizeof(int32_t) * p->ncell);
     C.off_rect = take(sizeof(int32_t) * C.rect.size());
+    C.off_span0 = take(sizeof(int32_t) * C.span0.size());
     C.off_table = take(sizeof(double) * (size_t)C.nblocks_pad * p->namp);
     C.off_tcol0 = take(sizeof(double) * (size_t)C.nblocks_pad);
     C.off_wsum = take(sizeof(double) * (size_t)C.nblocks_pad);
@@ -501,6 +516,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     C.moff = (const int32_t *)(ws + H.off_moff);
     C.mem = (const int32_t *)(ws + H.off_mem);
     C.rect = H.rect.empty() ? nullptr : (const int4 *)(ws + H.off_rect);
+    C.span0 = (const int32_t *)(ws + H.off_span0);
     C.table = (double *)(ws + H.off_table);
     C.tcol0 = (double *)(ws + H.off_tcol0);
     C.wsum = (double *)(ws + H.off_wsum);
@@ -538,6 +554,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     if (e == hipSuccess) e = upload(ws, H.off_moff, H.moff.data(), sizeof(int32_t) * H.moff.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_mem, H.mem.data(), sizeof(int32_t) * H.mem.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_rect, H.rect.data(), sizeof(int32_t) * H.rect.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_span0, H.span0.data(), sizeof(int32_t) * H.span0.size(), s);
   }
   // single-plan batch view: the device plan and its phase prefix sums
   p->prefix.assign(PH_COUNT * 2, 0);
