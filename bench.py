@@ -209,6 +209,19 @@ def main():
     roof = roofline(plan, phases, precision, args.workload)
     dtype = DTYPE[precision]
 
+    # the gradient of the potential for the gravitational sources (after the
+    # solve, not part of a step): HBM-bound, 8 B read + 24 B written per cell
+    grads = [torch.empty_like(out["phi"]) for _ in range(3)]
+    plan.gradient(out["phi"], *grads)
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(10):
+        plan.gradient(out["phi"], *grads)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    grad_ms = g0.elapsed_time(g1) / 10
+    del grads
+
     result = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "dtype": dtype, "data": "synthetic",
@@ -218,6 +231,8 @@ def main():
               "roofline": roof,
               "step_ms_p50": float(np.percentile(step_ms, 50)), "step_ms_p99": float(np.percentile(step_ms, 99)),
               "plan_ms": plan_ms,
+              "gradient": {"ms": grad_ms, "algorithmic_gbs": 32.0 * mesh.ncells / (grad_ms * 1e-3) / 1e9,
+                           "hbm_frac": 32.0 * mesh.ncells / (grad_ms * 1e-3) / 8e12},
               "tuning": plan.tuning(), "autotuned": not args.no_tune, "tune_s": tune_s}
     if fp64 is not None:
         result["fp64_ms_per_step"] = fp64["ms_per_step"]

@@ -198,6 +198,25 @@ int mpole_plan_work(mpole_plan plan, double *moment_flops, double *expand_flops,
  * {w, 0, 0}; mpole_plan_moment_wgs reports the moment launch size.  These
  * are the knobs the package's autotuner searches.
  */
+/*
+ * Coordinate gradient of a potential on the plan's mesh, for the
+ * gravitational source terms -rho grad Phi and -rho v . grad Phi of the
+ * balance equations (Sec. 3; each derivative the simplest centred difference
+ * over the two nearest neighbours).  Writes, on hip_stream, dPhi/dr,
+ * dPhi/dtheta and dPhi/dphi at the cell centres (edge midpoints) as
+ * (Phi(next) - Phi(previous)) / (x(next) - x(previous)); the first and last
+ * shell and theta row use the cell itself for the missing neighbour
+ * (one-sided); phi wraps around when phi_edges span 2 pi (to 1e-12),
+ * otherwise it is one-sided too; a dimension with one cell gets 0.
+ * phi (in) and d_r, d_theta, d_phi (out) are device [nr][ntheta][nphi] FP64
+ * (phi fastest), owned by the caller; an output may be NULL (not written).
+ * The plan must be bound.  MPOLE_ERR_INVALID for a null plan or phi or an
+ * unbound plan, MPOLE_ERR_DEVICE for a launch failure.  Asynchronous, no
+ * allocation, graph-capturable.
+ */
+int mpole_gradient(mpole_plan plan, const double *phi, double *d_r, double *d_theta, double *d_phi,
+                   void *hip_stream);
+
 typedef struct {
   int32_t moment_wgs;
   int32_t moment_tile_m;

@@ -36,6 +36,7 @@ def lib():
         L.oracle_solve.argtypes = [c_int, c_int, c_int, c_int, dp, dp, dp, c_double, c_int, ip, ip,
                                    dp, dp, dp, dp, dp, dp, dp]
         L.oracle_solve.restype = c_int
+        L.oracle_gradient.argtypes = [c_int, c_int, c_int, dp, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -135,6 +136,20 @@ def solve(r_edges, theta_edges, phi_edges, lmax, rho, G=1.0, shell_class=None, c
     lib().oracle_solve(nr, nt, npf, lmax, _dp(r), _dp(th), _dp(ph), float(G), ncls, _ip(sc), _ip(cb),
                        _dp(rho), _dp(phi), _dp(ang), _dp(itr), _dp(ext), _dp(coef), _dp(sec))
     return dict(phi=phi, ang=ang, interior=itr, exterior=ext, coef=coef, seconds=(sec[0], sec[1]))
+
+
+def gradient(r_edges, theta_edges, phi_edges, phi):
+    """Centred-difference coordinate derivatives (dPhi/dr, dPhi/dtheta,
+    dPhi/dphi) at cell centres, each [nr][ntheta][nphi] (Sec. 3 source terms)."""
+    r = np.ascontiguousarray(r_edges, dtype=np.float64)
+    th = np.ascontiguousarray(theta_edges, dtype=np.float64)
+    ph = np.ascontiguousarray(phi_edges, dtype=np.float64)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    shape = (r.size - 1, th.size - 1, ph.size - 1)
+    assert phi.shape == shape
+    out = [np.zeros(shape) for _ in range(3)]
+    lib().oracle_gradient(shape[0], shape[1], shape[2], _dp(r), _dp(th), _dp(ph), _dp(phi), *[_dp(o) for o in out])
+    return tuple(out)
 
 
 def threads():

@@ -424,3 +424,69 @@ int oracle_solve(int nr, int ntheta, int nphi, int lmax, const double *r, const 
   free(C);
   return 0;
 }
+
+/* Gradient of the potential for the gravitational source terms (Sec. 3, the
+ * source vector of the balance equations with its -rho grad Phi and
+ * -rho v . grad Phi entries, and the sentence after it: each component is
+ * the simplest centred difference, from the two nearest neighbours).
+ *
+ * Readings: the components are the coordinate derivatives dPhi/dr,
+ * dPhi/dtheta, dPhi/dphi at cell centres (the covariant components that the
+ * covector momentum source uses); a cell's coordinate is the midpoint of its
+ * edges; the difference is (Phi(next) - Phi(previous)) / (x(next) -
+ * x(previous)); where a neighbour is missing (first or last shell, first or
+ * last theta row, phi when the phi edges do not close the circle) the cell
+ * itself takes its place (one-sided difference); phi wraps around when its
+ * edges span 2 pi; a dimension with a single cell has zero derivative. */
+static double mid(const double *e, int i) { return 0.5 * (e[i] + e[i + 1]); }
+
+static void neighbours(int i, int n, int *lo, int *hi) {
+  *lo = i > 0 ? i - 1 : i;
+  *hi = i < n - 1 ? i + 1 : i;
+}
+
+void oracle_gradient(int nr, int ntheta, int nphi, const double *r, const double *th, const double *ph,
+                     const double *phi, double *d_r, double *d_th, double *d_ph) {
+  const double two_pi = 2.0 * ORACLE_PI;
+  const int periodic = fabs((ph[nphi] - ph[0]) - two_pi) <= 1e-12 * two_pi;
+  const long ncell = (long)ntheta * nphi;
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < nr; ++i) {
+    for (int j = 0; j < ntheta; ++j) {
+      for (int k = 0; k < nphi; ++k) {
+        const long q = (long)i * ncell + (long)j * nphi + k;
+        int lo, hi;
+        /* radius */
+        if (nr == 1) {
+          d_r[q] = 0.0;
+        } else {
+          neighbours(i, nr, &lo, &hi);
+          d_r[q] = (phi[(long)hi * ncell + (long)j * nphi + k] - phi[(long)lo * ncell + (long)j * nphi + k]) /
+                   (mid(r, hi) - mid(r, lo));
+        }
+        /* polar angle */
+        if (ntheta == 1) {
+          d_th[q] = 0.0;
+        } else {
+          neighbours(j, ntheta, &lo, &hi);
+          d_th[q] = (phi[(long)i * ncell + (long)hi * nphi + k] - phi[(long)i * ncell + (long)lo * nphi + k]) /
+                    (mid(th, hi) - mid(th, lo));
+        }
+        /* azimuth */
+        if (nphi == 1) {
+          d_ph[q] = 0.0;
+        } else if (periodic) {
+          const int kl = (k + nphi - 1) % nphi, kh = (k + 1) % nphi;
+          double xl = mid(ph, kl), xh = mid(ph, kh);
+          if (k == 0) xl -= two_pi;
+          if (k == nphi - 1) xh += two_pi;
+          d_ph[q] = (phi[(long)i * ncell + (long)j * nphi + kh] - phi[(long)i * ncell + (long)j * nphi + kl]) / (xh - xl);
+        } else {
+          neighbours(k, nphi, &lo, &hi);
+          d_ph[q] = (phi[(long)i * ncell + (long)j * nphi + hi] - phi[(long)i * ncell + (long)j * nphi + lo]) /
+                    (mid(ph, hi) - mid(ph, lo));
+        }
+      }
+    }
+  }
+}

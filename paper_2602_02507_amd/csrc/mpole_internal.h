@@ -113,6 +113,8 @@ hipError_t launch_reduce(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_scan(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
+hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
+                           hipStream_t s);
 
 hipError_t launch_moment_f64(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_expand_f64(const BatchDev &B, int wgs, hipStream_t s);

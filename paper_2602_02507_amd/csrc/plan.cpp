@@ -100,6 +100,7 @@ struct mpole_plan_t {
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
+  int phi_periodic = 0;   // phi edges close the circle (gradient wraps around)
   size_t off_shift = 0, off_tsum_part = 0;
   int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
   size_t off_plandev = 0, off_prefix = 0;
@@ -202,6 +203,7 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->r.assign(m->r_edges, m->r_edges + m->nr + 1);
   p->th.assign(m->theta_edges, m->theta_edges + m->ntheta + 1);
   p->ph.assign(m->phi_edges, m->phi_edges + m->nphi + 1);
+  p->phi_periodic = std::fabs((p->ph[p->np] - p->ph[0]) - 2.0 * kPi) <= 1e-12 * 2.0 * kPi;
   p->ncls = m->nclasses > 0 ? m->nclasses : 1;
   p->cls.assign(p->ncls, ClassHost{});
   p->shell_class.assign(p->nr, 0);
@@ -626,6 +628,16 @@ int mpole_plan_get_tuning(mpole_plan p, mpole_tuning *t) {
 }
 
 int mpole_plan_moment_wgs(mpole_plan p) { return p ? p->wg_mom : 0; }
+
+int mpole_gradient(mpole_plan p, const double *phi, double *d_r, double *d_theta, double *d_phi, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!p->bound) return fail(MPOLE_ERR_INVALID, "plan is not bound to a workspace");
+  if (!phi) return fail(MPOLE_ERR_INVALID, "phi is null");
+  if (!d_r && !d_theta && !d_phi) return ok();
+  const hipError_t e = launch_gradient(p->dev, phi, d_r, d_theta, d_phi, p->phi_periodic, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "gradient launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
 
 int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");

@@ -22,7 +22,7 @@ STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE
 # every entry point include/mpole.h declares
 EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_plan_workspace_bytes",
            "mpole_plan_nmodes", "mpole_plan_bind", "mpole_solve", "mpole_plan_copy_table",
-           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_plan_tune",
+           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_gradient", "mpole_plan_tune",
            "mpole_plan_get_tuning", "mpole_plan_configure", "mpole_plan_moment_wgs", "mpole_plan_destroy",
            "mpole_batch_create", "mpole_batch_tune", "mpole_batch_configure", "mpole_batch_workspace_bytes",
            "mpole_batch_bind",
@@ -93,6 +93,7 @@ def lib():
         L.mpole_plan_phase_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         dptr = ctypes.POINTER(ctypes.c_double)
         L.mpole_plan_work.argtypes = [vp, dptr, dptr, dptr]
+        L.mpole_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mpole_plan_tune.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_plan_configure.argtypes = [vp, ctypes.c_int32]
@@ -261,6 +262,21 @@ class Plan(HostPlan):
         out = self.empty_outputs(**want)
         self.solve_into(rho, **out)
         return out
+
+    def gradient(self, phi, d_r=None, d_theta=None, d_phi=None, stream=None):
+        """Centred-difference (dPhi/dr, dPhi/dtheta, dPhi/dphi) of a potential on
+        this mesh (mpole_gradient); outputs allocated when not given."""
+        import torch
+        self._check_tensor(phi, self.shape, "phi")
+        outs = []
+        for t in (d_r, d_theta, d_phi):
+            if t is None:
+                t = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+            self._check_tensor(t, self.shape, "gradient output")
+            outs.append(t)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_gradient(self.handle, _dev_ptr(phi), *[_dev_ptr(t) for t in outs], ctypes.c_void_p(s)))
+        return tuple(outs)
 
     def table(self, cls=0):
         """FP64 block-mean kernel table of a coarsening class, [nblocks][nAM] (host numpy)."""

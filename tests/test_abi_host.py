@@ -141,3 +141,12 @@ def test_workload_library_exports_its_header():
     assert L.mpole_wl_rotated_density(0, 1, 1, 1, 1, 1, 0, 1, 0.0, 1, 1, None) == 1
     assert L.mpole_wl_rotated_density(1, 1, 1, 1, 1, 1, 17, 1, 0.0, 1, 1, None) == 1
     assert L.mpole_wl_rotated_density(1, 1, 1, None, 1, 1, 0, 1, 0.0, 1, 1, None) == 1
+
+
+def test_gradient_rejects_unbound_plan():
+    m = wl.production_mesh(4, nr=8, ntheta=8, nphi=8, merged=False)
+    p = mpole.HostPlan.from_mesh(m)
+    L = mpole.lib()
+    assert L.mpole_gradient(None, 1, 1, 1, 1, None) == 1
+    assert L.mpole_gradient(p.handle, 1, 1, 1, 1, None) == 1      # not bound: nothing launched
+    assert b"not bound" in L.mpole_last_error()
