@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cell*(l,m)-modes/s, multipole Phi solve: mixed vs FP64 on GPU at <=1e-6 rel err"
 UNIT = "cell*(l,m)-modes/s"
 PEAK = {"f64": (78.6e12, "TFLOP/s"), "bf16": (2.5e15, "TFLOP/s"), "f16": (2.5e15, "TFLOP/s")}
-DTYPE = {"fp64": "f64", "bf16x3": "bf16", "fp16x2": "f16"}
+DTYPE = {"fp64": "f64", "bf16x3": "bf16", "fp16x2": "f16", "fp64sep": "f64"}
 
 WORKLOADS = {
     # name: (workload generator key, precision)
@@ -30,6 +30,9 @@ WORKLOADS = {
     "production_l32_fp64": ("production_l32", "fp64"),
     "production_l32_bf16x3": ("production_l32", "bf16x3"),
     "production_l32_fp16x2": ("production_l32", "fp16x2"),
+    # separable FP64 contractions (phi transform + per-m theta transforms)
+    "production_sep": ("production", "fp64sep"),
+    "production_l32_sep": ("production_l32", "fp64sep"),
     "spheroid_fp64": ("spheroid", "fp64"),
     # 64 uneven fields, one launch per phase, replayed from a HIP graph
     "batch64_bf16x3": ("batch64", "bf16x3"),
@@ -38,6 +41,7 @@ WORKLOADS = {
     # run) on a rotating density, density update + solve per step, one HIP graph
     "large_fp16x2": ("large", "fp16x2"),
     "large_bf16x3": ("large", "bf16x3"),
+    "large_sep": ("large", "fp64sep"),
 }
 DEFAULT = "production_l32_bf16x3"
 
@@ -57,11 +61,12 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_NAMES = {("fp64", "moment"): "k_moment_f64", ("fp64", "expand"): "k_expand_f64"}
+KERNEL_NAMES = {("fp64", "moment"): "k_moment_f64", ("fp64", "expand"): "k_expand_f64",
+                ("fp64sep", "moment"): "k_sep_phi_anal", ("fp64sep", "expand"): "k_sep_phi_syn"}
 
 
 def kernel_name(precision, phase):
-    if precision == "fp64":
+    if precision in ("fp64", "fp64sep"):
         return KERNEL_NAMES[(precision, phase)]
     return "k_gemm_split<%s, %s>" % (precision, phase)
 
@@ -111,7 +116,7 @@ def roofline(plan, phases, precision, workload):
     achieved = flops / (dom_ms * 1e-3)
     # executed MFMA work: the split precisions run `products` narrow products per
     # algorithmic multiply-add, over padded tiles
-    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
+    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1}[precision]
     return {"bound": "mfma", "kernel": kernel_name(precision, dom),
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
             "traffic": measured_traffic(workload, dom), "launch_ms": dom_ms,
@@ -349,7 +354,7 @@ def bench_large(args, precision):
                                                                          solve_ms))
     cell_modes = float(mesh.ncells) * mesh.nmodes
     mflops, eflops, min_bytes = plan.work()
-    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
+    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1}[precision]
     roof = roofline(plan, phases, precision, args.workload)
     result = {"metric": METRIC, "value": cell_modes / (solve_ms * 1e-3), "unit": UNIT, "n_gpus": 1,
               "steps": steps, "warmup": args.warmup, "ms_per_step": graph_ms / steps, "higher_is_better": True,

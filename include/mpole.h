@@ -69,7 +69,11 @@ typedef enum {
 typedef enum {
   MPOLE_FP64 = 0,            /* both contractions in FP64 (MFMA f64) */
   MPOLE_BF16X3 = 1,          /* both contractions as three-way split BF16 products, FP32 accumulation */
-  MPOLE_FP16X2 = 2           /* both contractions as two-way split FP16 products, per-shell scaling */
+  MPOLE_FP16X2 = 2,          /* both contractions as two-way split FP16 products, per-shell scaling */
+  MPOLE_FP64_SEPARABLE = 3   /* FP64; each contraction as a phi transform and per-m theta transforms
+                                (the cell-averaged kernels and solid angles factor in theta and phi;
+                                the same sums reordered).  Single-plan solves only: mpole_batch_create
+                                returns MPOLE_ERR_UNSUPPORTED, mpole_plan_copy_table has no table. */
 } mpole_precision;
 
 typedef struct mpole_plan_t *mpole_plan;

@@ -35,6 +35,11 @@ __device__ inline __attribute__((address_space(1))) T *gmem(T *p) {
   return (__attribute__((address_space(1))) T *)p;
 }
 
+// cos t0 - cos t1 as a product, exact for thin theta cells.
+__device__ inline double cos_diff(double t0, double t1) {
+  return 2.0 * sin(0.5 * (t0 + t1)) * sin(0.5 * (t1 - t0));
+}
+
 // Field of workgroup wg in a launch of phase h (binary search of the prefix
 // sums; the searched values are uniform across the workgroup).
 __device__ inline int field_of(const BatchDev &B, int h, int wg) {

@@ -92,6 +92,27 @@ struct BatchDev {
   unsigned long long *stamps;  // [nf+1]: per field, wall clock when its potential is done; [nf] batch start; or null
 };
 
+// Separable FP64 path: bind-time transform tables and per-solve intermediates
+// (trig modes t = 0, 2m-1 (cos), 2m (sin), padded to tpad; t-major per shell).
+struct SepDev {
+  int32_t tpad;
+  double *tw;              // [2][tpad][nphi]: dphi_k <trig_t>_k, then <trig_t>_k
+  double *pw;              // [L+1][ntheta][L+1]: 4 pi G dcos_j <P~_{l'+m,m}>_j as [m][j][l']
+  double *pt;              // [L+1][L+1][ntheta]: <P~_{l'+m,m}>_j as [m][l'][j]
+  double *shat;            // [nr][ntheta][nphi] block-mean density on rows with a merged block
+  const uint8_t *rowalt;   // [nr][ntheta] 1 where the row reads shat
+  double *f, *g;           // [nr][tpad][ntheta] phi analysis, theta synthesis
+  double *dom;             // [ntheta][nphi] solid angle of each cell
+};
+// Per class: blocks on rows with a merged block (source means), and blocks
+// with more than one member (potential means); device lists.
+struct SepClass {
+  const int32_t *src;
+  int32_t n_src;
+  const int32_t *avg;
+  int32_t n_avg;
+};
+
 // Split precisions: operands are sums of nplanes narrow floats (hi + mid + lo),
 // stored as raw 16-bit patterns.
 enum SplitKind { kSplitBf16x3 = 1, kSplitFp16x2 = 2 };
@@ -100,7 +121,7 @@ enum SplitKind { kSplitBf16x3 = 1, kSplitFp16x2 = 2 };
 // bind time, per plan
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s);
-hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g,
+hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g, bool dense,
                          hipStream_t s);
 hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, int kind, hipStream_t s);
 // solve time, one launch per phase covering every field of B; wgs = total workgroups
@@ -115,6 +136,16 @@ hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStrea
 hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
                            hipStream_t s);
+
+// separable FP64 path (single plan)
+hipError_t launch_sep_tables(const PlanDev &P, const SepDev &S, hipStream_t s);
+hipError_t launch_sep_source(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
+                             const double *rho, hipStream_t s);
+hipError_t launch_sep_phi_anal(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s);
+hipError_t launch_sep_theta_anal(const PlanDev &P, const SepDev &S, double *ang_out, hipStream_t s);
+hipError_t launch_sep_theta_syn(const PlanDev &P, const SepDev &S, hipStream_t s);
+hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
+                              double *phi, hipStream_t s);
 
 hipError_t launch_moment_f64(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_expand_f64(const BatchDev &B, int wgs, hipStream_t s);

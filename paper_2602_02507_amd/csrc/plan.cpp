@@ -74,6 +74,8 @@ struct ClassHost {
   std::vector<int32_t> rows, moff, mem;
   std::vector<int32_t> rect;  // 4 per block when every block is a rectangle in (j, k)
   std::vector<int32_t> span0; // per packing span: first cell when the span is a run of single cells, else -1
+  std::vector<int32_t> sep_src, sep_avg;   // separable path: blocks on merged rows, blocks with > 1 member
+  size_t off_sep_src = 0, off_sep_avg = 0;
   size_t off_span0 = 0;
   size_t off_rect = 0;
   int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
@@ -101,6 +103,13 @@ struct mpole_plan_t {
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
   int phi_periodic = 0;   // phi edges close the circle (gradient wraps around)
+  bool sep = false;       // separable FP64 contractions
+  int tpad = 0;           // separable: trig modes 2L+1 padded to 16
+  bool any_alt = false;   // separable: some row holds a merged block
+  std::vector<uint8_t> rowalt;   // separable: [nr][ntheta] rows read from the block means
+  size_t off_tw = 0, off_pw = 0, off_pt = 0, off_shat = 0, off_rowalt = 0, off_f = 0, off_g = 0, off_dom = 0;
+  SepDev sdev{};
+  std::vector<SepClass> scls;
   size_t off_shift = 0, off_tsum_part = 0;
   int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
   size_t off_plandev = 0, off_prefix = 0;
@@ -162,7 +171,8 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     return fail(MPOLE_ERR_INVALID, "mesh sizes must be >= 1 (nr=%d ntheta=%d nphi=%d)", m->nr, m->ntheta, m->nphi);
   if (m->lmax < 0) return fail(MPOLE_ERR_INVALID, "lmax must be >= 0");
   if (m->lmax > MPOLE_LMAX_MAX) return fail(MPOLE_ERR_UNSUPPORTED, "lmax %d above %d", m->lmax, MPOLE_LMAX_MAX);
-  if (m->precision != MPOLE_FP64 && m->precision != MPOLE_BF16X3 && m->precision != MPOLE_FP16X2)
+  if (m->precision != MPOLE_FP64 && m->precision != MPOLE_BF16X3 && m->precision != MPOLE_FP16X2 &&
+      m->precision != MPOLE_FP64_SEPARABLE)
     return fail(MPOLE_ERR_UNSUPPORTED, "unknown precision %d", m->precision);
   if (!std::isfinite(m->G)) return fail(MPOLE_ERR_INVALID, "G is not finite");
   const long long ncell = (long long)m->ntheta * m->nphi;
@@ -195,6 +205,8 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->ncell = (int)ncell;
   p->precision = m->precision;
   p->nplanes = n_planes(m->precision);
+  p->sep = m->precision == MPOLE_FP64_SEPARABLE;
+  p->tpad = round_up(2 * m->lmax + 1, 16);
   // output tiles of the contraction kernels: 64 x 64 (f64 MFMA); 128 x 128
   // (split; the height may be tuned to 64)
   p->tm_mom = p->tm_exp = p->nplanes ? 128 : 64;
@@ -272,6 +284,29 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     }
     C.n_tiles_mom = (p->namp + p->tile_n - 1) / p->tile_n;
     C.n_tiles_exp = (C.nblocks + p->tile_n - 1) / p->tile_n;
+  }
+  if (p->sep) {
+    // rows holding a merged block read the block-mean density; their blocks
+    // are averaged on the way in, blocks of several cells on the way out
+    p->rowalt.assign((size_t)p->nr * p->nt, 0);
+    std::vector<std::vector<uint8_t>> merged(p->ncls, std::vector<uint8_t>(p->nt, 0));
+    for (int c = 0; c < p->ncls; ++c) {
+      ClassHost &C = p->cls[c];
+      for (int b = 0; b < C.nblocks; ++b)
+        if (C.moff[b + 1] - C.moff[b] > 1)
+          for (int e = C.moff[b]; e < C.moff[b + 1]; ++e) merged[c][C.mem[e] / p->np] = 1;
+      C.sep_src.clear();
+      C.sep_avg.clear();
+      for (int b = 0; b < C.nblocks; ++b) {
+        if (C.moff[b + 1] - C.moff[b] > 1) C.sep_avg.push_back(b);
+        if (merged[c][C.mem[C.moff[b]] / p->np]) C.sep_src.push_back(b);
+      }
+    }
+    for (int i = 0; i < p->nr; ++i)
+      for (int j = 0; j < p->nt; ++j) {
+        p->rowalt[(size_t)i * p->nt + j] = merged[p->shell_class[i]][j];
+        p->any_alt = p->any_alt || merged[p->shell_class[i]][j];
+      }
   }
   p->rule = make_gauss_rule();
   // about one full round of resident workgroups: 4 per CU (f64 kernel), 3 per CU (split kernel)
@@ -368,17 +403,31 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_mem = take(sizeof(int32_t) * p->ncell);
     C.off_rect = take(sizeof(int32_t) * C.rect.size());
     C.off_span0 = take(sizeof(int32_t) * C.span0.size());
-    C.off_table = take(sizeof(double) * (size_t)C.nblocks_pad * p->namp);
-    C.off_tcol0 = take(sizeof(double) * (size_t)C.nblocks_pad);
+    const size_t dense = p->sep ? 0 : 1;   // the separable path has no block x mode tables
+    C.off_table = take(dense * sizeof(double) * (size_t)C.nblocks_pad * p->namp);
+    C.off_tcol0 = take(dense * sizeof(double) * (size_t)C.nblocks_pad);
     C.off_wsum = take(sizeof(double) * (size_t)C.nblocks_pad);
-    C.off_tsum = take(sizeof(double) * (size_t)p->namp);
-    C.off_pack = take(sizeof(double) * nrows * C.nblocks_pad);
+    C.off_tsum = take(dense * sizeof(double) * (size_t)p->namp);
+    C.off_pack = take(dense * sizeof(double) * nrows * C.nblocks_pad);
     // split-K partials: FP64 for the f64 kernel, FP32 (the accumulator type) for split precisions
-    C.off_partial = take((p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp);
+    C.off_partial = take(dense * (p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp);
+    C.off_sep_src = take(sizeof(int32_t) * C.sep_src.size());
+    C.off_sep_avg = take(sizeof(int32_t) * C.sep_avg.size());
     C.off_tplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
     C.off_ttplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
     C.off_ppacks = take(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.nblocks_pad);
     C.off_pscale = take(sizeof(double) * std::max<size_t>(nrows, 1));
+  }
+  if (p->sep) {
+    const size_t L1 = p->L + 1, nrt = (size_t)p->nr * p->nt;
+    p->off_tw = take(sizeof(double) * 2 * (size_t)p->tpad * p->np);
+    p->off_pw = take(sizeof(double) * L1 * p->nt * L1);
+    p->off_pt = take(sizeof(double) * L1 * L1 * p->nt);
+    p->off_shat = take(p->any_alt ? sizeof(double) * (size_t)p->nr * p->ncell : 0);
+    p->off_rowalt = take(nrt);
+    p->off_f = take(sizeof(double) * nrt * p->tpad);
+    p->off_g = take(sizeof(double) * nrt * p->tpad);
+    p->off_dom = take(sizeof(double) * (size_t)p->ncell);
   }
   // the single-plan view of the batched kernels: one device plan, phase prefix sums
   p->off_plandev = take(sizeof(PlanDev));
@@ -563,7 +612,29 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   for (int h = 0; h < PH_COUNT; ++h) p->prefix[2 * h + 1] = phase_wgs_host(p, h);
   if (e == hipSuccess) e = upload(ws, p->off_plandev, &p->dev, sizeof(PlanDev), s);
   if (e == hipSuccess) e = upload(ws, p->off_prefix, p->prefix.data(), sizeof(int32_t) * p->prefix.size(), s);
-  if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, s);
+  if (p->sep) {
+    SepDev &S = p->sdev;
+    S.tpad = p->tpad;
+    S.tw = (double *)(ws + p->off_tw);
+    S.pw = (double *)(ws + p->off_pw);
+    S.pt = (double *)(ws + p->off_pt);
+    S.shat = p->any_alt ? (double *)(ws + p->off_shat) : nullptr;
+    S.rowalt = p->any_alt ? (const uint8_t *)(ws + p->off_rowalt) : nullptr;
+    S.f = (double *)(ws + p->off_f);
+    S.g = (double *)(ws + p->off_g);
+    S.dom = (double *)(ws + p->off_dom);
+    p->scls.assign(p->ncls, SepClass{});
+    for (int c = 0; c < p->ncls; ++c) {
+      const ClassHost &H = p->cls[c];
+      p->scls[c] = SepClass{(const int32_t *)(ws + H.off_sep_src), (int32_t)H.sep_src.size(),
+                            (const int32_t *)(ws + H.off_sep_avg), (int32_t)H.sep_avg.size()};
+      if (e == hipSuccess) e = upload(ws, H.off_sep_src, H.sep_src.data(), sizeof(int32_t) * H.sep_src.size(), s);
+      if (e == hipSuccess) e = upload(ws, H.off_sep_avg, H.sep_avg.data(), sizeof(int32_t) * H.sep_avg.size(), s);
+    }
+    if (e == hipSuccess) e = upload(ws, p->off_rowalt, p->rowalt.data(), p->rowalt.size(), s);
+  }
+  if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, !p->sep, s);
+  if (e == hipSuccess && p->sep) e = launch_sep_tables(D, p->sdev, s);
   if (e == hipSuccess && p->nplanes) e = launch_split_tables(D, p->cdev.data(), p->precision, s);
   // unit row scales (BF16 x3 operands are not scaled; FP16 x2 rows overwrite theirs)
   for (int c = 0; c < p->ncls && e == hipSuccess; ++c)
@@ -659,8 +730,24 @@ int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, doubl
   B.stamps = nullptr;
   int wgs[PH_COUNT];
   for (int h = 0; h < PH_COUNT; ++h) wgs[h] = p->prefix[2 * h + 1];
-  hipError_t e = run_solve(B, p->precision, wgs, phi != nullptr, s,
-                           [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
+  hipError_t e;
+  if (p->sep) {
+    const PlanDev &D = p->dev;
+    const SepDev &S = p->sdev;
+    auto T = [&](int phase, auto &&launch) { return timed(p, phase, s, launch); };
+    e = hipSuccess;
+    if (p->any_alt)
+      e = T(MPOLE_PHASE_PACK, [&] { return launch_sep_source(D, S, p->cdev.data(), p->scls.data(), rho, s); });
+    if (e == hipSuccess) e = T(MPOLE_PHASE_MOMENT, [&] { return launch_sep_phi_anal(D, S, rho, s); });
+    if (e == hipSuccess) e = T(MPOLE_PHASE_REDUCE, [&] { return launch_sep_theta_anal(D, S, ang, s); });
+    if (e == hipSuccess) e = T(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], s); });
+    if (e == hipSuccess && phi) e = T(MPOLE_PHASE_SPLIT, [&] { return launch_sep_theta_syn(D, S, s); });
+    if (e == hipSuccess && phi)
+      e = T(MPOLE_PHASE_EXPAND, [&] { return launch_sep_phi_syn(D, S, p->cdev.data(), p->scls.data(), phi, s); });
+  } else {
+    e = run_solve(B, p->precision, wgs, phi != nullptr, s,
+                  [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
+  }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
   return ok();
 }
@@ -670,6 +757,7 @@ int mpole_plan_copy_table(mpole_plan p, int32_t cls, double *host_out, int64_t *
   if (cls < 0 || cls >= p->ncls) return fail(MPOLE_ERR_INVALID, "class %d out of range", cls);
   const ClassHost &H = p->cls[cls];
   if (nblocks) *nblocks = H.nblocks;
+  if (p->sep) return fail(MPOLE_ERR_UNSUPPORTED, "the separable path keeps no block x mode table");
   if (!host_out) return ok();
   if (!p->bound) return fail(MPOLE_ERR_WORKSPACE, "plan has no bound workspace");
   hipStream_t s = (hipStream_t)stream;
@@ -710,9 +798,14 @@ int mpole_plan_phase_ms(mpole_plan p, double *total_ms, int64_t *launches) {
 int mpole_plan_work(mpole_plan p, double *moment_flops, double *expand_flops, double *min_bytes) {
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
   double f = 0.0, tb = 0.0;
-  for (const auto &C : p->cls) {
-    f += 2.0 * (double)C.rows.size() * C.nblocks * p->nam;
-    if (!C.rows.empty()) tb += 8.0 * (double)C.nblocks * p->nam;
+  if (p->sep) {
+    // the phi transform of each direction, 2 flops per (shell, theta row, phi cell, trig mode)
+    f = 2.0 * (double)p->nr * p->ncell * (2 * p->L + 1);
+  } else {
+    for (const auto &C : p->cls) {
+      f += 2.0 * (double)C.rows.size() * C.nblocks * p->nam;
+      if (!C.rows.empty()) tb += 8.0 * (double)C.nblocks * p->nam;
+    }
   }
   if (moment_flops) *moment_flops = f;
   if (expand_flops) *expand_flops = f;
@@ -786,6 +879,8 @@ int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *o
   if (!out) return fail(MPOLE_ERR_INVALID, "out is null");
   if (nfields < 1 || nfields > 4096) return fail(MPOLE_ERR_INVALID, "nfields %d outside [1, 4096]", nfields);
   if (!meshes) return fail(MPOLE_ERR_INVALID, "meshes is null");
+  if (meshes[0].precision == MPOLE_FP64_SEPARABLE)
+    return fail(MPOLE_ERR_UNSUPPORTED, "the separable path solves single plans only");
   try {
     mpole_batch_t *b = new mpole_batch_t();
     for (int f = 0; f < nfields; ++f) {

@@ -1,0 +1,453 @@
+// Separable form of the two angular contractions, in FP64.
+//
+// The cell-averaged kernels factor: <A_lma>_jk = <P~_lm>_j <trig_ma>_k, and
+// so do the solid angles, dOmega_jk = dcos_j dphi_k (Eqs. AngularKernel_c /
+// AngularKernel_s averaged over a theta-phi cell).  Within a shell:
+//
+//   moment   A_lma  = sum_j [4 pi G dcos_j P~_lm(j)] F_ma(j),
+//            F_ma(j) = sum_k [dphi_k <trig_ma>_k] rhohat_jk,
+//   potential Phihat_jk = sum_ma <trig_ma>_k G_ma(j),
+//            G_ma(j) = sum_l C_lma P~_lm(j),
+//
+// where rhohat is the density with every coarsening block replaced by its
+// solid-angle weighted mean, and a block's potential is the solid-angle
+// weighted mean of Phihat over its members.  Both identities are exact
+// (a reordering of the sums of Eq. AngularMomentsDiscrete and Eq. Solution
+// with block-mean kernels), so this path computes the same result as the
+// dense contractions over blocks x modes, in about (2L+1) nphi + (L+1)^2
+// instead of 2 (L+1)^2 nphi multiply-adds per (shell, theta row).
+//
+// Trig modes are t = 0 (m = 0), 2m-1 (cos m phi), 2m (sin m phi), padded to
+// tpad (a multiple of 16).  Per-shell intermediates are t-major:
+// F[i][t][j], G[i][t][j].  Steps and kernels:
+//   source     block means of rho on the rows that hold a merged block
+//   phi_anal   F_i[t][j]  = sum_k TW[t][k] rhohat_i[j][k]       (batched over shells)
+//   theta_anal A[i][lma]  = sum_j F[i][t][j] PW_m[j][l-m]       (batched over t)
+//   (radial scans and coefficients as in the dense path)
+//   theta_syn  G[i][t][j] = sum_l C[i][lma] PT_m[l-m][j]         (batched over t)
+//   phi_syn    Phihat_i[j][k] = sum_t G_i[t][j] TT[t][k]        (batched over shells)
+//   block_mean block means of Phihat written to the members of merged blocks
+// All four contractions run on v_mfma_f64_16x16x4 with the 64 x 64 tiles
+// and conflict-free LDS layouts of the dense FP64 kernels.
+#include <algorithm>
+
+#include "device_util.h"
+#include "f64_mma.h"
+
+namespace mpole {
+namespace {
+
+using namespace f64mma;
+
+// Operand of a tile.  K-contiguous operands (staged [row][k]) give the start
+// of a row, row(b, r), and the offset of element k in it, off(k);
+// row-contiguous operands (staged [k][row]) give the column start col(b, r)
+// and the stride between k, ld.  Callers pass clamped, in-range rows and k;
+// the tile zeroes elements outside (rows, K).
+struct RowsK {   // element (r, k) at base + b*bs + r*ld + k
+  const double *base;
+  long bs, ld;
+  __device__ const double *row(int b, int r) const { return base + b * bs + (long)r * ld; }
+  __device__ int off(int k) const { return k; }
+};
+struct KRows {   // element (r, k) at base + b*bs + k*ld + r
+  const double *base;
+  long bs, ld;
+  __device__ const double *col(int b, int r) const { return base + b * bs + r; }
+};
+// The density rows of shell b: rho, or the block means for rows with a merged block.
+struct SourceRows {
+  const double *rho, *shat;
+  const uint8_t *alt;   // [nr][ntheta]
+  int ntheta, nphi;
+  long ncell;
+  __device__ const double *row(int b, int r) const {
+    const long o = b * ncell + (long)r * nphi;
+    return (alt != nullptr && alt[(long)b * ntheta + r]) ? shat + o : rho + o;
+  }
+  __device__ int off(int k) const { return k; }
+};
+// Coefficients C[i][l m a] of one trig mode t = (m, a), element k at l = k + m.
+struct CoefGather {
+  const double *coef;
+  int namp, m, a;
+  __device__ const double *row(int, int r) const { return coef + (long)r * namp; }
+  __device__ int off(int k) const {
+    const int l = k + m;
+    return m == 0 ? l * l : l * l + 2 * m - 1 + a;
+  }
+};
+
+__device__ inline void trig_mode(int t, int &m, int &a) {
+  m = (t + 1) >> 1;
+  a = (t > 0 && (t & 1) == 0) ? 1 : 0;
+}
+
+// Loader of one operand of a 64-row tile (rows r0.., R rows in all, K deep):
+// K-contiguous operands move 4 consecutive k of row tid/4, row-contiguous
+// ones rows tid%16 + 16 e of k-row tid/16.  Row addresses are resolved once.
+template <bool KC, class OP>
+struct TileLoader {
+  const double *p[4];
+  long ld;
+  int r[4], kk[4];
+  OP op;
+  __device__ TileLoader(const OP &o, int b, int r0, int R, long ld_) : ld(ld_), op(o) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      r[e] = KC ? (tid >> 2) : (tid & 15) + 16 * e;
+      kk[e] = KC ? (tid & 3) * 4 + e : (tid >> 4);
+      const int rc = min(r0 + r[e], max(R, 1) - 1);
+      if constexpr (KC) p[e] = o.row(b, rc);
+      else p[e] = o.col(b, rc);
+    }
+  }
+  __device__ double load(int e, int k0, int K) const {
+    const int k = min(k0 + kk[e], K - 1);
+    if constexpr (KC) return *gmem(p[e] + op.off(k));
+    else return *gmem(p[e] + (long)k * ld);
+  }
+  __device__ void store(double *S, int e, double v, bool ok) const {
+    const double x = ok ? v : 0.0;
+    if (KC) S[r[e] * RK + kk[e]] = x; else S[kk[e] * KR + r[e]] = x;
+  }
+};
+
+// Accumulates the M x N x K product of one 64 x 64 output tile (rows m0..,
+// columns n0..) of batch b into acc.
+struct NoHook {
+  __device__ void operator()(const double *, const double *, int) const {}
+};
+
+template <bool A_KC, bool B_KC, class OA, class OB, class HOOK = NoHook>
+__device__ __forceinline__ void tile_product(const OA &A, long a_ld, const OB &B, long b_ld, int b, int M, int N,
+                                             int K, int m0, int n0, d4 acc[2][2], double (*As)[STAGE],
+                                             double (*Bs)[STAGE], const HOOK &hook = HOOK()) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const TileLoader<A_KC, OA> la(A, b, m0, M, a_ld);
+  const TileLoader<B_KC, OB> lb(B, b, n0, N, b_ld);
+  double av[4], bv[4];
+  auto load = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      av[e] = la.load(e, k0, K);
+      bv[e] = lb.load(e, k0, K);
+    }
+  };
+  auto store = [&](int buf, int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      la.store(As[buf], e, av[e], m0 + la.r[e] < M && k0 + la.kk[e] < K);
+      lb.store(Bs[buf], e, bv[e], n0 + lb.r[e] < N && k0 + lb.kk[e] < K);
+    }
+  };
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load((kt + 1) * BK);
+    hook(As[cur], Bs[cur], kt * BK);   // the stage in LDS, before it is overwritten
+    mfma_stage<A_KC, B_KC>(As[cur], Bs[cur], wm, wn, lane, acc);
+    if (more) store(cur ^ 1, (kt + 1) * BK);
+    __syncthreads();
+  }
+}
+
+// Row and column of accumulator element (t, u, r) of this lane.
+__device__ inline void acc_pos(int t, int u, int r, int &row, int &col) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  row = (w & 1) * 32 + t * 16 + 4 * r + (lane >> 4);
+  col = (w >> 1) * 32 + u * 16 + (lane & 15);
+}
+
+// ---- per-solve kernels ------------------------------------------------------
+
+// Block means of rho for every block on a row that holds a merged block.
+__global__ __launch_bounds__(256) void k_sep_source(PlanDev P, SepDev S, ClassDev C, const int32_t *blocks,
+                                                    int nblocks, const double *rho_) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= nblocks) return;
+  const int b = blocks[x];
+  const int i = gmem(C.rows)[blockIdx.y];
+  const auto rho = gmem(rho_) + (long)i * P.ncell;
+  const auto shat = gmem(S.shat) + (long)i * P.ncell;
+  const auto mem = gmem(C.mem);
+  const int e0 = gmem(C.moff)[b], e1 = gmem(C.moff)[b + 1];
+  double num = 0.0, den = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int q = mem[e];
+    const double dom = gmem(S.dom)[q];
+    num += dom * rho[q];
+    den += dom;
+  }
+  const double v = num / den;
+  for (int e = e0; e < e1; ++e) shat[mem[e]] = v;
+}
+
+// F_i[t][j] = sum_k TW[t][k] rhohat_i[j][k]; grid (t tiles x j tiles, shells).
+// The MFMA tiles cover t = 1 .. 2L (cos and sin of m >= 1: 2L rows, whole
+// 64-row tiles for even L); the m = 0 row, a dphi-weighted row sum, is added
+// from the density stages in LDS by the workgroups of the first t tile.
+struct RowSum {
+  const double *dphi;   // TW row 0: dphi_k
+  int j0, nphi;
+  double *sum;          // this thread's running sum (row tid, tid < 64)
+  __device__ void operator()(const double *, const double *Bs, int k0) const {
+    if (threadIdx.x >= BN) return;
+    double s = *sum;
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk)
+      if (k0 + kk < nphi) s += dphi[k0 + kk] * Bs[threadIdx.x * RK + kk];
+    *sum = s;
+  }
+};
+
+__global__ __launch_bounds__(NTHREADS) void k_sep_phi_anal(PlanDev P, SepDev S, const double *rho) {
+  __shared__ double As[2][STAGE], Bs[2][STAGE];
+  const int i = blockIdx.y;
+  const int ntj = (P.ntheta + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntj) * BM, n0 = (blockIdx.x % ntj) * BN;
+  const int M = 2 * P.lmax;   // t = 1 .. 2L
+  const RowsK A{S.tw + P.nphi, 0, P.nphi};
+  const SourceRows Bop{rho, S.shat, S.rowalt, P.ntheta, P.nphi, (long)P.ncell};
+  d4 acc[2][2];
+  double rs = 0.0;
+  const auto F = gmem(S.f) + (long)i * S.tpad * P.ntheta;
+  if (m0 == 0) {
+    tile_product<true, true>(A, 0, Bop, 0, i, M, P.ntheta, P.nphi, m0, n0, acc, As, Bs,
+                             RowSum{S.tw, n0, P.nphi, &rs});
+    if (threadIdx.x < BN && n0 + (int)threadIdx.x < P.ntheta) F[n0 + threadIdx.x] = rs;
+  } else {
+    tile_product<true, true>(A, 0, Bop, 0, i, M, P.ntheta, P.nphi, m0, n0, acc, As, Bs);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(t, u, r, row, col);
+        row += m0;
+        col += n0;
+        if (row < M && col < P.ntheta) F[(long)(row + 1) * P.ntheta + col] = acc[t][u][r];
+      }
+}
+
+// A[i][l m a] = sum_j F[i][t][j] PW_m[j][l-m]; grid (shell tiles x l tiles, t).
+__global__ __launch_bounds__(NTHREADS) void k_sep_theta_anal(PlanDev P, SepDev S, double *ang_out) {
+  __shared__ double As[2][STAGE], Bs[2][STAGE];
+  const int t = blockIdx.y;
+  int m, a;
+  trig_mode(t, m, a);
+  const int L1 = P.lmax + 1, N = L1 - m;
+  const int ntl = (L1 + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntl) * BM, n0 = (blockIdx.x % ntl) * BN;
+  if (n0 >= N) return;
+  const RowsK A{S.f + (long)t * P.ntheta, 0, (long)S.tpad * P.ntheta};
+  const KRows Bop{S.pw + (long)m * P.ntheta * L1, 0, L1};
+  d4 acc[2][2];
+  tile_product<true, false>(A, 0, Bop, Bop.ld, 0, P.nr, N, P.ntheta, m0, n0, acc, As, Bs);
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(tt, u, r, row, col);
+        row += m0;
+        col += n0;
+        if (row >= P.nr || col >= N) continue;
+        const int l = col + m;
+        const int n = m == 0 ? l * l : l * l + 2 * m - 1 + a;
+        gmem(P.ang)[(long)row * P.namp + n] = acc[tt][u][r];
+        if (ang_out != nullptr) gmem(ang_out)[(long)row * P.nam + n] = acc[tt][u][r];
+      }
+}
+
+// G[i][t][j] = sum_l C[i][l m a] PT_m[l-m][j]; grid (shell tiles x j tiles, t).
+__global__ __launch_bounds__(NTHREADS) void k_sep_theta_syn(PlanDev P, SepDev S) {
+  __shared__ double As[2][STAGE], Bs[2][STAGE];
+  const int t = blockIdx.y;
+  int m, a;
+  trig_mode(t, m, a);
+  const int L1 = P.lmax + 1, K = L1 - m;
+  const int ntj = (P.ntheta + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntj) * BM, n0 = (blockIdx.x % ntj) * BN;
+  const CoefGather A{P.coef, P.namp, m, a};
+  const KRows Bop{S.pt + (long)m * L1 * P.ntheta, 0, P.ntheta};
+  d4 acc[2][2];
+  tile_product<true, false>(A, 0, Bop, Bop.ld, 0, P.nr, P.ntheta, K, m0, n0, acc, As, Bs);
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(tt, u, r, row, col);
+        row += m0;
+        col += n0;
+        if (row < P.nr && col < P.ntheta)
+          gmem(S.g)[((long)row * S.tpad + t) * P.ntheta + col] = acc[tt][u][r];
+      }
+}
+
+// Phihat_i[j][k] = sum_t G_i[t][j] TT[t][k]; grid (j tiles x k tiles, shells).
+__global__ __launch_bounds__(NTHREADS) void k_sep_phi_syn(PlanDev P, SepDev S, double *phi) {
+  __shared__ double As[2][STAGE], Bs[2][STAGE];
+  const int i = blockIdx.y;
+  const int ntk = (P.nphi + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntk) * BM, n0 = (blockIdx.x % ntk) * BN;
+  const KRows A{S.g, (long)S.tpad * P.ntheta, P.ntheta};
+  const KRows Bop{S.tw + (long)S.tpad * P.nphi, 0, P.nphi};   // TT follows TW
+  d4 acc[2][2];
+  tile_product<false, false>(A, A.ld, Bop, Bop.ld, i, P.ntheta, P.nphi, S.tpad, m0, n0, acc, As, Bs);
+  const auto out = gmem(phi) + (long)i * P.ncell;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row, col;
+        acc_pos(t, u, r, row, col);
+        row += m0;
+        col += n0;
+        if (row < P.ntheta && col < P.nphi) out[(long)row * P.nphi + col] = acc[t][u][r];
+      }
+}
+
+// Solid-angle weighted mean of Phihat over each merged block, written to its members.
+__global__ __launch_bounds__(256) void k_sep_block_mean(PlanDev P, SepDev S, ClassDev C, const int32_t *blocks,
+                                                        int nblocks, double *phi_) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= nblocks) return;
+  const int b = blocks[x];
+  const int i = gmem(C.rows)[blockIdx.y];
+  const auto phi = gmem(phi_) + (long)i * P.ncell;
+  const auto mem = gmem(C.mem);
+  const int e0 = gmem(C.moff)[b], e1 = gmem(C.moff)[b + 1];
+  double num = 0.0, den = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int q = mem[e];
+    const double dom = gmem(S.dom)[q];
+    num += dom * phi[q];
+    den += dom;
+  }
+  const double v = num / den;
+  for (int e = e0; e < e1; ++e) phi[mem[e]] = v;
+}
+
+// ---- bind-time tables -------------------------------------------------------
+
+// TW[t][k] = dphi_k <trig_t>_k and TT[t][k] = <trig_t>_k (zero for t > 2L);
+// PW[m][j][l-m] = 4 pi G dcos_j <P~_lm>_j and PT[m][l-m][j] = <P~_lm>_j (zero for l > L).
+__global__ __launch_bounds__(256) void k_sep_tables(PlanDev P, SepDev S) {
+  const long x = (long)blockIdx.x * 256 + threadIdx.x;
+  const int L1 = P.lmax + 1;
+  const long ntw = (long)S.tpad * P.nphi;
+  const long npw = (long)L1 * P.ntheta * L1;
+  if (x < ntw) {
+    const int t = (int)(x / P.nphi), k = (int)(x % P.nphi);
+    int m, a;
+    trig_mode(t, m, a);
+    const double v = (t < 2 * L1 - 1) ? P.trig[(long)k * 2 * L1 + 2 * m + a] : 0.0;
+    S.tw[x] = (P.phi_edges[k + 1] - P.phi_edges[k]) * v;
+    S.tw[ntw + x] = v;
+    return;
+  }
+  const long y = x - ntw;
+  if (y >= 2 * npw) {   // solid angle of each cell
+    const long q = y - 2 * npw;
+    if (q < P.ncell) {
+      const int j = (int)(q / P.nphi), k = (int)(q % P.nphi);
+      S.dom[q] = cos_diff(P.theta_edges[j], P.theta_edges[j + 1]) * (P.phi_edges[k + 1] - P.phi_edges[k]);
+    }
+    return;
+  }
+  const int nplm = L1 * (L1 + 1) / 2;
+  if (y < npw) {   // PW[m][j][lp]
+    const int m = (int)(y / ((long)P.ntheta * L1));
+    const int j = (int)(y / L1 % P.ntheta), lp = (int)(y % L1);
+    const int l = lp + m;
+    double v = 0.0;
+    if (l <= P.lmax)
+      v = 4.0 * kPi * P.G * cos_diff(P.theta_edges[j], P.theta_edges[j + 1]) *
+          P.pavg[(long)j * nplm + l * (l + 1) / 2 + m];
+    S.pw[y] = v;
+  } else {         // PT[m][lp][j]
+    const long z = y - npw;
+    const int m = (int)(z / ((long)L1 * P.ntheta));
+    const int lp = (int)(z / P.ntheta % L1), j = (int)(z % P.ntheta);
+    const int l = lp + m;
+    S.pt[z] = (l <= P.lmax) ? P.pavg[(long)j * nplm + l * (l + 1) / 2 + m] : 0.0;
+  }
+}
+
+inline unsigned tiles(int n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_sep_tables(const PlanDev &P, const SepDev &S, hipStream_t s) {
+  const long L1 = P.lmax + 1;
+  const long n = (long)S.tpad * P.nphi + 2 * L1 * P.ntheta * L1 + P.ncell;
+  hipLaunchKernelGGL(k_sep_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_source(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
+                             const double *rho, hipStream_t s) {
+  for (int c = 0; c < P.nclasses; ++c) {
+    if (sc[c].n_src == 0 || classes[c].nrows == 0) continue;
+    hipLaunchKernelGGL(k_sep_source, dim3(tiles(sc[c].n_src, 256), classes[c].nrows), dim3(256), 0, s, P, S,
+                       classes[c], sc[c].src, sc[c].n_src, rho);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_sep_phi_anal(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_sep_phi_anal, dim3(tiles(std::max(2 * P.lmax, 1), BM) * tiles(P.ntheta, BN), P.nr),
+                     dim3(NTHREADS), 0, s, P, S, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_theta_anal(const PlanDev &P, const SepDev &S, double *ang_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sep_theta_anal, dim3(tiles(P.nr, BM) * tiles(P.lmax + 1, BN), 2 * P.lmax + 1),
+                     dim3(NTHREADS), 0, s, P, S, ang_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_theta_syn(const PlanDev &P, const SepDev &S, hipStream_t s) {
+  hipLaunchKernelGGL(k_sep_theta_syn, dim3(tiles(P.nr, BM) * tiles(P.ntheta, BN), 2 * P.lmax + 1), dim3(NTHREADS),
+                     0, s, P, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
+                              double *phi, hipStream_t s) {
+  hipLaunchKernelGGL(k_sep_phi_syn, dim3(tiles(P.ntheta, BM) * tiles(P.nphi, BN), P.nr), dim3(NTHREADS), 0, s, P, S,
+                     phi);
+  hipError_t e = hipGetLastError();
+  for (int c = 0; c < P.nclasses && e == hipSuccess; ++c) {
+    if (sc[c].n_avg == 0 || classes[c].nrows == 0) continue;
+    hipLaunchKernelGGL(k_sep_block_mean, dim3(tiles(sc[c].n_avg, 256), classes[c].nrows), dim3(256), 0, s, P, S,
+                       classes[c], sc[c].avg, sc[c].n_avg, phi);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace mpole

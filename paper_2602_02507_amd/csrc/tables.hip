@@ -12,15 +12,10 @@
 //                 averages of r^l, r^-(l+1) used by the radial sums
 #include <algorithm>
 
-#include "mpole_internal.h"
+#include "device_util.h"
 
 namespace mpole {
 namespace {
-
-__device__ inline double cos_diff(double t0, double t1) {
-  // cos t0 - cos t1 as a product, exact for thin cells
-  return 2.0 * sin(0.5 * (t0 + t1)) * sin(0.5 * (t1 - t0));
-}
 
 // P~_l^m(x) at x = cos th, s = sin th, by the m-seeded three-term recurrence in l.
 __device__ double ptilde(int l, int m, double x, double s) {
@@ -217,7 +212,8 @@ hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g, hipStream_t s) {
+hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g, bool dense,
+                         hipStream_t s) {
   const int nplm = (P.lmax + 1) * (P.lmax + 2) / 2;
   hipLaunchKernelGGL(k_theta_avg, dim3(grid_for((long)P.ntheta * nplm, 64)), dim3(64), 0, s, P, g);
   hipLaunchKernelGGL(k_trig, dim3(grid_for((long)P.nphi * (P.lmax + 1), 256)), dim3(256), 0, s, P);
@@ -227,10 +223,12 @@ hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const G
   if (e != hipSuccess) return e;
   for (int c = 0; c < P.nclasses; ++c) {
     const ClassDev &C = host_classes[c];
-    hipLaunchKernelGGL(k_block_table, dim3(grid_for((long)C.nblocks_pad * P.namp, 256)), dim3(256), 0, s, P, C);
     hipLaunchKernelGGL(k_block_wsum, dim3(grid_for(C.nblocks, 256)), dim3(256), 0, s, P, C);
-    hipLaunchKernelGGL(k_tsum_part, dim3(grid_for(P.namp, 256), kTsumChunks), dim3(256), 0, s, P, C);
-    hipLaunchKernelGGL(k_tsum_final, dim3(grid_for(P.namp, 256)), dim3(256), 0, s, P, C);
+    if (dense) {   // block-mean kernel table and its weighted column sums
+      hipLaunchKernelGGL(k_block_table, dim3(grid_for((long)C.nblocks_pad * P.namp, 256)), dim3(256), 0, s, P, C);
+      hipLaunchKernelGGL(k_tsum_part, dim3(grid_for(P.namp, 256), kTsumChunks), dim3(256), 0, s, P, C);
+      hipLaunchKernelGGL(k_tsum_final, dim3(grid_for(P.namp, 256)), dim3(256), 0, s, P, C);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

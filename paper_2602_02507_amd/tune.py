@@ -81,7 +81,9 @@ def _device_name(device):
 
 def candidates(precision):
     """(moment candidates, expansion candidates) as partial tunings."""
-    if precision == "fp64":
+    if precision == "fp64sep":   # the separable path has no launch knobs
+        mom, exp = [{"moment_wgs": 0}], [{"expand_tile_m": 0}]
+    elif precision == "fp64":
         mom = [{"moment_wgs": w, "moment_tile_m": 64} for w in (512, 1024, 2048, 4096)]
         exp = [{"expand_tile_m": 64}]
     else:
@@ -138,8 +140,8 @@ def tune_plan(mesh, precision="bf16x3", device="cuda", warmup=1, reps=3, cache=N
         if ms < best_e_ms:
             best_e, best_e_ms = c, ms
     del rho
-    tuning = {"moment_wgs": best_m["moment_wgs"], "moment_tile_m": best_m["moment_tile_m"],
-              "expand_tile_m": best_e["expand_tile_m"]}
+    tuning = {"moment_wgs": best_m.get("moment_wgs", 0), "moment_tile_m": best_m.get("moment_tile_m", 0),
+              "expand_tile_m": best_e.get("expand_tile_m", 0)}
     cache[key] = {"tuning": tuning, "moment_ms": best_m_ms, "expand_ms": best_e_ms,
                   "seconds": time.perf_counter() - t0}
     if log:
