@@ -221,6 +221,78 @@ int mpole_plan_work(mpole_plan plan, double *moment_flops, double *expand_flops,
 int mpole_gradient(mpole_plan plan, const double *phi, double *d_r, double *d_theta, double *d_phi,
                    void *hip_stream);
 
+/*
+ * Coarsening operation of Sec. 2.3 on the plan's blocks: every cell of a
+ * coarsening block receives the volume-weighted mean of the block,
+ * sum_j V_j K_j / sum_j V_j over its member cells j (within a shell the
+ * volumes are proportional to the solid angles); a block of one cell keeps
+ * its value.  This is how the paper averages the Runge-Kutta updates of the
+ * balanced densities; it is also the block mean the solve applies to its
+ * density.  in (read) and out (written) are device [nr][ntheta][nphi] FP64,
+ * owned by the caller; in == out (in place) is allowed, other overlap is
+ * not.  The plan must be bound.  MPOLE_ERR_INVALID for a null plan, in or
+ * out or an unbound plan, MPOLE_ERR_DEVICE for a launch failure.
+ * Asynchronous on hip_stream, no allocation, graph-capturable.
+ */
+int mpole_coarsen(mpole_plan plan, const double *in, double *out, void *hip_stream);
+
+/*
+ * GenASiS spherical mesh with automatic angular coarsening (Sec. 2.1; the
+ * mesh parameters of Sec. 3), built on the host (no HIP call).
+ *
+ * Radius: a core r < r_core of N_core shells of uniform width
+ * dr_min = r_core / N_core, then shells growing by the factor (1 + 1/N_core)
+ * each (dr proportional to r, so the polar/radial aspect ratio stays at its
+ * value at r_core); N_core = N_theta / core_ratio to the nearest integer,
+ * N_r = floor(r_radial * N_theta) (with a 1e-9 guard against the rounding of
+ * the product).  theta: N_theta uniform cells on [0, pi]; phi: 2 N_theta
+ * uniform cells on [0, 2 pi] (dphi = dtheta).  dims 2 has one phi cell and
+ * dims 1 one theta cell as well.
+ *
+ * Coarsening: in each shell, angular cells narrower than the coarsening
+ * width (dr_coarsen, or dr_min when 0) are grouped into aligned blocks of
+ * 2, 4, 8, ... cells per dimension: the theta group is the smallest power of
+ * two c with c r dtheta >= width, then the phi group of each theta block is
+ * the smallest power of two c with c r sin(theta) dphi >= width for every
+ * row of the block (its row nearest the axis decides), r and theta at cell
+ * centres (coordinate midpoints); each group is capped at the largest power
+ * of two dividing the cell count of its dimension.  A cell's coarsening
+ * factors c_i (Sec. 2.3) are its block's group sizes.
+ *
+ * Output in the layout of mpole_mesh: shells with equal block patterns form
+ * one class (numbered by first shell), block ids of a class are numbered by
+ * first member cell (j * nphi + k), so the arrays feed mpole_plan_create
+ * directly.
+ */
+typedef struct {
+  int32_t dims;        /* 1, 2 or 3 */
+  int32_t ntheta;      /* resolution parameter N_theta, 1..65536 */
+  double r_core;       /* core radius, > 0 */
+  double core_ratio;   /* N_theta / N_core, > 0; 0 = 32/25 (the paper's choice) */
+  double r_radial;     /* N_r / N_theta, > 0 */
+  double dr_coarsen;   /* coarsening width, >= 0; 0 = dr_min */
+} mpole_genasis;
+
+/*
+ * Sizes of the GenASiS mesh: shells, theta and phi cells, core shells and
+ * coarsening classes (any output may be NULL).  MPOLE_ERR_INVALID for bad
+ * parameters (N_core or N_r outside 1..2^20 included), MPOLE_ERR_RANGE when
+ * the outer radius overflows.
+ */
+int mpole_genasis_shape(const mpole_genasis *params, int32_t *nr, int32_t *ntheta, int32_t *nphi,
+                        int32_t *ncore, int32_t *nclasses);
+
+/*
+ * Fill caller-owned HOST arrays sized by mpole_genasis_shape:
+ * r_edges[nr+1], theta_edges[ntheta+1], phi_edges[nphi+1], shell_class[nr],
+ * class_block[nclasses][ntheta*nphi]; optionally (NULL = skip) c_theta[nr]
+ * (theta group of each shell) and c_phi[nr][ntheta] (phi group of the block
+ * holding each row).  Errors as mpole_genasis_shape, plus MPOLE_ERR_INVALID
+ * for a null required array; nothing is written on error.
+ */
+int mpole_genasis_build(const mpole_genasis *params, double *r_edges, double *theta_edges, double *phi_edges,
+                        int32_t *shell_class, int32_t *class_block, int32_t *c_theta, int32_t *c_phi);
+
 typedef struct {
   int32_t moment_wgs;
   int32_t moment_tile_m;

@@ -113,6 +113,11 @@ struct SepClass {
   int32_t n_avg;
 };
 
+// Thread-local error message of the C ABI: fail() sets it and returns code,
+// ok() clears it and returns MPOLE_OK (defined in plan.cpp).
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int ok();
+
 // Split precisions: operands are sums of nplanes narrow floats (hi + mid + lo),
 // stored as raw 16-bit patterns.
 enum SplitKind { kSplitBf16x3 = 1, kSplitFp16x2 = 2 };
@@ -136,6 +141,9 @@ hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStrea
 hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
                            hipStream_t s);
+// block volume average of a cell field (host copies of the class views give the spans per class)
+hipError_t launch_coarsen(const PlanDev &P, const ClassDev *host_classes, const double *in, double *out,
+                          hipStream_t s);
 
 // separable FP64 path (single plan)
 hipError_t launch_sep_tables(const PlanDev &P, const SepDev &S, hipStream_t s);

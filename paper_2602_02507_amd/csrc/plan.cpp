@@ -16,7 +16,7 @@
 
 using namespace mpole;
 
-namespace {
+namespace mpole {
 
 thread_local std::string g_error;
 
@@ -34,6 +34,10 @@ int ok() {
   g_error.clear();
   return MPOLE_OK;
 }
+
+}  // namespace mpole
+
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -707,6 +711,15 @@ int mpole_gradient(mpole_plan p, const double *phi, double *d_r, double *d_theta
   if (!d_r && !d_theta && !d_phi) return ok();
   const hipError_t e = launch_gradient(p->dev, phi, d_r, d_theta, d_phi, p->phi_periodic, (hipStream_t)stream);
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "gradient launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int mpole_coarsen(mpole_plan p, const double *in, double *out, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!p->bound) return fail(MPOLE_ERR_INVALID, "plan is not bound to a workspace");
+  if (!in || !out) return fail(MPOLE_ERR_INVALID, "in or out is null");
+  const hipError_t e = launch_coarsen(p->dev, p->cdev.data(), in, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "coarsen launch failed: %s", hipGetErrorString(e));
   return ok();
 }
 

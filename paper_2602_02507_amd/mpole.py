@@ -22,7 +22,8 @@ STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE
 # every entry point include/mpole.h declares
 EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_plan_workspace_bytes",
            "mpole_plan_nmodes", "mpole_plan_bind", "mpole_solve", "mpole_plan_copy_table",
-           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_gradient", "mpole_plan_tune",
+           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_gradient", "mpole_coarsen",
+           "mpole_genasis_shape", "mpole_genasis_build", "mpole_plan_tune",
            "mpole_plan_get_tuning", "mpole_plan_configure", "mpole_plan_moment_wgs", "mpole_plan_destroy",
            "mpole_batch_create", "mpole_batch_tune", "mpole_batch_configure", "mpole_batch_workspace_bytes",
            "mpole_batch_bind",
@@ -51,6 +52,12 @@ class MpoleError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (STATUS.get(code, code), msg))
         self.code = code
+
+
+class GenasisC(ctypes.Structure):
+    """GenASiS mesh parameters (mpole_genasis)."""
+    _fields_ = [("dims", ctypes.c_int32), ("ntheta", ctypes.c_int32), ("r_core", ctypes.c_double),
+                ("core_ratio", ctypes.c_double), ("r_radial", ctypes.c_double), ("dr_coarsen", ctypes.c_double)]
 
 
 class MeshC(ctypes.Structure):
@@ -94,6 +101,10 @@ def lib():
         dptr = ctypes.POINTER(ctypes.c_double)
         L.mpole_plan_work.argtypes = [vp, dptr, dptr, dptr]
         L.mpole_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mpole_coarsen.argtypes = [vp, vp, vp, vp]
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.mpole_genasis_shape.argtypes = [ctypes.POINTER(GenasisC), ip, ip, ip, ip, ip]
+        L.mpole_genasis_build.argtypes = [ctypes.POINTER(GenasisC), dptr, dptr, dptr, ip, ip, ip, ip]
         L.mpole_plan_tune.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_plan_configure.argtypes = [vp, ctypes.c_int32]
@@ -123,6 +134,26 @@ def _ptr(a, ctype):
 
 def _dev_ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def genasis_mesh(ntheta, r_core, r_radial, dims=3, core_ratio=0.0, dr_coarsen=0.0):
+    """GenASiS mesh with automatic angular coarsening (mpole_genasis_build).
+    Returns a dict of host arrays: r_edges, theta_edges, phi_edges,
+    shell_class, class_block [nclasses][ntheta*nphi], c_theta [nr],
+    c_phi [nr][ntheta], and the core shell count ncore."""
+    g = GenasisC(int(dims), int(ntheta), float(r_core), float(core_ratio), float(r_radial), float(dr_coarsen))
+    n = [ctypes.c_int32() for _ in range(5)]
+    _check(lib().mpole_genasis_shape(ctypes.byref(g), *[ctypes.byref(x) for x in n]))
+    nr, nt, nph, ncore, ncls = (x.value for x in n)
+    out = dict(r_edges=np.empty(nr + 1), theta_edges=np.empty(nt + 1), phi_edges=np.empty(nph + 1),
+               shell_class=np.empty(nr, np.int32), class_block=np.empty((ncls, nt * nph), np.int32),
+               c_theta=np.empty(nr, np.int32), c_phi=np.empty((nr, nt), np.int32))
+    d, i = ctypes.c_double, ctypes.c_int32
+    _check(lib().mpole_genasis_build(ctypes.byref(g), _ptr(out["r_edges"], d), _ptr(out["theta_edges"], d),
+                                     _ptr(out["phi_edges"], d), _ptr(out["shell_class"], i),
+                                     _ptr(out["class_block"], i), _ptr(out["c_theta"], i), _ptr(out["c_phi"], i)))
+    out["ncore"] = ncore
+    return out
 
 
 def make_mesh(r_edges, theta_edges, phi_edges, lmax, shell_class=None, class_block=None, G=1.0,
@@ -277,6 +308,18 @@ class Plan(HostPlan):
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         _check(lib().mpole_gradient(self.handle, _dev_ptr(phi), *[_dev_ptr(t) for t in outs], ctypes.c_void_p(s)))
         return tuple(outs)
+
+    def coarsen(self, field, out=None, stream=None):
+        """Block volume average of a cell field over this mesh's coarsening
+        blocks (mpole_coarsen); out may be field itself (in place)."""
+        import torch
+        self._check_tensor(field, self.shape, "field")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._check_tensor(out, self.shape, "coarsen output")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_coarsen(self.handle, _dev_ptr(field), _dev_ptr(out), ctypes.c_void_p(s)))
+        return out
 
     def table(self, cls=0):
         """FP64 block-mean kernel table of a coarsening class, [nblocks][nAM] (host numpy)."""

@@ -1,0 +1,120 @@
+"""GPU parity on GenASiS meshes with automatic coarsening (Sec. 2.1) and of
+the coarsening operation (Sec. 2.3): mpole_coarsen against the oracle's
+block volume average (GenASiS maps, rectangular and arbitrary block maps,
+in place), and the solve on a GenASiS mesh in every precision against the
+oracle's solve (FP64 paths 1e-12, split precisions 1e-6).  The input meshes
+come from the oracle's builder (the library's builder is bit-identical to
+it, checked on the host)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import genasis as og
+from paper_2602_02507_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def genasis_case(ntheta, dims, lmax, r_radial=3.68):
+    g = og.mesh(ntheta, 0.25, r_radial, dims=dims)
+    m = wl.Mesh(g["r_edges"], g["theta_edges"], g["phi_edges"], lmax, g["shell_class"], g["class_block"],
+                name="genasis%d_%dd" % (ntheta, dims))
+    return m
+
+
+def coarsen_gpu(mesh, f, inplace=False):
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    plan = mpole.Plan.from_mesh(mesh, precision="fp64")
+    t = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    out = plan.coarsen(t, out=t if inplace else None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def coarsen_ref(mesh, f):
+    sc = mesh.shell_class if mesh.shell_class is not None else np.zeros(mesh.nr, np.int32)
+    cb = mesh.class_block if mesh.class_block is not None else np.arange(mesh.ntheta * mesh.nphi, dtype=np.int32)[None]
+    return og.coarsen(f, mesh.r_edges, mesh.theta_edges, mesh.phi_edges, sc, cb)
+
+
+COARSEN_CASES = [("genasis32_3d", 32, 3), ("genasis64_2d", 64, 2), ("genasis48_3d", 48, 3)]
+
+
+@pytest.mark.parametrize("name,nt,dims", COARSEN_CASES, ids=[c[0] for c in COARSEN_CASES])
+@pytest.mark.parametrize("inplace", [False, True])
+def test_coarsen_matches_oracle_on_genasis_meshes(name, nt, dims, inplace):
+    m = genasis_case(nt, dims, 4)
+    f = wl.random_density(11, m.shape, positive=False)
+    got = coarsen_gpu(m, f, inplace)
+    ref = coarsen_ref(m, f)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(name, "inplace" if inplace else "", "max rel %.3e" % err)
+    assert err <= 1e-14, err
+    # cells that are blocks of their own are copied exactly
+    for i in range(m.nr):
+        ids = m.class_block[m.shell_class[i]]
+        single = (np.bincount(ids)[ids] == 1).reshape(m.ntheta, m.nphi)
+        assert (got[i][single] == f[i][single]).all()
+
+
+def test_coarsen_rectangular_and_arbitrary_block_maps():
+    m = wl.production_mesh(4, nr=40, ntheta=32, nphi=64)
+    m.shell_class, m.class_block = wl.production_merge(40, 32, 64, inner_shells=8)
+    f = wl.random_density(5, m.shape)
+    assert np.max(np.abs(coarsen_gpu(m, f) - coarsen_ref(m, f))) <= 1e-14 * np.abs(f).max()
+    r = wl.random_mesh(9, 30, 12, 24, 4)
+    r.shell_class, r.class_block = wl.random_merge(10, 30, 12, 24)
+    f = wl.random_density(6, r.shape, positive=False)
+    assert np.max(np.abs(coarsen_gpu(r, f) - coarsen_ref(r, f))) <= 1e-14 * np.abs(f).max()
+    # no coarsening classes: a plain copy
+    u = wl.random_mesh(12, 7, 5, 9, 2)
+    f = wl.random_density(7, u.shape, positive=False)
+    assert (coarsen_gpu(u, f) == f).all()
+
+
+SOLVE_CASES = [("fp64", 1e-12), ("fp64sep", 1e-12), ("bf16x3", 1e-6), ("fp16x2", 1e-6)]
+
+
+@pytest.fixture(scope="module")
+def genasis_solve_case():
+    m = genasis_case(32, 3, 12)
+    rho = wl.production_density(m, seed=3)
+    ref = oracle.solve(rho=rho, **m.oracle_kwargs())
+    return m, rho, ref
+
+
+@pytest.mark.parametrize("precision,tol", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_on_genasis_mesh_matches_oracle(genasis_solve_case, precision, tol):
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    m, rho, ref = genasis_solve_case
+    plan = mpole.Plan.from_mesh(m, precision=precision)
+    out = plan.solve(torch.from_numpy(rho).cuda())
+    torch.cuda.synchronize()
+    phi = out["phi"].cpu().numpy()
+    err = np.max(np.abs(phi - ref["phi"]) / np.abs(ref["phi"]))
+    print(precision, "classes", m.class_block.shape[0], "max rel %.3e" % err)
+    assert err <= tol, err
+
+
+def test_solve_of_coarsened_density_is_the_same_solve(genasis_solve_case):
+    """A block is one cell of the solve: solving rho or its block volume
+    average gives the same potential (reading of the merged-cell solve)."""
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    m, rho, _ = genasis_solve_case
+    plan = mpole.Plan.from_mesh(m, precision="fp64sep")
+    t = torch.from_numpy(rho).cuda()
+    a = plan.solve(t)["phi"]
+    b = plan.solve(plan.coarsen(t))["phi"]
+    torch.cuda.synchronize()
+    err = ((a - b).abs().max() / a.abs().max()).item()
+    assert err <= 1e-13, err
