@@ -9,7 +9,8 @@
 // most of a shell away from the origin and the axis) is a coalesced copy;
 // otherwise each thread gathers, averages and scatters whole blocks, so a
 // thread reads all members of its block before writing any and in-place
-// calls (in == out) are safe.  HBM-bound: 8 B read and 8 B written per cell.
+// calls (in == out) are safe; blocks of more than kLargeBlock cells get a
+// workgroup each (launch_large).  HBM-bound: 8 B read and 8 B written per cell.
 #include <algorithm>
 
 #include "device_util.h"
@@ -22,6 +23,7 @@ constexpr int CO_THREADS = 256, CO_UNROLL = kPackSpan / CO_THREADS;
 __global__ __launch_bounds__(CO_THREADS) void k_coarsen(PlanDev P, const double *in_, double *out_) {
   const int i = blockIdx.y, sp = blockIdx.x;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
+  if (C.bands != nullptr) return;            // banded classes: launch_bands
   if (sp * kPackSpan >= C.nblocks) return;   // span past this class's blocks
   const auto in = gmem(in_ + (size_t)i * P.ncell);
   const auto out = gmem(out_ + (size_t)i * P.ncell);
@@ -43,7 +45,6 @@ __global__ __launch_bounds__(CO_THREADS) void k_coarsen(PlanDev P, const double 
     return;
   }
   const auto moff = gmem(C.moff), mem = gmem(C.mem);
-  const auto th = gmem(P.theta_edges), ph = gmem(P.phi_edges);
   for (int u = 0; u < CO_UNROLL; ++u) {
     const int b = b0 + u * CO_THREADS;
     if (b >= C.nblocks) break;
@@ -53,16 +54,10 @@ __global__ __launch_bounds__(CO_THREADS) void k_coarsen(PlanDev P, const double 
       out[q] = in[q];
       continue;
     }
+    if (e1 - e0 > kLargeBlock) continue;   // one workgroup each, in launch_large
     double num = 0.0, den = 0.0;
-    for (int e = e0; e < e1; ++e) {
-      const int q = mem[e];
-      const int j = q / P.nphi, k = q - j * P.nphi;
-      const double w = cos_diff(th[j], th[j + 1]) * (ph[k + 1] - ph[k]);
-      num += w * in[q];
-      den += w;
-    }
-    const double mean = num / den;
-    for (int e = e0; e < e1; ++e) out[mem[e]] = mean;
+    block_wsum(C, P.dom, in_ + (size_t)i * P.ncell, P.nphi, b, num, den);
+    block_fill(C, out_ + (size_t)i * P.ncell, P.nphi, b, num / den);
   }
 }
 
@@ -75,7 +70,10 @@ hipError_t launch_coarsen(const PlanDev &P, const ClassDev *host_classes, const 
   const unsigned spans = (unsigned)((nb + kPackSpan - 1) / kPackSpan);
   if (spans == 0 || P.nr == 0) return hipSuccess;
   hipLaunchKernelGGL(k_coarsen, dim3(spans, (unsigned)P.nr), dim3(CO_THREADS), 0, s, P, in, out);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_bands(P, kBandCoarsen, in, out, s);
+  if (e == hipSuccess) e = launch_large(P, kLargeMean, in, out, s);
+  return e;
 }
 
 }  // namespace mpole

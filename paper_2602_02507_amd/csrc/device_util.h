@@ -99,6 +99,54 @@ __device__ inline double block_source(const ClassDev &C, const double *w_, const
   return s;
 }
 
+// Solid-angle weighted sums over the members of block b of a shell row x:
+// num += sum dOmega x, den += sum dOmega.  Rectangular blocks are walked row
+// by row with direct indexing, others through the member list.
+__device__ inline void block_wsum(const ClassDev &C, const double *dom_, const double *x_, int nphi, int b,
+                                  double &num, double &den) {
+  const auto dom = gmem(dom_), x = gmem(x_);
+  if (C.rect != nullptr) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 r = gmem(reinterpret_cast<const i4 *>(C.rect))[b];   // (j0, k0, nj, nk)
+    for (int j = 0; j < r.z; ++j) {
+      const int q0 = (r.x + j) * nphi + r.y;
+      for (int k = 0; k < r.w; ++k) {
+        const double w = dom[q0 + k];
+        num += w * x[q0 + k];
+        den += w;
+      }
+    }
+  } else {
+    const auto moff = gmem(C.moff), mem = gmem(C.mem);
+    for (int e = moff[b]; e < moff[b + 1]; ++e) {
+      const int q = mem[e];
+      const double w = dom[q];
+      num += w * x[q];
+      den += w;
+    }
+  }
+}
+
+// Writes v to every member cell of block b of a shell row out.
+__device__ inline void block_fill(const ClassDev &C, double *out_, int nphi, int b, double v) {
+  const auto out = gmem(out_);
+  if (C.rect != nullptr) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 r = gmem(reinterpret_cast<const i4 *>(C.rect))[b];
+    for (int j = 0; j < r.z; ++j)
+      for (int k = 0; k < r.w; ++k) out[(r.x + j) * nphi + r.y + k] = v;
+  } else {
+    const auto moff = gmem(C.moff), mem = gmem(C.mem);
+    for (int e = moff[b]; e < moff[b + 1]; ++e) out[mem[e]] = v;
+  }
+}
+
+// Source sum of a block of more than kLargeBlock cells of shell i, computed
+// by launch_large(kLargeSum) before the packing kernel.
+__device__ inline double large_source(const PlanDev &P, const ClassDev &C, int i, int b) {
+  return gmem(P.lsum)[ld_const(P.lbase + i) + gmem(C.lidx)[b]];
+}
+
 // Workgroup sum in a fixed order (butterfly within each wavefront, then the
 // wavefront totals in order); red holds blockDim.x/64 doubles.
 __device__ inline double block_sum(double v, double *red) {

@@ -195,7 +195,8 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
 
   // epilogue: the block potential goes to every member cell of the block.
   // This lane's two blocks are resolved once for all its rows (rect: first
-  // cell and extent; CSR: member range in bcell .. bnj).
+  // cell and extent; CSR: member range in bcell .. bnj); a block of more than
+  // kLargeBlock cells only gets its first cell here, launch_large copies it.
   bool bok[2];
   int bcell[2] = {0, 0}, bnj[2] = {0, 0}, bnk[2] = {0, 0};
 #pragma unroll
@@ -208,9 +209,11 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
       bcell[u] = rect[4 * b] * P.nphi + rect[4 * b + 1];
       bnj[u] = rect[4 * b + 2];
       bnk[u] = rect[4 * b + 3];
+      if (bnj[u] * bnk[u] > kLargeBlock) bnj[u] = bnk[u] = 1;   // first cell only; launch_large broadcasts
     } else {
       bcell[u] = gmem(C.moff)[b];
       bnj[u] = gmem(C.moff)[b + 1];
+      if (bnj[u] - bcell[u] > kLargeBlock) bnj[u] = bcell[u] + 1;
     }
   }
   const auto mem = gmem(C.mem);

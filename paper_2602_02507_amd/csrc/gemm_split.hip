@@ -226,7 +226,8 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   const auto part = gmem(reinterpret_cast<float *>(C.partial));
   // this lane's two expansion blocks, read once for all its rows: l = 0
   // table column and member cells (rect: first cell and extent; CSR: member
-  // range in bcell .. bnj)
+  // range in bcell .. bnj; a block of more than kLargeBlock cells only gets
+  // its first cell here, launch_large copies it to the rest)
   bool bok[2] = {false, false};
   double bt0[2] = {0.0, 0.0};
   int bcell[2] = {0, 0}, bnj[2] = {0, 0}, bnk[2] = {0, 0};
@@ -241,9 +242,11 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
         bcell[b] = rect[4 * blk] * P.nphi + rect[4 * blk + 1];
         bnj[b] = rect[4 * blk + 2];
         bnk[b] = rect[4 * blk + 3];
+        if (bnj[b] * bnk[b] > kLargeBlock) bnj[b] = bnk[b] = 1;   // first cell only; launch_large broadcasts
       } else {
         bcell[b] = moff[blk];
         bnj[b] = moff[blk + 1];
+        if (bnj[b] - bcell[b] > kLargeBlock) bnj[b] = bcell[b] + 1;
       }
     }
   }

@@ -14,6 +14,14 @@ constexpr int kPadF64 = 16;
 constexpr int kPackSpan = 1024;   // blocks of one shell per packing workgroup
 constexpr int kTsumChunks = 64;   // block chunks of the bind-time column sums of a table
 constexpr int kShiftSamples = 4;  // blocks sampled per shell for its mean source density
+// Blocks with more member cells than this are reduced and broadcast by one
+// workgroup each (kernels that give a block to one thread skip them).
+constexpr int kLargeBlock = 64;
+// Members per workgroup of a large block (larger blocks are split into
+// chunks whose partial sums are combined in chunk order).
+constexpr int kLargeChunk = 4096;
+// Rows of single cells copied per workgroup by the band kernel.
+constexpr int kBandCopyRows = 8;
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.
 struct GaussRule {
@@ -28,6 +36,14 @@ struct ClassDev {
   const int32_t *mem;    // [ncell] member fine-cell index j*nphi+k, ascending per block
   const int4 *rect;      // [nblocks] (j0, k0, nj, nk) when every block is a theta-phi rectangle, else null
   const int32_t *span0;  // [ceil(nblocks / kPackSpan)] first cell of a packing span of consecutive single cells, else -1
+  const int32_t *lidx;   // [nblocks] index of a large block in the class's large-block list, else -1; null if none
+  // theta bands when every block is an nj x nk rectangle at a phi column
+  // that is a multiple of nk, uniform within the band: (j0, nj, nk, kind),
+  // kind 0 = single cells (up to kBandCopyRows rows), 1 = blocks of at most
+  // kLargeBlock cells with nk a power of two <= 64, 2 = larger blocks; null
+  // for other block maps
+  const int4 *bands;
+  int32_t nbands;
   double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, zero padded
   double *tcol0;         // [nblocks_pad] copy of the table's l = 0 column (contiguous)
   uint16_t *tplanes;     // [nplanes][nblocks_pad][namp] split planes of table (expansion operand)
@@ -55,6 +71,7 @@ struct PlanDev {
   double *pavg;      // [ntheta][nplm] theta-cell averages of P~_l^m
   double *trig;      // [nphi][2*(lmax+1)] (<cos m ph>, <sin m ph>)
   double *weight;    // [ncell] 4 pi G dOmega
+  double *dom;       // [ncell] dOmega, the solid angle of each angular cell
   double *jr, *ji;   // [nr][lmax+1] exact shell integrals of r^(2+l), r^(1-l)
   double *rr, *ri;   // [nr][lmax+1] volume-averaged r^l, r^-(l+1)
   double *ang;       // [nr][namp] reduced angular moments
@@ -70,6 +87,19 @@ struct PlanDev {
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
   double *shift;            // [nr] per-shell mean source density removed before splitting (split precisions)
   double *tsum_part;        // [kTsumChunks][namp] bind-time partial sums of tsum
+  // blocks with more than kLargeBlock members, over all shells: items
+  // (shell, block) in shell order, the first item of each shell, and the
+  // block sources sum 4 pi G dOmega rho of the dense paths; each item is
+  // split into chunks of at most kLargeChunk members: (item, chunk of the
+  // item, chunks of the item, first chunk of the item) and their partial
+  // (weighted sum, weight) pairs
+  const int2 *litems;       // [n_litems]
+  const int32_t *lbase;     // [nr + 1]
+  double *lsum;             // [n_litems] (dense paths), or null
+  const int4 *lchunks;      // [n_lchunks]
+  double *lpart;            // [n_lchunks][2]
+  int32_t n_litems, n_lchunks;
+  int32_t max_bands;        // most bands of any class
 };
 
 // Phases of one solve; a launch of phase h covers the workgroups
@@ -94,18 +124,22 @@ struct BatchDev {
 
 // Separable FP64 path: bind-time transform tables and per-solve intermediates
 // (trig modes t = 0, 2m-1 (cos), 2m (sin), padded to tpad; t-major per shell).
+struct SepClass;
 struct SepDev {
   int32_t tpad;
+  int32_t max_src, max_avg;   // longest per-class block lists below
   double *tw;              // [2][tpad][nphi]: dphi_k <trig_t>_k, then <trig_t>_k
   double *pw;              // [L+1][ntheta][L+1]: 4 pi G dcos_j <P~_{l'+m,m}>_j as [m][j][l']
   double *pt;              // [L+1][L+1][ntheta]: <P~_{l'+m,m}>_j as [m][l'][j]
   double *shat;            // [nr][ntheta][nphi] block-mean density on rows with a merged block
   const uint8_t *rowalt;   // [nr][ntheta] 1 where the row reads shat
   double *f, *g;           // [nr][tpad][ntheta] phi analysis, theta synthesis
-  double *dom;             // [ntheta][nphi] solid angle of each cell
+  const double *dom;       // [ntheta][nphi] solid angle of each cell (the plan's table)
+  const SepClass *cls;     // [nclasses] per-class block lists (device copy)
 };
 // Per class: blocks on rows with a merged block (source means), and blocks
-// with more than one member (potential means); device lists.
+// with more than one member (potential means); device lists, without the
+// blocks of more than kLargeBlock members (those go through launch_large).
 struct SepClass {
   const int32_t *src;
   int32_t n_src;
@@ -141,19 +175,30 @@ hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStrea
 hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
                            hipStream_t s);
-// block volume average of a cell field (host copies of the class views give the spans per class)
+// block volume average of a cell field (host copies of the class views give the spans per class);
+// blocks of more than kLargeBlock members are left to launch_large
 hipError_t launch_coarsen(const PlanDev &P, const ClassDev *host_classes, const double *in, double *out,
                           hipStream_t s);
+// one workgroup per large block of every shell (P.litems):
+//   kLargeMean   out = solid-angle weighted block mean of in, on every member (in == out allowed)
+//   kLargeSum    P.lsum[item] = sum over members of P.weight * in
+//   kLargeBcast  out on every member = out at the block's first member
+enum LargeMode { kLargeMean = 0, kLargeSum = 1, kLargeBcast = 2 };
+hipError_t launch_large(const PlanDev &P, int mode, const double *in, double *out, hipStream_t s);
+// the classes with theta bands: kBandCoarsen writes the block mean of in
+// (solid-angle weights) to every cell of out, copying single cells;
+// kBandMean only does the bands of merged blocks of at most kLargeBlock
+// cells (in == out allowed)
+enum BandMode { kBandCoarsen = 0, kBandMean = 1 };
+hipError_t launch_bands(const PlanDev &P, int mode, const double *in, double *out, hipStream_t s);
 
 // separable FP64 path (single plan)
 hipError_t launch_sep_tables(const PlanDev &P, const SepDev &S, hipStream_t s);
-hipError_t launch_sep_source(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
-                             const double *rho, hipStream_t s);
+hipError_t launch_sep_source(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s);
 hipError_t launch_sep_phi_anal(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s);
 hipError_t launch_sep_theta_anal(const PlanDev &P, const SepDev &S, double *ang_out, hipStream_t s);
 hipError_t launch_sep_theta_syn(const PlanDev &P, const SepDev &S, hipStream_t s);
-hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
-                              double *phi, hipStream_t s);
+hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s);
 
 hipError_t launch_moment_f64(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_expand_f64(const BatchDev &B, int wgs, hipStream_t s);

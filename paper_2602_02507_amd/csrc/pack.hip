@@ -98,15 +98,18 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
       if (b < C.nblocks && (r[u].z != 1 || r[u].w != 1)) {
-        s[u] = block_source(C, w, src, P.nphi, b);
+        s[u] = r[u].z * r[u].w > kLargeBlock ? large_source(P, C, i, b) : block_source(C, w, src, P.nphi, b);
         wb[u] = gmem(C.wsum)[b];
       }
     }
   } else {
+    const auto moff = gmem(C.moff);
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
       const int b = b0 + u * PACK_THREADS;
-      s[u] = (b < C.nblocks) ? block_source(C, w, src, P.nphi, b) : 0.0;
+      s[u] = 0.0;
+      if (b < C.nblocks)
+        s[u] = moff[b + 1] - moff[b] > kLargeBlock ? large_source(P, C, i, b) : block_source(C, w, src, P.nphi, b);
       wb[u] = (b < C.nblocks && MODE != 0) ? gmem(C.wsum)[b] : 0.0;
     }
   }

@@ -79,6 +79,9 @@ struct ClassHost {
   std::vector<int32_t> rect;  // 4 per block when every block is a rectangle in (j, k)
   std::vector<int32_t> span0; // per packing span: first cell when the span is a run of single cells, else -1
   std::vector<int32_t> sep_src, sep_avg;   // separable path: blocks on merged rows, blocks with > 1 member
+  std::vector<int32_t> large, lidx;        // blocks of more than kLargeBlock cells; index in `large` per block
+  std::vector<int32_t> bands;              // theta bands (j0, nj, nk, kind), or empty
+  size_t off_lidx = 0, off_bands = 0;
   size_t off_sep_src = 0, off_sep_avg = 0;
   size_t off_span0 = 0;
   size_t off_rect = 0;
@@ -114,6 +117,11 @@ struct mpole_plan_t {
   size_t off_tw = 0, off_pw = 0, off_pt = 0, off_shat = 0, off_rowalt = 0, off_f = 0, off_g = 0, off_dom = 0;
   SepDev sdev{};
   std::vector<SepClass> scls;
+  size_t off_scls = 0;
+  int max_src = 0, max_avg = 0;   // separable: longest per-class block lists
+  // blocks of more than kLargeBlock cells over all shells: (shell, block) items and each shell's first item
+  std::vector<int32_t> litems, lbase, lchunks;
+  size_t off_litems = 0, off_lbase = 0, off_lsum = 0, off_lchunks = 0, off_lpart = 0;
   size_t off_shift = 0, off_tsum_part = 0;
   int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
   size_t off_plandev = 0, off_prefix = 0;
@@ -274,6 +282,36 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       C.rect[4 * b + 3] = k1 - k0 + 1;
     }
     if (!rect_ok) C.rect.clear();
+    // theta bands (the layout power-of-two coarsening produces): rows
+    // [j, j + nj) whose blocks are all nj x nk rectangles at phi columns that
+    // are multiples of nk; single-cell rows are merged into copy bands
+    C.bands.clear();
+    if (!C.rect.empty()) {
+      bool ok = true;
+      for (int j = 0; j < p->nt && ok;) {
+        const int b = id[(size_t)j * p->np];
+        const int nj = C.rect[4 * b + 2], nk = C.rect[4 * b + 3];
+        ok = C.rect[4 * b] == j && C.rect[4 * b + 1] == 0 && p->np % nk == 0 && j + nj <= p->nt;
+        for (int jj = j; jj < j + nj && ok; ++jj)
+          for (int k = 0; k < p->np && ok; ++k) {
+            const int bb = id[(size_t)jj * p->np + k];
+            ok = C.rect[4 * bb] == j && C.rect[4 * bb + 1] == k / nk * nk && C.rect[4 * bb + 2] == nj &&
+                 C.rect[4 * bb + 3] == nk;
+          }
+        const int kind = nj * nk == 1 ? 0 : nj * nk > kLargeBlock ? 2 : 1;
+        if (kind == 1 && (nk > 64 || (nk & (nk - 1)) != 0)) ok = false;
+        if (!ok) break;
+        const size_t nb4 = C.bands.size();
+        if (kind == 0 && nb4 > 0 && C.bands[nb4 - 1] == 0 && C.bands[nb4 - 3] < kBandCopyRows &&
+            C.bands[nb4 - 4] + C.bands[nb4 - 3] == j) {
+          ++C.bands[nb4 - 3];
+        } else {
+          C.bands.insert(C.bands.end(), {j, nj, nk, kind});
+        }
+        j += nj;
+      }
+      if (!ok) C.bands.clear();
+    }
     // packing spans whose blocks are single cells at consecutive cell indices:
     // span0[s] = cell of the span's first block, else -1
     const int nspan = (nb + kPackSpan - 1) / kPackSpan;
@@ -288,6 +326,39 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     }
     C.n_tiles_mom = (p->namp + p->tile_n - 1) / p->tile_n;
     C.n_tiles_exp = (C.nblocks + p->tile_n - 1) / p->tile_n;
+    // blocks too large for one thread: a workgroup each (launch_large)
+    C.large.clear();
+    for (int b = 0; b < nb; ++b)
+      if (C.moff[b + 1] - C.moff[b] > kLargeBlock) C.large.push_back(b);
+    C.lidx.clear();
+    if (!C.large.empty()) {
+      C.lidx.assign(nb, -1);
+      for (size_t l = 0; l < C.large.size(); ++l) C.lidx[C.large[l]] = (int32_t)l;
+    }
+  }
+  p->litems.clear();
+  p->lbase.assign(p->nr + 1, 0);
+  for (int i = 0; i < p->nr; ++i) {
+    p->lbase[i] = (int32_t)(p->litems.size() / 2);
+    for (int b : p->cls[p->shell_class[i]].large) {
+      p->litems.push_back(i);
+      p->litems.push_back(b);
+    }
+  }
+  p->lbase[p->nr] = (int32_t)(p->litems.size() / 2);
+  // chunks of at most kLargeChunk members: (item, chunk, chunks of the item, first chunk of the item)
+  p->lchunks.clear();
+  for (size_t it = 0; it < p->litems.size() / 2; ++it) {
+    const ClassHost &C = p->cls[p->shell_class[p->litems[2 * it]]];
+    const int b = p->litems[2 * it + 1];
+    const int n = (C.moff[b + 1] - C.moff[b] + kLargeChunk - 1) / kLargeChunk;
+    const int first = (int)(p->lchunks.size() / 4);
+    for (int c = 0; c < n; ++c) {
+      p->lchunks.push_back((int32_t)it);
+      p->lchunks.push_back(c);
+      p->lchunks.push_back(n);
+      p->lchunks.push_back(first);
+    }
   }
   if (p->sep) {
     // rows holding a merged block read the block-mean density; their blocks
@@ -301,10 +372,14 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
           for (int e = C.moff[b]; e < C.moff[b + 1]; ++e) merged[c][C.mem[e] / p->np] = 1;
       C.sep_src.clear();
       C.sep_avg.clear();
-      for (int b = 0; b < C.nblocks; ++b) {
-        if (C.moff[b + 1] - C.moff[b] > 1) C.sep_avg.push_back(b);
+      for (int b = 0; b < C.nblocks && C.bands.empty(); ++b) {   // banded classes: launch_bands
+        const int n = C.moff[b + 1] - C.moff[b];
+        if (n > kLargeBlock) continue;   // launch_large
+        if (n > 1) C.sep_avg.push_back(b);
         if (merged[c][C.mem[C.moff[b]] / p->np]) C.sep_src.push_back(b);
       }
+      p->max_src = std::max(p->max_src, (int)C.sep_src.size());
+      p->max_avg = std::max(p->max_avg, (int)C.sep_avg.size());
     }
     for (int i = 0; i < p->nr; ++i)
       for (int j = 0; j < p->nt; ++j) {
@@ -381,6 +456,7 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->off_pavg = take(sizeof(double) * (size_t)p->nt * nplm);
   p->off_trig = take(sizeof(double) * (size_t)p->np * 2 * (p->L + 1));
   p->off_weight = take(sizeof(double) * (size_t)p->ncell);
+  p->off_dom = take(sizeof(double) * (size_t)p->ncell);
   p->off_jr = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
   p->off_ji = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
   p->off_rr = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
@@ -400,6 +476,11 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->off_max = take(sizeof(double) * (size_t)p->nr * p->mono_stride);
   p->off_shift = take(sizeof(double) * (size_t)p->nr);
   p->off_tsum_part = take(sizeof(double) * (size_t)kTsumChunks * p->namp);
+  p->off_litems = take(sizeof(int32_t) * p->litems.size());
+  p->off_lbase = take(sizeof(int32_t) * p->lbase.size());
+  p->off_lsum = take(p->sep ? 0 : sizeof(double) * (p->litems.size() / 2));
+  p->off_lchunks = take(sizeof(int32_t) * p->lchunks.size());
+  p->off_lpart = take(sizeof(double) * 2 * (p->lchunks.size() / 4));
   for (auto &C : p->cls) {
     const size_t nrows = C.rows.size();
     C.off_rows = take(sizeof(int32_t) * std::max<size_t>(nrows, 1));
@@ -407,6 +488,8 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_mem = take(sizeof(int32_t) * p->ncell);
     C.off_rect = take(sizeof(int32_t) * C.rect.size());
     C.off_span0 = take(sizeof(int32_t) * C.span0.size());
+    C.off_lidx = take(sizeof(int32_t) * C.lidx.size());
+    C.off_bands = take(sizeof(int32_t) * C.bands.size());
     const size_t dense = p->sep ? 0 : 1;   // the separable path has no block x mode tables
     C.off_table = take(dense * sizeof(double) * (size_t)C.nblocks_pad * p->namp);
     C.off_tcol0 = take(dense * sizeof(double) * (size_t)C.nblocks_pad);
@@ -431,7 +514,7 @@ void layout_plan(mpole_plan_t *p, int target) {
     p->off_rowalt = take(nrt);
     p->off_f = take(sizeof(double) * nrt * p->tpad);
     p->off_g = take(sizeof(double) * nrt * p->tpad);
-    p->off_dom = take(sizeof(double) * (size_t)p->ncell);
+    p->off_scls = take(sizeof(SepClass) * p->ncls);
   }
   // the single-plan view of the batched kernels: one device plan, phase prefix sums
   p->off_plandev = take(sizeof(PlanDev));
@@ -548,6 +631,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   D.pavg = (double *)(ws + p->off_pavg);
   D.trig = (double *)(ws + p->off_trig);
   D.weight = (double *)(ws + p->off_weight);
+  D.dom = (double *)(ws + p->off_dom);
   D.jr = (double *)(ws + p->off_jr);
   D.ji = (double *)(ws + p->off_ji);
   D.rr = (double *)(ws + p->off_rr);
@@ -563,6 +647,13 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   D.mono_stride = p->mono_stride;
   D.shift = (double *)(ws + p->off_shift);
   D.tsum_part = (double *)(ws + p->off_tsum_part);
+  D.litems = (const int2 *)(ws + p->off_litems);
+  D.lbase = (const int32_t *)(ws + p->off_lbase);
+  D.lsum = p->sep ? nullptr : (double *)(ws + p->off_lsum);
+  D.n_litems = (int32_t)(p->litems.size() / 2);
+  D.lchunks = (const int4 *)(ws + p->off_lchunks);
+  D.lpart = (double *)(ws + p->off_lpart);
+  D.n_lchunks = (int32_t)(p->lchunks.size() / 4);
   p->cdev.assign(p->ncls, ClassDev{});
   for (int c = 0; c < p->ncls; ++c) {
     const ClassHost &H = p->cls[c];
@@ -572,6 +663,10 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     C.mem = (const int32_t *)(ws + H.off_mem);
     C.rect = H.rect.empty() ? nullptr : (const int4 *)(ws + H.off_rect);
     C.span0 = (const int32_t *)(ws + H.off_span0);
+    C.lidx = H.lidx.empty() ? nullptr : (const int32_t *)(ws + H.off_lidx);
+    C.bands = H.bands.empty() ? nullptr : (const int4 *)(ws + H.off_bands);
+    C.nbands = (int32_t)(H.bands.size() / 4);
+    D.max_bands = std::max(D.max_bands, C.nbands);
     C.table = (double *)(ws + H.off_table);
     C.tcol0 = (double *)(ws + H.off_tcol0);
     C.wsum = (double *)(ws + H.off_wsum);
@@ -610,7 +705,12 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     if (e == hipSuccess) e = upload(ws, H.off_mem, H.mem.data(), sizeof(int32_t) * H.mem.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_rect, H.rect.data(), sizeof(int32_t) * H.rect.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_span0, H.span0.data(), sizeof(int32_t) * H.span0.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_lidx, H.lidx.data(), sizeof(int32_t) * H.lidx.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_bands, H.bands.data(), sizeof(int32_t) * H.bands.size(), s);
   }
+  if (e == hipSuccess) e = upload(ws, p->off_litems, p->litems.data(), sizeof(int32_t) * p->litems.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_lbase, p->lbase.data(), sizeof(int32_t) * p->lbase.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_lchunks, p->lchunks.data(), sizeof(int32_t) * p->lchunks.size(), s);
   // single-plan batch view: the device plan and its phase prefix sums
   p->prefix.assign(PH_COUNT * 2, 0);
   for (int h = 0; h < PH_COUNT; ++h) p->prefix[2 * h + 1] = phase_wgs_host(p, h);
@@ -626,7 +726,10 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     S.rowalt = p->any_alt ? (const uint8_t *)(ws + p->off_rowalt) : nullptr;
     S.f = (double *)(ws + p->off_f);
     S.g = (double *)(ws + p->off_g);
-    S.dom = (double *)(ws + p->off_dom);
+    S.dom = D.dom;
+    S.cls = (const SepClass *)(ws + p->off_scls);
+    S.max_src = p->max_src;
+    S.max_avg = p->max_avg;
     p->scls.assign(p->ncls, SepClass{});
     for (int c = 0; c < p->ncls; ++c) {
       const ClassHost &H = p->cls[c];
@@ -636,6 +739,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
       if (e == hipSuccess) e = upload(ws, H.off_sep_avg, H.sep_avg.data(), sizeof(int32_t) * H.sep_avg.size(), s);
     }
     if (e == hipSuccess) e = upload(ws, p->off_rowalt, p->rowalt.data(), p->rowalt.size(), s);
+    if (e == hipSuccess) e = upload(ws, p->off_scls, p->scls.data(), sizeof(SepClass) * p->scls.size(), s);
   }
   if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, !p->sep, s);
   if (e == hipSuccess && p->sep) e = launch_sep_tables(D, p->sdev, s);
@@ -652,15 +756,28 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   return ok();
 }
 
+// A field with blocks of more than kLargeBlock cells: its device plan (host
+// copy) and I/O, for the per-field launch_large calls around the batched
+// packing and expansion kernels.
+struct LargeJob {
+  const PlanDev *P;
+  const double *rho;
+  double *phi;
+};
+
 // The kernel sequence of one solve for a batch view B of fields sharing
 // `precision`; wgs[h] = total workgroups of phase h; phi == false skips the
 // potential (moments only).
 template <class Timer>
-hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, bool phi, hipStream_t s, Timer &&timed) {
+hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, bool phi, const std::vector<LargeJob> &large,
+                     hipStream_t s, Timer &&timed) {
   const int k = precision;
   hipError_t e = launch_stamp_reset(B, s);
   if (e == hipSuccess) e = timed(MPOLE_PHASE_PACK, [&] {
-    hipError_t r = launch_pack(B, k, wgs[PH_PACK], s);
+    hipError_t r = hipSuccess;
+    for (const LargeJob &j : large)
+      if (r == hipSuccess) r = launch_large(*j.P, kLargeSum, j.rho, nullptr, s);
+    if (r == hipSuccess) r = launch_pack(B, k, wgs[PH_PACK], s);
     if (r == hipSuccess) r = launch_split_rows(B, wgs[PH_SPLITROWS], s);
     return r;
   });
@@ -669,7 +786,12 @@ hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, bool phi,
   if (e == hipSuccess) e = timed(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], s); });
   if (e == hipSuccess && phi && k != 0)
     e = timed(MPOLE_PHASE_SPLIT, [&] { return launch_split_coef(B, k, wgs[PH_COEF], s); });
-  if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] { return launch_expand(B, k, wgs[PH_EXPAND], s); });
+  if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] {
+    hipError_t r = launch_expand(B, k, wgs[PH_EXPAND], s);
+    for (const LargeJob &j : large)
+      if (r == hipSuccess) r = launch_large(*j.P, kLargeBcast, nullptr, j.phi, s);
+    return r;
+  });
   return e;
 }
 
@@ -750,15 +872,17 @@ int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, doubl
     auto T = [&](int phase, auto &&launch) { return timed(p, phase, s, launch); };
     e = hipSuccess;
     if (p->any_alt)
-      e = T(MPOLE_PHASE_PACK, [&] { return launch_sep_source(D, S, p->cdev.data(), p->scls.data(), rho, s); });
+      e = T(MPOLE_PHASE_PACK, [&] { return launch_sep_source(D, S, rho, s); });
     if (e == hipSuccess) e = T(MPOLE_PHASE_MOMENT, [&] { return launch_sep_phi_anal(D, S, rho, s); });
     if (e == hipSuccess) e = T(MPOLE_PHASE_REDUCE, [&] { return launch_sep_theta_anal(D, S, ang, s); });
     if (e == hipSuccess) e = T(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], s); });
     if (e == hipSuccess && phi) e = T(MPOLE_PHASE_SPLIT, [&] { return launch_sep_theta_syn(D, S, s); });
     if (e == hipSuccess && phi)
-      e = T(MPOLE_PHASE_EXPAND, [&] { return launch_sep_phi_syn(D, S, p->cdev.data(), p->scls.data(), phi, s); });
+      e = T(MPOLE_PHASE_EXPAND, [&] { return launch_sep_phi_syn(D, S, phi, s); });
   } else {
-    e = run_solve(B, p->precision, wgs, phi != nullptr, s,
+    std::vector<LargeJob> large;
+    if (p->dev.n_litems > 0) large.push_back(LargeJob{&p->dev, rho, phi});
+    e = run_solve(B, p->precision, wgs, phi != nullptr, large, s,
                   [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
   }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
@@ -1000,7 +1124,10 @@ int mpole_batch_solve(mpole_batch b, void *stream) {
   B.stamps = (unsigned long long *)(b->ws + b->off_stamps);
   int wgs[PH_COUNT];
   for (int h = 0; h < PH_COUNT; ++h) wgs[h] = b->prefix[h * (nf + 1) + nf];
-  hipError_t e = run_solve(B, b->precision, wgs, true, (hipStream_t)stream,
+  std::vector<LargeJob> large;
+  for (int f = 0; f < nf; ++f)
+    if (b->plans[f]->dev.n_litems > 0) large.push_back(LargeJob{&b->plans[f]->dev, b->io[f].rho, b->io[f].phi});
+  hipError_t e = run_solve(B, b->precision, wgs, true, large, (hipStream_t)stream,
                            [](int, auto &&launch) { return launch(); });
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch solve: %s", hipGetErrorString(e));
   return ok();

@@ -172,25 +172,20 @@ __device__ inline void acc_pos(int t, int u, int r, int &row, int &col) {
 // ---- per-solve kernels ------------------------------------------------------
 
 // Block means of rho for every block on a row that holds a merged block.
-__global__ __launch_bounds__(256) void k_sep_source(PlanDev P, SepDev S, ClassDev C, const int32_t *blocks,
-                                                    int nblocks, const double *rho_) {
+// Block means of the density on rows holding a merged block: thread x of
+// shell blockIdx.y takes the x-th block of its class's source list (blocks
+// of more than kLargeBlock cells are left to launch_large).
+__global__ __launch_bounds__(256) void k_sep_source(PlanDev P, SepDev S, const double *rho_) {
+  const int i = blockIdx.y;
+  const int c = ld_const(P.shell_class + i);
+  const SepClass L = ld_const(S.cls + c);
   const int x = blockIdx.x * 256 + threadIdx.x;
-  if (x >= nblocks) return;
-  const int b = blocks[x];
-  const int i = gmem(C.rows)[blockIdx.y];
-  const auto rho = gmem(rho_) + (long)i * P.ncell;
-  const auto shat = gmem(S.shat) + (long)i * P.ncell;
-  const auto mem = gmem(C.mem);
-  const int e0 = gmem(C.moff)[b], e1 = gmem(C.moff)[b + 1];
+  if (x >= L.n_src) return;
+  const ClassDev C = ld_const(P.classes + c);
+  const int b = gmem(L.src)[x];
   double num = 0.0, den = 0.0;
-  for (int e = e0; e < e1; ++e) {
-    const int q = mem[e];
-    const double dom = gmem(S.dom)[q];
-    num += dom * rho[q];
-    den += dom;
-  }
-  const double v = num / den;
-  for (int e = e0; e < e1; ++e) shat[mem[e]] = v;
+  block_wsum(C, S.dom, rho_ + (long)i * P.ncell, P.nphi, b, num, den);
+  block_fill(C, S.shat + (long)i * P.ncell, P.nphi, b, num / den);
 }
 
 // F_i[t][j] = sum_k TW[t][k] rhohat_i[j][k]; grid (t tiles x j tiles, shells).
@@ -328,25 +323,19 @@ __global__ __launch_bounds__(NTHREADS) void k_sep_phi_syn(PlanDev P, SepDev S, d
       }
 }
 
-// Solid-angle weighted mean of Phihat over each merged block, written to its members.
-__global__ __launch_bounds__(256) void k_sep_block_mean(PlanDev P, SepDev S, ClassDev C, const int32_t *blocks,
-                                                        int nblocks, double *phi_) {
+// Solid-angle weighted mean of Phihat over each merged block of shell
+// blockIdx.y, written to its members (large blocks: launch_large).
+__global__ __launch_bounds__(256) void k_sep_block_mean(PlanDev P, SepDev S, double *phi_) {
+  const int i = blockIdx.y;
+  const int c = ld_const(P.shell_class + i);
+  const SepClass L = ld_const(S.cls + c);
   const int x = blockIdx.x * 256 + threadIdx.x;
-  if (x >= nblocks) return;
-  const int b = blocks[x];
-  const int i = gmem(C.rows)[blockIdx.y];
-  const auto phi = gmem(phi_) + (long)i * P.ncell;
-  const auto mem = gmem(C.mem);
-  const int e0 = gmem(C.moff)[b], e1 = gmem(C.moff)[b + 1];
+  if (x >= L.n_avg) return;
+  const ClassDev C = ld_const(P.classes + c);
+  const int b = gmem(L.avg)[x];
   double num = 0.0, den = 0.0;
-  for (int e = e0; e < e1; ++e) {
-    const int q = mem[e];
-    const double dom = gmem(S.dom)[q];
-    num += dom * phi[q];
-    den += dom;
-  }
-  const double v = num / den;
-  for (int e = e0; e < e1; ++e) phi[mem[e]] = v;
+  block_wsum(C, S.dom, phi_ + (long)i * P.ncell, P.nphi, b, num, den);
+  block_fill(C, phi_ + (long)i * P.ncell, P.nphi, b, num / den);
 }
 
 // ---- bind-time tables -------------------------------------------------------
@@ -368,14 +357,7 @@ __global__ __launch_bounds__(256) void k_sep_tables(PlanDev P, SepDev S) {
     return;
   }
   const long y = x - ntw;
-  if (y >= 2 * npw) {   // solid angle of each cell
-    const long q = y - 2 * npw;
-    if (q < P.ncell) {
-      const int j = (int)(q / P.nphi), k = (int)(q % P.nphi);
-      S.dom[q] = cos_diff(P.theta_edges[j], P.theta_edges[j + 1]) * (P.phi_edges[k + 1] - P.phi_edges[k]);
-    }
-    return;
-  }
+  if (y >= 2 * npw) return;
   const int nplm = L1 * (L1 + 1) / 2;
   if (y < npw) {   // PW[m][j][lp]
     const int m = (int)(y / ((long)P.ntheta * L1));
@@ -401,21 +383,20 @@ inline unsigned tiles(int n, int t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_sep_tables(const PlanDev &P, const SepDev &S, hipStream_t s) {
   const long L1 = P.lmax + 1;
-  const long n = (long)S.tpad * P.nphi + 2 * L1 * P.ntheta * L1 + P.ncell;
+  const long n = (long)S.tpad * P.nphi + 2 * L1 * P.ntheta * L1;
   hipLaunchKernelGGL(k_sep_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, S);
   return hipGetLastError();
 }
 
-hipError_t launch_sep_source(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
-                             const double *rho, hipStream_t s) {
-  for (int c = 0; c < P.nclasses; ++c) {
-    if (sc[c].n_src == 0 || classes[c].nrows == 0) continue;
-    hipLaunchKernelGGL(k_sep_source, dim3(tiles(sc[c].n_src, 256), classes[c].nrows), dim3(256), 0, s, P, S,
-                       classes[c], sc[c].src, sc[c].n_src, rho);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_sep_source(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (S.max_src > 0) {
+    hipLaunchKernelGGL(k_sep_source, dim3(tiles(S.max_src, 256), P.nr), dim3(256), 0, s, P, S, rho);
+    e = hipGetLastError();
   }
-  return hipSuccess;
+  if (e == hipSuccess) e = launch_bands(P, kBandMean, rho, S.shat, s);
+  if (e == hipSuccess) e = launch_large(P, kLargeMean, rho, S.shat, s);
+  return e;
 }
 
 hipError_t launch_sep_phi_anal(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s) {
@@ -436,17 +417,16 @@ hipError_t launch_sep_theta_syn(const PlanDev &P, const SepDev &S, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, const ClassDev *classes, const SepClass *sc,
-                              double *phi, hipStream_t s) {
+hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s) {
   hipLaunchKernelGGL(k_sep_phi_syn, dim3(tiles(P.ntheta, BM) * tiles(P.nphi, BN), P.nr), dim3(NTHREADS), 0, s, P, S,
                      phi);
   hipError_t e = hipGetLastError();
-  for (int c = 0; c < P.nclasses && e == hipSuccess; ++c) {
-    if (sc[c].n_avg == 0 || classes[c].nrows == 0) continue;
-    hipLaunchKernelGGL(k_sep_block_mean, dim3(tiles(sc[c].n_avg, 256), classes[c].nrows), dim3(256), 0, s, P, S,
-                       classes[c], sc[c].avg, sc[c].n_avg, phi);
+  if (e == hipSuccess && S.max_avg > 0) {
+    hipLaunchKernelGGL(k_sep_block_mean, dim3(tiles(S.max_avg, 256), P.nr), dim3(256), 0, s, P, S, phi);
     e = hipGetLastError();
   }
+  if (e == hipSuccess) e = launch_bands(P, kBandMean, phi, phi, s);
+  if (e == hipSuccess) e = launch_large(P, kLargeMean, phi, phi, s);
   return e;
 }
 

@@ -6,7 +6,7 @@
 //                 P~_l^m(cos th) sin th (the paper uses Romberg; any quadrature
 //                 exact to rounding gives the same table)
 //   k_trig        phi-cell averages of cos m ph and sin m ph (exact antiderivative)
-//   k_weight      4 pi G dOmega per angular cell (S = 4 pi G rho)
+//   k_weight      dOmega and 4 pi G dOmega per angular cell (S = 4 pi G rho)
 //   k_block_table solid-angle weighted block means of A_iAM = <P~> x <trig>
 //   k_radial      exact shell integrals of r^(2+l), r^(1-l) and the volume
 //                 averages of r^l, r^-(l+1) used by the radial sums
@@ -88,6 +88,7 @@ __global__ void k_weight(PlanDev P) {
   if (q >= P.ncell) return;
   const int j = q / P.nphi, k = q % P.nphi;
   const double dom = cos_diff(P.theta_edges[j], P.theta_edges[j + 1]) * (P.phi_edges[k + 1] - P.phi_edges[k]);
+  P.dom[q] = dom;
   P.weight[q] = 4.0 * kPi * P.G * dom;
 }
 

@@ -118,3 +118,39 @@ def test_solve_of_coarsened_density_is_the_same_solve(genasis_solve_case):
     torch.cuda.synchronize()
     err = ((a - b).abs().max() / a.abs().max()).item()
     assert err <= 1e-13, err
+
+
+def scattered_large_blocks(seed, nr, nt, nph):
+    """Two classes: one with two irregular (non-rectangular) blocks of a few
+    hundred scattered cells each plus singletons, one without merging."""
+    rng = np.random.default_rng(seed)
+    ncell = nt * nph
+    ids = np.arange(ncell)
+    perm = rng.permutation(ncell)
+    ids[perm[:300]] = perm[0]
+    ids[perm[300:700]] = perm[300]
+    _, dense = np.unique(ids, return_inverse=True)
+    cb = np.stack([dense.astype(np.int32), np.arange(ncell, dtype=np.int32)])
+    sc = (rng.random(nr) < 0.5).astype(np.int32)
+    sc[0] = 0
+    return sc, cb
+
+
+@pytest.mark.parametrize("precision,tol", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_irregular_large_blocks(precision, tol):
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    m = wl.random_mesh(21, 24, 24, 48, 8, r0=0.05)
+    m.shell_class, m.class_block = scattered_large_blocks(22, 24, 24, 48)
+    rho = wl.random_density(23, m.shape)
+    ref = oracle.solve(rho=rho, **m.oracle_kwargs())
+    plan = mpole.Plan.from_mesh(m, precision=precision)
+    out = plan.solve(torch.from_numpy(rho).cuda())
+    phi = out["phi"].cpu().numpy()
+    err = np.max(np.abs(phi - ref["phi"]) / np.abs(ref["phi"]))
+    print(precision, "max rel %.3e" % err)
+    assert err <= tol, err
+    if precision == "fp64":
+        f = wl.random_density(24, m.shape, positive=False)
+        got = plan.coarsen(torch.from_numpy(f).cuda()).cpu().numpy()
+        assert np.max(np.abs(got - coarsen_ref(m, f))) <= 1e-14 * np.abs(f).max()
