@@ -9,63 +9,151 @@
 // (one-sided), phi wraps around when its edges close the circle (else
 // one-sided too), and a single-cell dimension has zero derivative.
 //
-// One thread per cell (grid x: cells of a shell, y: shells), phi fastest, so
-// every neighbour load of a wavefront
-// is a coalesced run; neighbours along theta (+-nphi) and radius (+-ncell)
-// are re-read from L2 by the workgroups of the adjacent rows and shells.
-// HBM-bound: about 8 B read and 24 B written per cell.
+// Each wavefront owns a tile of GJ theta rows x 64 phi columns (a lane per
+// column, the tile's rows in its registers) and walks a chunk of GR shells
+// outward; a workgroup's four wavefronts take four theta-adjacent tiles.  A
+// lane keeps its column's potential at the previous, current and next shell
+// for the tile's rows and the rows just above and below it, so radial and
+// theta neighbours come from registers; phi neighbours come from the
+// adjacent lanes, and only the columns past the tile's edges (or across the
+// periodic seam) are loaded.  Every load is issued one shell ahead of its
+// use.  The reciprocal widths are computed once per row, column and shell.
+// HBM-bound: about 8 B read (plus the halo rows and shells) and 24 B written
+// per cell.
 #include "device_util.h"
 
 namespace mpole {
 namespace {
 
-__device__ inline double centre(const double *e, int i) { return 0.5 * (e[i] + e[i + 1]); }
+constexpr int GTH = 256;   // threads: 4 wavefronts, one tile each
+constexpr int GJ = 4;      // theta rows per tile
+constexpr int GR = 8;      // shells per workgroup
 
-__global__ __launch_bounds__(256) void k_gradient(PlanDev P, const double *phi_, double *d_r, double *d_th,
+template <class T>
+__device__ inline double centre(T e, int i) { return 0.5 * (e[i] + e[i + 1]); }
+
+__global__ __launch_bounds__(GTH) void k_gradient(PlanDev P, const double *phi_, double *d_r, double *d_th,
                                                   double *d_ph, int periodic) {
+  const int ntk = (P.nphi + 63) / 64, ntj = (P.ntheta + GJ - 1) / GJ;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // theta-major tile order (adjacent rows in one workgroup and, through the
+  // XCD-aware workgroup order, on one L2)
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x) * 4 + w;
+  const int tj = tile % ntj, tk = tile / ntj;
+  const bool tin = tk < ntk;   // the last workgroup may hold tiles past the mesh
+  const int k = tk * 64 + lane;
+  const bool kin = tin && k < P.nphi;
+  const int j0 = tj * GJ, nj = min(GJ, P.ntheta - j0);
   const long ncell = (long)P.ntheta * P.nphi;
-  const int i = blockIdx.y;                       // shell
-  const int c = blockIdx.x * 256 + threadIdx.x;   // cell within the shell
-  if (c >= ncell) return;
-  const long q = (long)i * ncell + c;
-  const int j = c / P.nphi, k = c - j * P.nphi;
-  const auto phi = gmem(phi_);
-  if (d_r != nullptr) {
-    double v = 0.0;
+  const auto re = gmem(P.r_edges), te = gmem(P.theta_edges), pe = gmem(P.phi_edges);
+
+  // phi: neighbour columns and reciprocal width of this lane's column
+  int klo = k, khi = k;
+  double inv_ph = 0.0;
+  if (kin && P.nphi > 1) {
+    double xl, xh;
+    if (periodic) {
+      klo = k > 0 ? k - 1 : P.nphi - 1;
+      khi = k < P.nphi - 1 ? k + 1 : 0;
+      xl = centre(pe, klo) - (k == 0 ? 2.0 * kPi : 0.0);
+      xh = centre(pe, khi) + (k == P.nphi - 1 ? 2.0 * kPi : 0.0);
+    } else {
+      klo = k > 0 ? k - 1 : k;
+      khi = k < P.nphi - 1 ? k + 1 : k;
+      xl = centre(pe, klo);
+      xh = centre(pe, khi);
+    }
+    inv_ph = 1.0 / (xh - xl);
+  }
+  // where the phi neighbours come from: the cell itself (one-sided), the
+  // adjacent lane, or a load (tile edge, periodic seam)
+  const bool lo_self = klo == k, hi_self = khi == k;
+  const bool lo_lane = !lo_self && klo == k - 1 && lane > 0, hi_lane = !hi_self && khi == k + 1 && lane < 63;
+  const bool lo_load = kin && !lo_self && !lo_lane, hi_load = kin && !hi_self && !hi_lane;
+
+  // theta: reciprocal widths of the tile's rows (one-sided at the poles)
+  double inv_th[GJ];
+#pragma unroll
+  for (int u = 0; u < GJ; ++u) {
+    const int j = j0 + u, jl = j > 0 ? j - 1 : j, jh = j < P.ntheta - 1 ? j + 1 : j;
+    inv_th[u] = (u < nj && P.ntheta > 1) ? 1.0 / (centre(te, jh) - centre(te, jl)) : 0.0;
+  }
+  const bool has_top = j0 > 0, has_bot = j0 + nj < P.ntheta;
+
+  // column values at one shell: v = rows -1 .. GJ (rows -1 and GJ: the halo
+  // rows), lo / hi = the loaded phi neighbours of the tile's rows; the
+  // previous shell keeps only the tile's rows
+  double pv[GJ], cv[GJ + 2], nv[GJ + 2], clo[GJ], chi[GJ], nlo[GJ], nhi[GJ];
+  // loads: a shell's base pointer (workgroup-uniform) plus 32-bit cell offsets
+  int off[GJ + 2];
+#pragma unroll
+  for (int u = 0; u < GJ + 2; ++u) {
+    const int j = j0 + u - 1;
+    const bool row = u == 0 ? has_top : u == GJ + 1 ? has_bot : u - 1 < nj;
+    off[u] = (kin && row) ? j * P.nphi + k : -1;
+  }
+  auto load = [&](double *v, double *lo, double *hi, int i) {
+    const auto sp = gmem(phi_ + (size_t)i * ncell);
+#pragma unroll
+    for (int u = 0; u < GJ + 2; ++u) v[u] = off[u] >= 0 ? sp[(unsigned)off[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) {
+      lo[u] = (lo_load && u < nj) ? sp[(unsigned)(off[u + 1] - k + klo)] : 0.0;
+      hi[u] = (hi_load && u < nj) ? sp[(unsigned)(off[u + 1] - k + khi)] : 0.0;
+    }
+  };
+
+  const int i0 = blockIdx.y * GR, i1 = min(P.nr, i0 + GR);
+  load(cv, clo, chi, i0);
+  if (i0 > 0) {
+    load(nv, nlo, nhi, i0 - 1);
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) pv[u] = nv[u + 1];
+  } else {
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) pv[u] = cv[u + 1];
+  }
+  for (int i = i0; i < i1; ++i) {
+    const bool up = i + 1 < P.nr;
+    if (up) {
+      load(nv, nlo, nhi, i + 1);
+    } else {
+#pragma unroll
+      for (int u = 0; u < GJ + 2; ++u) nv[u] = cv[u];
+    }
+    double inv_r = 0.0;   // one-sided at the first and last shell, zero for one shell
     if (P.nr > 1) {
-      const int lo = i > 0 ? i - 1 : i, hi = i < P.nr - 1 ? i + 1 : i;
-      v = (phi[(long)hi * ncell + c] - phi[(long)lo * ncell + c]) / (centre(P.r_edges, hi) - centre(P.r_edges, lo));
+      const int lo = i > 0 ? i - 1 : i, hi = up ? i + 1 : i;
+      inv_r = 1.0 / (centre(re, hi) - centre(re, lo));
     }
-    gmem(d_r)[q] = v;
-  }
-  if (d_th != nullptr) {
-    double v = 0.0;
-    if (P.ntheta > 1) {
-      const int lo = j > 0 ? j - 1 : j, hi = j < P.ntheta - 1 ? j + 1 : j;
-      v = (phi[q + (long)(hi - j) * P.nphi] - phi[q + (long)(lo - j) * P.nphi]) /
-          (centre(P.theta_edges, hi) - centre(P.theta_edges, lo));
-    }
-    gmem(d_th)[q] = v;
-  }
-  if (d_ph != nullptr) {
-    double v = 0.0;
-    if (P.nphi > 1) {
-      int lo, hi;
-      double xl, xh;
-      if (periodic) {
-        lo = k > 0 ? k - 1 : P.nphi - 1;
-        hi = k < P.nphi - 1 ? k + 1 : 0;
-        xl = centre(P.phi_edges, lo) - (k == 0 ? 2.0 * kPi : 0.0);
-        xh = centre(P.phi_edges, hi) + (k == P.nphi - 1 ? 2.0 * kPi : 0.0);
-      } else {
-        lo = k > 0 ? k - 1 : k;
-        hi = k < P.nphi - 1 ? k + 1 : k;
-        xl = centre(P.phi_edges, lo);
-        xh = centre(P.phi_edges, hi);
+    const size_t base = (size_t)i * ncell;
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) {
+      const double c0 = cv[u + 1];
+      // every lane takes part in the shuffles; only cells of the mesh store
+      const double left = __shfl_up(c0, 1, 64), right = __shfl_down(c0, 1, 64);
+      if (!kin || u >= nj) continue;
+      const size_t q = base + (unsigned)off[u + 1];
+      if (d_r != nullptr) gmem(d_r)[q] = (nv[u + 1] - pv[u]) * inv_r;
+      if (d_th != nullptr) {
+        const double a = (u + 1 < nj || has_bot) ? cv[u + 2] : c0;
+        const double b = (u > 0 || has_top) ? cv[u] : c0;
+        gmem(d_th)[q] = (a - b) * inv_th[u];
       }
-      v = (phi[q + (hi - k)] - phi[q + (lo - k)]) / (xh - xl);
+      if (d_ph != nullptr) {
+        const double a = hi_self ? c0 : hi_lane ? right : chi[u];
+        const double b = lo_self ? c0 : lo_lane ? left : clo[u];
+        gmem(d_ph)[q] = (a - b) * inv_ph;
+      }
     }
-    gmem(d_ph)[q] = v;
+#pragma unroll
+    for (int u = 0; u < GJ; ++u) {
+      pv[u] = cv[u + 1];
+      clo[u] = nlo[u];
+      chi[u] = nhi[u];
+    }
+#pragma unroll
+    for (int u = 0; u < GJ + 2; ++u) cv[u] = nv[u];
   }
 }
 
@@ -73,9 +161,10 @@ __global__ __launch_bounds__(256) void k_gradient(PlanDev P, const double *phi_,
 
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
                            hipStream_t s) {
-  const long ncell = (long)P.ntheta * P.nphi;
-  hipLaunchKernelGGL(k_gradient, dim3((unsigned)((ncell + 255) / 256), (unsigned)P.nr), dim3(256), 0, s, P, phi, d_r, d_th,
-                     d_ph, periodic);
+  if (P.nr == 0 || P.ntheta == 0 || P.nphi == 0) return hipSuccess;
+  const int tiles = ((P.ntheta + GJ - 1) / GJ) * ((P.nphi + 63) / 64);
+  const unsigned groups = (unsigned)((tiles + 3) / 4), chunks = (unsigned)((P.nr + GR - 1) / GR);
+  hipLaunchKernelGGL(k_gradient, dim3(groups, chunks), dim3(GTH), 0, s, P, phi, d_r, d_th, d_ph, periodic);
   return hipGetLastError();
 }
 
