@@ -37,6 +37,7 @@ WORKLOADS = {
     # 64 uneven fields, one launch per phase, replayed from a HIP graph
     "batch64_bf16x3": ("batch64", "bf16x3"),
     "batch64_fp64": ("batch64", "fp64"),
+    "batch64_sep": ("batch64", "fp64sep"),
     # 2048 x 256 x 512, lmax 64: --steps consecutive solves (1000 for the full
     # run) on a rotating density, density update + solve per step, one HIP graph
     "large_fp16x2": ("large", "fp16x2"),

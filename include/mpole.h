@@ -72,8 +72,8 @@ typedef enum {
   MPOLE_FP16X2 = 2,          /* both contractions as two-way split FP16 products, per-shell scaling */
   MPOLE_FP64_SEPARABLE = 3   /* FP64; each contraction as a phi transform and per-m theta transforms
                                 (the cell-averaged kernels and solid angles factor in theta and phi;
-                                the same sums reordered).  Single-plan solves only: mpole_batch_create
-                                returns MPOLE_ERR_UNSUPPORTED, mpole_plan_copy_table has no table. */
+                                the same sums reordered).  A batch of separable fields runs each
+                                field's launches in turn; mpole_plan_copy_table has no table. */
 } mpole_precision;
 
 typedef struct mpole_plan_t *mpole_plan;
@@ -310,9 +310,11 @@ int mpole_plan_destroy(mpole_plan plan);
  * Batched solve of many independent fields with uneven meshes and lmax (one
  * plan per field, all with the same precision).  Every phase of the solve is
  * ONE kernel launch covering all fields (workgroups are assigned to fields by
- * prefix sums), so a batch solve is a fixed sequence of at most seven launches
- * with no host synchronisation, allocation or memset: it can be captured in a
- * HIP graph and replayed.
+ * prefix sums), so a batch solve is a fixed sequence of a few launches with
+ * no host synchronisation, allocation or memset: it can be captured in a HIP
+ * graph and replayed.  Separable fields (MPOLE_FP64_SEPARABLE) are solved
+ * one after another, each field's launches filling the device on their own,
+ * equally without host synchronisation, allocation or memset.
  *
  * mpole_batch_create: nfields in [1, 4096] meshes (host descriptors, copied);
  *   MPOLE_ERR_INVALID if their precisions differ.

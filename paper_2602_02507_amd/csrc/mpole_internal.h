@@ -166,6 +166,7 @@ hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, i
 // solve time, one launch per phase covering every field of B; wgs = total workgroups
 // (prefix[h][nf]); precision = the fields' common precision (0 = FP64)
 hipError_t launch_stamp_reset(const BatchDev &B, hipStream_t s);
+hipError_t launch_stamp(unsigned long long *stamps, int idx, hipStream_t s);   // stamps[idx] = wall clock
 hipError_t launch_pack(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_split_rows(const BatchDev &B, int wgs, hipStream_t s);   // FP16 x2 only
 hipError_t launch_moment(const BatchDev &B, int precision, int wgs, hipStream_t s);

@@ -186,6 +186,16 @@ __global__ void k_stamp_reset(unsigned long long *stamps, int nf) {
   if (t == nf) stamps[nf] = ~0ull;
 }
 
+__global__ void k_stamp(unsigned long long *stamps, int idx) {
+  if (threadIdx.x == 0) stamps[idx] = wall_clock64();
+}
+
+hipError_t launch_stamp(unsigned long long *stamps, int idx, hipStream_t s) {
+  if (stamps == nullptr) return hipSuccess;
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, stamps, idx);
+  return hipGetLastError();
+}
+
 hipError_t launch_stamp_reset(const BatchDev &B, hipStream_t s) {
   if (B.stamps == nullptr) return hipSuccess;
   hipLaunchKernelGGL(k_stamp_reset, dim3(1), dim3(((B.nf + 1 + 63) / 64) * 64), 0, s, B.stamps, B.nf);

@@ -850,6 +850,37 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
   return bind_plan(p, dev_ws, bytes, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The separable solve of one plan on stream s (phi == null: moments only).
+template <class Timer>
+hipError_t run_sep(mpole_plan_t *p, const double *rho, double *phi, double *ang, double *interior, double *exterior,
+                   hipStream_t s, Timer &&T) {
+  BatchDev B{};
+  B.plans = (const PlanDev *)(p->ws + p->off_plandev);
+  B.io = nullptr;
+  B.io1 = SolveIO{rho, phi, ang, interior, exterior};
+  B.prefix = (const int32_t *)(p->ws + p->off_prefix);
+  B.nf = 1;
+  B.stamps = nullptr;
+  const PlanDev &D = p->dev;
+  const SepDev &S = p->sdev;
+  hipError_t e = hipSuccess;
+  if (p->any_alt) e = T(MPOLE_PHASE_PACK, [&] { return launch_sep_source(D, S, rho, s); });
+  if (e == hipSuccess) e = T(MPOLE_PHASE_MOMENT, [&] { return launch_sep_phi_anal(D, S, rho, s); });
+  if (e == hipSuccess) e = T(MPOLE_PHASE_REDUCE, [&] { return launch_sep_theta_anal(D, S, ang, s); });
+  if (e == hipSuccess) e = T(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, p->prefix[2 * PH_SCAN + 1], s); });
+  if (e == hipSuccess && phi) e = T(MPOLE_PHASE_SPLIT, [&] { return launch_sep_theta_syn(D, S, s); });
+  if (e == hipSuccess && phi) e = T(MPOLE_PHASE_EXPAND, [&] { return launch_sep_phi_syn(D, S, phi, s); });
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, double *interior, double *exterior,
                 void *stream) {
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
@@ -867,18 +898,8 @@ int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, doubl
   for (int h = 0; h < PH_COUNT; ++h) wgs[h] = p->prefix[2 * h + 1];
   hipError_t e;
   if (p->sep) {
-    const PlanDev &D = p->dev;
-    const SepDev &S = p->sdev;
-    auto T = [&](int phase, auto &&launch) { return timed(p, phase, s, launch); };
-    e = hipSuccess;
-    if (p->any_alt)
-      e = T(MPOLE_PHASE_PACK, [&] { return launch_sep_source(D, S, rho, s); });
-    if (e == hipSuccess) e = T(MPOLE_PHASE_MOMENT, [&] { return launch_sep_phi_anal(D, S, rho, s); });
-    if (e == hipSuccess) e = T(MPOLE_PHASE_REDUCE, [&] { return launch_sep_theta_anal(D, S, ang, s); });
-    if (e == hipSuccess) e = T(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], s); });
-    if (e == hipSuccess && phi) e = T(MPOLE_PHASE_SPLIT, [&] { return launch_sep_theta_syn(D, S, s); });
-    if (e == hipSuccess && phi)
-      e = T(MPOLE_PHASE_EXPAND, [&] { return launch_sep_phi_syn(D, S, phi, s); });
+    e = run_sep(p, rho, phi, ang, interior, exterior, s,
+                [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
   } else {
     std::vector<LargeJob> large;
     if (p->dev.n_litems > 0) large.push_back(LargeJob{&p->dev, rho, phi});
@@ -1016,8 +1037,6 @@ int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *o
   if (!out) return fail(MPOLE_ERR_INVALID, "out is null");
   if (nfields < 1 || nfields > 4096) return fail(MPOLE_ERR_INVALID, "nfields %d outside [1, 4096]", nfields);
   if (!meshes) return fail(MPOLE_ERR_INVALID, "meshes is null");
-  if (meshes[0].precision == MPOLE_FP64_SEPARABLE)
-    return fail(MPOLE_ERR_UNSUPPORTED, "the separable path solves single plans only");
   try {
     mpole_batch_t *b = new mpole_batch_t();
     for (int f = 0; f < nfields; ++f) {
@@ -1124,11 +1143,25 @@ int mpole_batch_solve(mpole_batch b, void *stream) {
   B.stamps = (unsigned long long *)(b->ws + b->off_stamps);
   int wgs[PH_COUNT];
   for (int h = 0; h < PH_COUNT; ++h) wgs[h] = b->prefix[h * (nf + 1) + nf];
-  std::vector<LargeJob> large;
-  for (int f = 0; f < nf; ++f)
-    if (b->plans[f]->dev.n_litems > 0) large.push_back(LargeJob{&b->plans[f]->dev, b->io[f].rho, b->io[f].phi});
-  hipError_t e = run_solve(B, b->precision, wgs, true, large, (hipStream_t)stream,
-                           [](int, auto &&launch) { return launch(); });
+  hipError_t e;
+  if (b->precision == MPOLE_FP64_SEPARABLE) {
+    // separable fields: each field's launch sequence in turn (the fields are
+    // independent; every launch fills the device on its own), with a
+    // completion stamp after each field
+    hipStream_t s = (hipStream_t)stream;
+    e = launch_stamp_reset(B, s);
+    if (e == hipSuccess) e = launch_stamp(B.stamps, nf, s);
+    for (int f = 0; f < nf && e == hipSuccess; ++f) {
+      e = run_sep(b->plans[f], b->io[f].rho, b->io[f].phi, nullptr, nullptr, nullptr, s,
+                  [](int, auto &&launch) { return launch(); });
+      if (e == hipSuccess) e = launch_stamp(B.stamps, f, s);
+    }
+  } else {
+    std::vector<LargeJob> large;
+    for (int f = 0; f < nf; ++f)
+      if (b->plans[f]->dev.n_litems > 0) large.push_back(LargeJob{&b->plans[f]->dev, b->io[f].rho, b->io[f].phi});
+    e = run_solve(B, b->precision, wgs, true, large, (hipStream_t)stream, [](int, auto &&launch) { return launch(); });
+  }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch solve: %s", hipGetErrorString(e));
   return ok();
 }
