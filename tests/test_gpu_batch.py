@@ -110,3 +110,33 @@ def test_batch_field_times_after_eager_solve():
     torch.cuda.synchronize()
     ms = batch.field_ms()
     assert len(ms) == 4 and all(0 < x < 1e3 for x in ms), ms
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3", 1e-6), ("fp64sep", 1e-12)])
+def test_batch_of_genasis_meshes(precision, tol):
+    """GenASiS meshes (automatic coarsening: many classes, blocks up to whole
+    shells) mixed with a production-rule mesh in one batch: the per-field
+    block sums and broadcasts of the large blocks run around the batched
+    launches; every field equals its single-plan solve bitwise and the
+    oracle to the precision's bar."""
+    torch = _torch()
+    from oracle import genasis as og
+    from paper_2602_02507_amd import mpole
+    meshes = []
+    for nt, rr, L in ((16, 2.5, 6), (32, 1.5, 10)):
+        g = og.mesh(nt, 0.25, rr, dims=3)
+        meshes.append(wl.Mesh(g["r_edges"], g["theta_edges"], g["phi_edges"], L, g["shell_class"],
+                              g["class_block"]))
+    meshes += small_batch(1, seed0=91)
+    rho = [torch.from_numpy(wl.production_density(m, seed=5)).cuda() for m in meshes]
+    wgs = [7, 3, 5]   # the same split-K on both sides
+    batch = mpole.Batch(meshes, precision=precision, rho=rho, moment_wgs=wgs)
+    batch.solve()
+    torch.cuda.synchronize()
+    for f, m in enumerate(meshes):
+        single = mpole.Plan.from_mesh(m, precision=precision, moment_wgs=wgs[f]).solve(rho[f])["phi"]
+        torch.cuda.synchronize()
+        assert torch.equal(single, batch.phi[f]), f
+        ref = oracle.solve(rho=rho[f].cpu().numpy(), **m.oracle_kwargs())["phi"]
+        rel = np.max(np.abs(batch.phi[f].cpu().numpy() - ref) / np.abs(ref))
+        assert rel <= tol, (f, rel)

@@ -157,3 +157,39 @@ def test_separable_batch_equals_single_plans_and_graph_replay():
         g.replay()
         torch.cuda.synchronize()
         assert all(torch.equal(p, e) for p, e in zip(b.phi, eager))
+
+
+def uniform_phi_mesh(seed, nr, nt, nph, L, merged=False, jitter_phi=False):
+    m = wl.random_mesh(seed, nr, nt, nph, L, r0=0.05)
+    m.phi_edges = wl.uniform_edges(0.3, 0.3 + 2 * np.pi, nph)
+    if jitter_phi:   # still closing the circle, no longer uniform: the MFMA transforms
+        m.phi_edges = m.phi_edges.copy()
+        m.phi_edges[nph // 2] += 1e-3
+    if merged:
+        m.shell_class, m.class_block = wl.random_merge(seed + 1, nr, nt, nph)
+    return m
+
+
+UNIFORM_PHI_CASES = [
+    ("nphi16_lmax7", 9, 6, 16, 7, False, False),
+    ("nphi64_lmax31_merged", 7, 5, 64, 31, True, False),
+    ("nphi1024", 5, 3, 1024, 20, False, False),
+    ("offset_merged", 11, 8, 32, 12, True, False),
+    ("nonuniform", 11, 8, 32, 12, True, True),
+]
+
+
+@pytest.mark.parametrize("case", UNIFORM_PHI_CASES, ids=[c[0] for c in UNIFORM_PHI_CASES])
+def test_separable_uniform_phi_rows(case):
+    """Uniform phi cells closing the circle (lmax up to nphi/2 - 1, nphi up
+    to 1024, phi starting off zero, merged blocks) and a nudged edge: the
+    phi transforms match the oracle at the FP64 bar."""
+    name, nr, nt, nph, L, merged, jit = case
+    seed = sum(map(ord, name))
+    m = uniform_phi_mesh(seed, nr, nt, nph, L, merged, jit)
+    rho = wl.random_density(seed + 2, m.shape, positive=False)
+    got = run(m, rho)
+    ref = oracle.solve(rho=rho, **m.oracle_kwargs())
+    ephi, eang = compare(m, rho, got, ref)
+    print(name, "phi %.3e ang %.3e" % (ephi, eang))
+    assert ephi <= TOL and eang <= TOL, (ephi, eang)
