@@ -152,6 +152,22 @@ def gradient(r_edges, theta_edges, phi_edges, phi):
     return tuple(out)
 
 
+def gravity_sources(r_edges, theta_edges, phi_edges, phi, rho, v_r=None, v_theta=None, v_phi=None):
+    """Gravitational sources of the balance equations (Sec. 3): the momentum
+    covector source -rho grad Phi, i.e. -rho dPhi/dx^i for x = (r, theta,
+    phi), and the energy source -rho v . grad Phi = -rho sum_i v^i dPhi/dx^i
+    with v the contravariant velocity components (a missing component is
+    zero); the derivatives are the centred differences of gradient()."""
+    g = gradient(r_edges, theta_edges, phi_edges, phi)
+    rho = np.asarray(rho, dtype=np.float64)
+    s = tuple(-rho * gi for gi in g)
+    e = np.zeros_like(rho)
+    for v, gi in zip((v_r, v_theta, v_phi), g):
+        if v is not None:
+            e = e + np.asarray(v, dtype=np.float64) * gi
+    return s + (-rho * e,)
+
+
 def threads():
     """OpenMP threads the oracle uses."""
     import os

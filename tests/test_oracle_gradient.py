@@ -82,3 +82,31 @@ def test_radial_gradient_outside_uniform_sphere_converges_to_gm_over_r2():
         errs.append(np.max(np.abs(dr[out, 0, 0] - mass / rc[out] ** 2) / (mass / rc[out] ** 2)))
     assert errs[1] < errs[0] / 3.0, errs
     assert errs[1] < 1e-3, errs
+
+
+def test_gravity_sources_definition_and_closed_forms():
+    """-rho grad Phi and -rho v . grad Phi: on a potential linear in r,
+    theta and phi the sources are -rho times the slopes (exactly), the
+    energy source is -rho (v^r a + v^theta b + v^phi c); a velocity along
+    the level sets of Phi (v . grad Phi = 0) gives no energy source, and a
+    missing velocity component counts as zero."""
+    rng = np.random.default_rng(5)
+    r = np.cumsum(np.r_[0.1, rng.random(6) + 0.2])
+    th = np.sort(np.r_[0.0, rng.random(5) * np.pi, np.pi])
+    ph = np.linspace(0.0, 3.0, 6)
+    R, T, P = grid(r, th, ph)
+    a, b, c = 0.7, -1.3, 0.4
+    phi = a * R + b * T + c * P
+    rho = 1.0 + rng.random(R.shape)
+    vr, vt, vp = rng.standard_normal((3,) + R.shape)
+    sr, st, sp, se = oracle.gravity_sources(r, th, ph, phi, rho, vr, vt, vp)
+    assert np.abs(sr + rho * a).max() < 1e-12
+    assert np.abs(st + rho * b).max() < 1e-12
+    assert np.abs(sp + rho * c).max() < 1e-12
+    assert np.abs(se + rho * (vr * a + vt * b + vp * c)).max() < 1e-12
+    # v^r = -b s, v^theta = a s: tangent to the level sets of a r + b theta
+    s = rng.random(R.shape)
+    _, _, _, se0 = oracle.gravity_sources(r, th, ph, a * R + b * T, rho, -b * s, a * s, None)
+    assert np.abs(se0).max() < 1e-12
+    _, _, _, se1 = oracle.gravity_sources(r, th, ph, phi, rho, None, None, None)
+    assert (se1 == 0).all()
