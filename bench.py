@@ -242,6 +242,20 @@ def main():
     torch.cuda.synchronize()
     grad_ms = g0.elapsed_time(g1) / 10
     del grads
+    # the gravitational sources -rho grad Phi and -rho v . grad Phi in one
+    # pass (synthetic velocity field): 40 B read + 32 B written per cell
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    vel = [torch.randn(out["phi"].shape, dtype=torch.float64, device=dev, generator=gen) for _ in range(3)]
+    srcs = tuple(torch.empty_like(out["phi"]) for _ in range(4))
+    plan.gravity_sources(out["phi"], rho, tuple(vel), out=srcs)
+    g0.record(stream)
+    for _ in range(10):
+        plan.gravity_sources(out["phi"], rho, tuple(vel), out=srcs)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    src_ms = g0.elapsed_time(g1) / 10
+    del vel, srcs
     # the block volume average (coarsening operation) of the density into
     # another buffer: HBM-bound, 8 B read + 8 B written per cell
     work = torch.empty_like(rho)
@@ -265,6 +279,8 @@ def main():
               "plan_ms": plan_ms,
               "gradient": {"ms": grad_ms, "algorithmic_gbs": 32.0 * mesh.ncells / (grad_ms * 1e-3) / 1e9,
                            "hbm_frac": 32.0 * mesh.ncells / (grad_ms * 1e-3) / 8e12},
+              "gravity_sources": {"ms": src_ms, "algorithmic_gbs": 72.0 * mesh.ncells / (src_ms * 1e-3) / 1e9,
+                                  "hbm_frac": 72.0 * mesh.ncells / (src_ms * 1e-3) / 8e12},
               "coarsen": {"ms": coarsen_ms, "classes": 0 if mesh.class_block is None else int(mesh.class_block.shape[0]),
                           "algorithmic_gbs": 16.0 * mesh.ncells / (coarsen_ms * 1e-3) / 1e9,
                           "hbm_frac": 16.0 * mesh.ncells / (coarsen_ms * 1e-3) / 8e12},

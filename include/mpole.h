@@ -222,6 +222,25 @@ int mpole_gradient(mpole_plan plan, const double *phi, double *d_r, double *d_th
                    void *hip_stream);
 
 /*
+ * Gravitational sources of the balance equations (Sec. 3, the source vector
+ * of the gravitational collapse problems), from the same centred
+ * differences as mpole_gradient: the momentum covector source
+ * s_i = -rho dPhi/dx^i for x = (r, theta, phi), and the energy source
+ * s_energy = -rho v . grad Phi = -rho sum_i v^i dPhi/dx^i with v^i the
+ * contravariant velocity components.  phi and rho (mass density, in) are
+ * required; v_r, v_theta, v_phi (in) may be NULL (that component counts as
+ * zero); s_r, s_theta, s_phi, s_energy (out) may be NULL (not written).
+ * All are device [nr][ntheta][nphi] FP64 (phi fastest), owned by the caller;
+ * outputs must not overlap the inputs.  One pass over the mesh.  The plan
+ * must be bound.  MPOLE_ERR_INVALID for a null plan, phi or rho or an
+ * unbound plan, MPOLE_ERR_DEVICE for a launch failure.  Asynchronous on
+ * hip_stream, no allocation, graph-capturable.
+ */
+int mpole_gravity_sources(mpole_plan plan, const double *phi, const double *rho, const double *v_r,
+                          const double *v_theta, const double *v_phi, double *s_r, double *s_theta,
+                          double *s_phi, double *s_energy, void *hip_stream);
+
+/*
  * Coarsening operation of Sec. 2.3 on the plan's blocks: every cell of a
  * coarsening block receives the volume-weighted mean of the block,
  * sum_j V_j K_j / sum_j V_j over its member cells j (within a shell the

@@ -19,21 +19,33 @@
 // periodic seam) are loaded.  Every load is issued one shell ahead of its
 // use.  The reciprocal widths are computed once per row, column and shell.
 // HBM-bound: about 8 B read (plus the halo rows and shells) and 24 B written
-// per cell.
+// per cell.  The gravitational sources of the balance equations (-rho grad
+// Phi and -rho v . grad Phi, Sec. 3) come from the same pass, reading rho and
+// the velocity beside the potential (40 B read and 32 B written per cell).
 #include "device_util.h"
 
 namespace mpole {
 namespace {
 
 constexpr int GTH = 256;   // threads: 4 wavefronts, one tile each
-constexpr int GJ = 4;      // theta rows per tile
+constexpr int GJ = 4;      // theta rows per tile (derivatives)
+constexpr int GJS = 2;     // theta rows per tile (sources: more loads per cell)
 constexpr int GR = 8;      // shells per workgroup
 
 template <class T>
 __device__ inline double centre(T e, int i) { return 0.5 * (e[i] + e[i + 1]); }
 
-__global__ __launch_bounds__(GTH) void k_gradient(PlanDev P, const double *phi_, double *d_r, double *d_th,
-                                                  double *d_ph, int periodic) {
+// Outputs of one launch: the three derivatives (SRC false), or the
+// gravitational sources (SRC true): o[0..2] = -rho dPhi/dx^i and o[3] =
+// -rho sum_i v^i dPhi/dx^i with v[i] the contravariant velocity (null: 0).
+struct GradIO {
+  double *o[4];
+  const double *rho, *v[3];
+};
+
+template <bool SRC, int GJ>
+__global__ __launch_bounds__(GTH) void k_gradient(PlanDev P, const double *phi_, GradIO io, int periodic) {
+  double *const d_r = io.o[0], *const d_th = io.o[1], *const d_ph = io.o[2];
   const int ntk = (P.nphi + 63) / 64, ntj = (P.ntheta + GJ - 1) / GJ;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // theta-major tile order (adjacent rows in one workgroup and, through the
@@ -127,6 +139,18 @@ __global__ __launch_bounds__(GTH) void k_gradient(PlanDev P, const double *phi_,
       inv_r = 1.0 / (centre(re, hi) - centre(re, lo));
     }
     const size_t base = (size_t)i * ncell;
+    // sources: rho and the velocity of this shell, issued before the stores
+    double srho[SRC ? GJ : 1], sv[SRC ? 3 : 1][SRC ? GJ : 1];
+    if constexpr (SRC) {
+#pragma unroll
+      for (int u = 0; u < GJ; ++u) {
+        const bool in = kin && u < nj;
+        const size_t q = base + (unsigned)(in ? off[u + 1] : 0);
+        srho[u] = in ? gmem(io.rho)[q] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sv[c][u] = (in && io.v[c] != nullptr) ? gmem(io.v[c])[q] : 0.0;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < GJ; ++u) {
       const double c0 = cv[u + 1];
@@ -134,16 +158,20 @@ __global__ __launch_bounds__(GTH) void k_gradient(PlanDev P, const double *phi_,
       const double left = __shfl_up(c0, 1, 64), right = __shfl_down(c0, 1, 64);
       if (!kin || u >= nj) continue;
       const size_t q = base + (unsigned)off[u + 1];
-      if (d_r != nullptr) gmem(d_r)[q] = (nv[u + 1] - pv[u]) * inv_r;
-      if (d_th != nullptr) {
-        const double a = (u + 1 < nj || has_bot) ? cv[u + 2] : c0;
-        const double b = (u > 0 || has_top) ? cv[u] : c0;
-        gmem(d_th)[q] = (a - b) * inv_th[u];
-      }
-      if (d_ph != nullptr) {
-        const double a = hi_self ? c0 : hi_lane ? right : chi[u];
-        const double b = lo_self ? c0 : lo_lane ? left : clo[u];
-        gmem(d_ph)[q] = (a - b) * inv_ph;
+      const double gr = (nv[u + 1] - pv[u]) * inv_r;
+      const double gt = (((u + 1 < nj || has_bot) ? cv[u + 2] : c0) - ((u > 0 || has_top) ? cv[u] : c0)) * inv_th[u];
+      const double gp = ((hi_self ? c0 : hi_lane ? right : chi[u]) - (lo_self ? c0 : lo_lane ? left : clo[u])) * inv_ph;
+      if constexpr (!SRC) {
+        if (d_r != nullptr) gmem(d_r)[q] = gr;
+        if (d_th != nullptr) gmem(d_th)[q] = gt;
+        if (d_ph != nullptr) gmem(d_ph)[q] = gp;
+      } else {
+        const double nrho = -srho[u];
+        if (d_r != nullptr) gmem(d_r)[q] = nrho * gr;
+        if (d_th != nullptr) gmem(d_th)[q] = nrho * gt;
+        if (d_ph != nullptr) gmem(d_ph)[q] = nrho * gp;
+        if (io.o[3] != nullptr)
+          gmem(io.o[3])[q] = nrho * (sv[0][u] * gr + sv[1][u] * gt + sv[2][u] * gp);
       }
     }
 #pragma unroll
@@ -164,7 +192,18 @@ hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, dou
   if (P.nr == 0 || P.ntheta == 0 || P.nphi == 0) return hipSuccess;
   const int tiles = ((P.ntheta + GJ - 1) / GJ) * ((P.nphi + 63) / 64);
   const unsigned groups = (unsigned)((tiles + 3) / 4), chunks = (unsigned)((P.nr + GR - 1) / GR);
-  hipLaunchKernelGGL(k_gradient, dim3(groups, chunks), dim3(GTH), 0, s, P, phi, d_r, d_th, d_ph, periodic);
+  const GradIO io{{d_r, d_th, d_ph, nullptr}, nullptr, {nullptr, nullptr, nullptr}};
+  hipLaunchKernelGGL((k_gradient<false, GJ>), dim3(groups, chunks), dim3(GTH), 0, s, P, phi, io, periodic);
+  return hipGetLastError();
+}
+
+hipError_t launch_gravity_sources(const PlanDev &P, const double *phi, const double *rho, const double *const v[3],
+                                  double *const out[4], int periodic, hipStream_t s) {
+  if (P.nr == 0 || P.ntheta == 0 || P.nphi == 0) return hipSuccess;
+  const int tiles = ((P.ntheta + GJS - 1) / GJS) * ((P.nphi + 63) / 64);
+  const unsigned groups = (unsigned)((tiles + 3) / 4), chunks = (unsigned)((P.nr + GR - 1) / GR);
+  const GradIO io{{out[0], out[1], out[2], out[3]}, rho, {v[0], v[1], v[2]}};
+  hipLaunchKernelGGL((k_gradient<true, GJS>), dim3(groups, chunks), dim3(GTH), 0, s, P, phi, io, periodic);
   return hipGetLastError();
 }
 

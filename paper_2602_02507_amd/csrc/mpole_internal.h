@@ -176,6 +176,9 @@ hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStrea
 hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
                            hipStream_t s);
+// out[0..2] = -rho dPhi/dx^i, out[3] = -rho sum_i v^i dPhi/dx^i (any pointer may be null)
+hipError_t launch_gravity_sources(const PlanDev &P, const double *phi, const double *rho, const double *const v[3],
+                                  double *const out[4], int periodic, hipStream_t s);
 // block volume average of a cell field (host copies of the class views give the spans per class);
 // blocks of more than kLargeBlock members are left to launch_large
 hipError_t launch_coarsen(const PlanDev &P, const ClassDev *host_classes, const double *in, double *out,

@@ -836,6 +836,20 @@ int mpole_gradient(mpole_plan p, const double *phi, double *d_r, double *d_theta
   return ok();
 }
 
+int mpole_gravity_sources(mpole_plan p, const double *phi, const double *rho, const double *v_r,
+                          const double *v_theta, const double *v_phi, double *s_r, double *s_theta, double *s_phi,
+                          double *s_energy, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!p->bound) return fail(MPOLE_ERR_INVALID, "plan is not bound to a workspace");
+  if (!phi || !rho) return fail(MPOLE_ERR_INVALID, "phi and rho are required");
+  if (!s_r && !s_theta && !s_phi && !s_energy) return ok();
+  const double *v[3] = {v_r, v_theta, v_phi};
+  double *out[4] = {s_r, s_theta, s_phi, s_energy};
+  const hipError_t e = launch_gravity_sources(p->dev, phi, rho, v, out, p->phi_periodic, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "gravity sources launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 int mpole_coarsen(mpole_plan p, const double *in, double *out, void *stream) {
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
   if (!p->bound) return fail(MPOLE_ERR_INVALID, "plan is not bound to a workspace");

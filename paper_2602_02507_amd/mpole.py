@@ -22,7 +22,7 @@ STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE
 # every entry point include/mpole.h declares
 EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_plan_workspace_bytes",
            "mpole_plan_nmodes", "mpole_plan_bind", "mpole_solve", "mpole_plan_copy_table",
-           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_gradient", "mpole_coarsen",
+           "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_gradient", "mpole_gravity_sources", "mpole_coarsen",
            "mpole_genasis_shape", "mpole_genasis_build", "mpole_plan_tune",
            "mpole_plan_get_tuning", "mpole_plan_configure", "mpole_plan_moment_wgs", "mpole_plan_destroy",
            "mpole_batch_create", "mpole_batch_tune", "mpole_batch_configure", "mpole_batch_workspace_bytes",
@@ -102,6 +102,7 @@ def lib():
         L.mpole_plan_work.argtypes = [vp, dptr, dptr, dptr]
         L.mpole_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mpole_coarsen.argtypes = [vp, vp, vp, vp]
+        L.mpole_gravity_sources.argtypes = [vp] + [vp] * 10
         ip = ctypes.POINTER(ctypes.c_int32)
         L.mpole_genasis_shape.argtypes = [ctypes.POINTER(GenasisC), ip, ip, ip, ip, ip]
         L.mpole_genasis_build.argtypes = [ctypes.POINTER(GenasisC), dptr, dptr, dptr, ip, ip, ip, ip]
@@ -308,6 +309,26 @@ class Plan(HostPlan):
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         _check(lib().mpole_gradient(self.handle, _dev_ptr(phi), *[_dev_ptr(t) for t in outs], ctypes.c_void_p(s)))
         return tuple(outs)
+
+    def gravity_sources(self, phi, rho, v=(None, None, None), out=None, stream=None):
+        """(-rho dPhi/dr, -rho dPhi/dtheta, -rho dPhi/dphi, -rho v . grad Phi)
+        of a potential (mpole_gravity_sources); v = contravariant velocity
+        components (None: zero); outputs allocated when out is None."""
+        import torch
+        self._check_tensor(phi, self.shape, "phi")
+        self._check_tensor(rho, self.shape, "rho")
+        for t in v:
+            if t is not None:
+                self._check_tensor(t, self.shape, "velocity")
+        if out is None:
+            out = tuple(torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(4))
+        for t in out:
+            if t is not None:
+                self._check_tensor(t, self.shape, "source output")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_gravity_sources(self.handle, _dev_ptr(phi), _dev_ptr(rho), *[_dev_ptr(t) for t in v],
+                                           *[_dev_ptr(t) for t in out], ctypes.c_void_p(s)))
+        return out
 
     def coarsen(self, field, out=None, stream=None):
         """Block volume average of a cell field over this mesh's coarsening

@@ -62,3 +62,36 @@ def test_gradient_of_production_potential():
     rc = 0.5 * (m.r_edges[1:] + m.r_edges[:-1])
     outer = (rc > 0.1) & (np.arange(m.nr) < m.nr - 1)
     assert (got[0][outer] > 0).all()
+
+
+SRC_CASES = [((37, 11, 23), (True, True, True)), ((5, 1, 9), (True, False, True)), ((3, 4, 2), (False, False, False)),
+             ((64, 33, 65), (True, True, False)), ((1, 6, 1), (False, True, False))]
+
+
+@pytest.mark.parametrize("shape,vel", SRC_CASES, ids=[str(c[0]) for c in SRC_CASES])
+def test_gravity_sources_match_oracle(shape, vel):
+    """-rho grad Phi and -rho v . grad Phi in one pass (missing velocity
+    components count as zero) against the oracle, on ragged meshes with
+    single-cell dimensions; a null output is not written."""
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    nr, nt, npf = shape
+    seed = sum(shape) + 7
+    m = wl.random_mesh(seed, nr, nt, npf, 4, r0=0.01)
+    phi = wl.random_density(seed + 1, m.shape, positive=False)
+    rho = wl.random_density(seed + 2, m.shape)
+    v = [wl.random_density(seed + 3 + k, m.shape, positive=False) if on else None for k, on in enumerate(vel)]
+    plan = mpole.Plan.from_mesh(m, precision="fp64")
+    cu = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    got = [g.cpu().numpy() for g in plan.gravity_sources(cu(phi), cu(rho), tuple(cu(x) for x in v))]
+    want = oracle.gravity_sources(m.r_edges, m.theta_edges, m.phi_edges, phi, rho, *v)
+    for name, g, w in zip(("s_r", "s_theta", "s_phi", "s_energy"), got, want):
+        scale = max(np.abs(w).max(), 1e-300)
+        assert np.abs(g - w).max() <= TOL * scale or np.abs(w).max() == 0 and np.abs(g).max() == 0, name
+    # outputs left out are not written
+    keep = torch.full(m.shape, 7.0, dtype=torch.float64, device="cuda")
+    out = (None, keep, None, None)
+    plan.gravity_sources(cu(phi), cu(rho), tuple(cu(x) for x in v), out=out)
+    torch.cuda.synchronize()
+    assert np.abs(keep.cpu().numpy() - want[1]).max() <= TOL * max(np.abs(want[1]).max(), 1e-300) or \
+        np.abs(want[1]).max() == 0
