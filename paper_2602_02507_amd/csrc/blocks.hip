@@ -9,6 +9,11 @@
 // partials in chunk order (the same result on every chunk) and writes the
 // mean with the same stride.  The two launches order every read of a mean
 // before its writes, so in-place means are safe.
+//
+// Block maps made of theta bands (every block of rows [j0, j0 + nj) an
+// nj x nk rectangle at a phi column divisible by nk, the layout of
+// power-of-two coarsening) take the band kernel for block means instead of
+// one thread per block: coalesced column sums and lane butterflies.
 #include "device_util.h"
 
 namespace mpole {
