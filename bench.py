@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cell*(l,m)-modes/s, multipole Phi solve: mixed vs FP64 on GPU at <=1e-6 rel err"
 UNIT = "cell*(l,m)-modes/s"
 PEAK = {"f64": (78.6e12, "TFLOP/s"), "bf16": (2.5e15, "TFLOP/s"), "f16": (2.5e15, "TFLOP/s")}
-DTYPE = {"fp64": "f64", "bf16x3": "bf16", "fp16x2": "f16", "fp64sep": "f64"}
+DTYPE = {"fp64": "f64", "bf16x3": "bf16", "fp16x2": "f16", "fp64sep": "f64", "bf16x3sep": "bf16"}
 
 WORKLOADS = {
     # name: (workload generator key, precision)
@@ -33,6 +33,8 @@ WORKLOADS = {
     # separable FP64 contractions (phi transform + per-m theta transforms)
     "production_sep": ("production", "fp64sep"),
     "production_l32_sep": ("production_l32", "fp64sep"),
+    # separable with BF16 x3 phi transforms (m >= 1), FP64 theta transforms
+    "production_l32_bf16x3sep": ("production_l32", "bf16x3sep"),
     "spheroid_fp64": ("spheroid", "fp64"),
     # 64 uneven fields, one launch per phase, replayed from a HIP graph
     "batch64_bf16x3": ("batch64", "bf16x3"),
@@ -43,10 +45,13 @@ WORKLOADS = {
     "large_fp16x2": ("large", "fp16x2"),
     "large_bf16x3": ("large", "bf16x3"),
     "large_sep": ("large", "fp64sep"),
+    "large_bf16x3sep": ("large", "bf16x3sep"),
     # GenASiS mesh of the spheroid tests (N_theta 256, r_core 0.25, R_radial 3.68:
     # 942 x 256 x 512, 201 coarsening classes), lmax 12 (the paper's default)
     "genasis_sep": ("genasis", "fp64sep"),
     "genasis_bf16x3": ("genasis", "bf16x3"),
+    "genasis_bf16x3sep": ("genasis", "bf16x3sep"),
+    "batch64_bf16x3sep": ("batch64", "bf16x3sep"),
 }
 DEFAULT = "production_l32_bf16x3"
 
@@ -67,11 +72,12 @@ def parse():
 
 
 KERNEL_NAMES = {("fp64", "moment"): "k_moment_f64", ("fp64", "expand"): "k_expand_f64",
-                ("fp64sep", "moment"): "k_sep_phi_anal", ("fp64sep", "expand"): "k_sep_phi_syn"}
+                ("fp64sep", "moment"): "k_sep_phi_anal", ("fp64sep", "expand"): "k_sep_phi_syn",
+                ("bf16x3sep", "moment"): "k_sep_phi_anal_bf16", ("bf16x3sep", "expand"): "k_sep_phi_syn_bf16"}
 
 
 def kernel_name(precision, phase):
-    if precision in ("fp64", "fp64sep"):
+    if (precision, phase) in KERNEL_NAMES:
         return KERNEL_NAMES[(precision, phase)]
     return "k_gemm_split<%s, %s>" % (precision, phase)
 
@@ -121,7 +127,7 @@ def roofline(plan, phases, precision, workload):
     achieved = flops / (dom_ms * 1e-3)
     # executed MFMA work: the split precisions run `products` narrow products per
     # algorithmic multiply-add, over padded tiles
-    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1}[precision]
+    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1, "bf16x3sep": 6}[precision]
     return {"bound": "mfma", "kernel": kernel_name(precision, dom),
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
             "traffic": measured_traffic(workload, dom), "launch_ms": dom_ms,
@@ -400,7 +406,7 @@ def bench_large(args, precision):
                                                                          solve_ms))
     cell_modes = float(mesh.ncells) * mesh.nmodes
     mflops, eflops, min_bytes = plan.work()
-    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1}[precision]
+    products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1, "bf16x3sep": 6}[precision]
     roof = roofline(plan, phases, precision, args.workload)
     result = {"metric": METRIC, "value": cell_modes / (solve_ms * 1e-3), "unit": UNIT, "n_gpus": 1,
               "steps": steps, "warmup": args.warmup, "ms_per_step": graph_ms / steps, "higher_is_better": True,

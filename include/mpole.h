@@ -70,10 +70,15 @@ typedef enum {
   MPOLE_FP64 = 0,            /* both contractions in FP64 (MFMA f64) */
   MPOLE_BF16X3 = 1,          /* both contractions as three-way split BF16 products, FP32 accumulation */
   MPOLE_FP16X2 = 2,          /* both contractions as two-way split FP16 products, per-shell scaling */
-  MPOLE_FP64_SEPARABLE = 3   /* FP64; each contraction as a phi transform and per-m theta transforms
+  MPOLE_FP64_SEPARABLE = 3,  /* FP64; each contraction as a phi transform and per-m theta transforms
                                 (the cell-averaged kernels and solid angles factor in theta and phi;
                                 the same sums reordered).  A batch of separable fields runs each
                                 field's launches in turn; mpole_plan_copy_table has no table. */
+  MPOLE_BF16X3_SEPARABLE = 4 /* the separable form with both phi transforms (the m >= 1 trig modes)
+                                as three-way split BF16 products with FP32 accumulation, the density
+                                and the theta-synthesis output split on the fly; the m = 0 mode, the
+                                theta transforms and the radial sums stay FP64.  Batches and tables
+                                as for MPOLE_FP64_SEPARABLE. */
 } mpole_precision;
 
 typedef struct mpole_plan_t *mpole_plan;
@@ -331,7 +336,7 @@ int mpole_plan_destroy(mpole_plan plan);
  * ONE kernel launch covering all fields (workgroups are assigned to fields by
  * prefix sums), so a batch solve is a fixed sequence of a few launches with
  * no host synchronisation, allocation or memset: it can be captured in a HIP
- * graph and replayed.  Separable fields (MPOLE_FP64_SEPARABLE) are solved
+ * graph and replayed.  Separable fields (MPOLE_FP64_SEPARABLE, MPOLE_BF16X3_SEPARABLE) are solved
  * one after another, each field's launches filling the device on their own,
  * equally without host synchronisation, allocation or memset.
  *

@@ -136,6 +136,14 @@ struct SepDev {
   double *f, *g;           // [nr][tpad][ntheta] phi analysis, theta synthesis
   const double *dom;       // [ntheta][nphi] solid angle of each cell (the plan's table)
   const SepClass *cls;     // [nclasses] per-class block lists (device copy)
+  // BF16 x3 phi transforms (null for FP64): the m >= 1 rows of TW and TT
+  // split into bf16 planes and stored in MFMA fragment order, 64 lanes x 16
+  // bytes per (32-deep K step, 16-row tile, plane):
+  //   twf [ks_a][mt_a][3][64]: lane l holds TW[1 + 16 mt + l % 16][32 ks + 8 (l / 16) + e], e < 8
+  //   ttf [ks_s][nt_s][3][64]: lane l holds TT[1 + 32 ks + 8 (l / 16) + e][16 nt + l % 16]
+  // (zero past t = 2L or k = nphi)
+  const uint32_t *twf, *ttf;
+  int32_t ks_a, mt_a, ks_s, nt_s;
 };
 // Per class: blocks on rows with a merged block (source means), and blocks
 // with more than one member (potential means); device lists, without the
@@ -203,6 +211,12 @@ hipError_t launch_sep_phi_anal(const PlanDev &P, const SepDev &S, const double *
 hipError_t launch_sep_theta_anal(const PlanDev &P, const SepDev &S, double *ang_out, hipStream_t s);
 hipError_t launch_sep_theta_syn(const PlanDev &P, const SepDev &S, hipStream_t s);
 hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s);
+// BF16 x3 phi transforms of the separable path (S.twf, S.ttf set)
+hipError_t launch_sep_split_tables(const PlanDev &P, const SepDev &S, hipStream_t s);
+hipError_t launch_sep_phi_anal_bf16(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s);
+hipError_t launch_sep_phi_syn_bf16(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s);
+// the block means of the potential after a phi synthesis (merged blocks, bands, large blocks)
+hipError_t launch_sep_block_means(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s);
 
 hipError_t launch_moment_f64(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_expand_f64(const BatchDev &B, int wgs, hipStream_t s);

@@ -110,11 +110,14 @@ struct mpole_plan_t {
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
   int phi_periodic = 0;   // phi edges close the circle (gradient wraps around)
-  bool sep = false;       // separable FP64 contractions
+  bool sep = false;       // separable contractions
+  bool sep_bf16 = false;  // separable with BF16 x3 phi transforms
   int tpad = 0;           // separable: trig modes 2L+1 padded to 16
   bool any_alt = false;   // separable: some row holds a merged block
   std::vector<uint8_t> rowalt;   // separable: [nr][ntheta] rows read from the block means
   size_t off_tw = 0, off_pw = 0, off_pt = 0, off_shat = 0, off_rowalt = 0, off_f = 0, off_g = 0, off_dom = 0;
+  size_t off_twf = 0, off_ttf = 0;
+  int ks_a = 0, mt_a = 0, ks_s = 0, nt_s = 0;   // BF16 x3 separable: fragment table shapes
   SepDev sdev{};
   std::vector<SepClass> scls;
   size_t off_scls = 0;
@@ -184,7 +187,7 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   if (m->lmax < 0) return fail(MPOLE_ERR_INVALID, "lmax must be >= 0");
   if (m->lmax > MPOLE_LMAX_MAX) return fail(MPOLE_ERR_UNSUPPORTED, "lmax %d above %d", m->lmax, MPOLE_LMAX_MAX);
   if (m->precision != MPOLE_FP64 && m->precision != MPOLE_BF16X3 && m->precision != MPOLE_FP16X2 &&
-      m->precision != MPOLE_FP64_SEPARABLE)
+      m->precision != MPOLE_FP64_SEPARABLE && m->precision != MPOLE_BF16X3_SEPARABLE)
     return fail(MPOLE_ERR_UNSUPPORTED, "unknown precision %d", m->precision);
   if (!std::isfinite(m->G)) return fail(MPOLE_ERR_INVALID, "G is not finite");
   const long long ncell = (long long)m->ntheta * m->nphi;
@@ -217,7 +220,8 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->ncell = (int)ncell;
   p->precision = m->precision;
   p->nplanes = n_planes(m->precision);
-  p->sep = m->precision == MPOLE_FP64_SEPARABLE;
+  p->sep = m->precision == MPOLE_FP64_SEPARABLE || m->precision == MPOLE_BF16X3_SEPARABLE;
+  p->sep_bf16 = m->precision == MPOLE_BF16X3_SEPARABLE;
   p->tpad = round_up(2 * m->lmax + 1, 16);
   // output tiles of the contraction kernels: 64 x 64 (f64 MFMA); 128 x 128
   // (split; the height may be tuned to 64)
@@ -515,6 +519,14 @@ void layout_plan(mpole_plan_t *p, int target) {
     p->off_f = take(sizeof(double) * nrt * p->tpad);
     p->off_g = take(sizeof(double) * nrt * p->tpad);
     p->off_scls = take(sizeof(SepClass) * p->ncls);
+    // fragment-order split tables (64 lanes x 16 bytes per K step, tile and plane)
+    p->ks_a = (p->np + 31) / 32;
+    p->mt_a = (2 * p->L + 15) / 16;
+    p->ks_s = (2 * p->L + 31) / 32;
+    p->nt_s = (p->np + 15) / 16;
+    const size_t frag = 3 * 64 * 16;
+    p->off_twf = take(p->sep_bf16 ? frag * p->ks_a * p->mt_a : 0);
+    p->off_ttf = take(p->sep_bf16 ? frag * p->ks_s * p->nt_s : 0);
   }
   // the single-plan view of the batched kernels: one device plan, phase prefix sums
   p->off_plandev = take(sizeof(PlanDev));
@@ -730,6 +742,12 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     S.cls = (const SepClass *)(ws + p->off_scls);
     S.max_src = p->max_src;
     S.max_avg = p->max_avg;
+    S.twf = p->sep_bf16 ? (const uint32_t *)(ws + p->off_twf) : nullptr;
+    S.ttf = p->sep_bf16 ? (const uint32_t *)(ws + p->off_ttf) : nullptr;
+    S.ks_a = p->ks_a;
+    S.mt_a = p->mt_a;
+    S.ks_s = p->ks_s;
+    S.nt_s = p->nt_s;
     p->scls.assign(p->ncls, SepClass{});
     for (int c = 0; c < p->ncls; ++c) {
       const ClassHost &H = p->cls[c];
@@ -743,6 +761,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   }
   if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, !p->sep, s);
   if (e == hipSuccess && p->sep) e = launch_sep_tables(D, p->sdev, s);
+  if (e == hipSuccess && p->sep_bf16) e = launch_sep_split_tables(D, p->sdev, s);
   if (e == hipSuccess && p->nplanes) e = launch_split_tables(D, p->cdev.data(), p->precision, s);
   // unit row scales (BF16 x3 operands are not scaled; FP16 x2 rows overwrite theirs)
   for (int c = 0; c < p->ncls && e == hipSuccess; ++c)
@@ -883,11 +902,15 @@ hipError_t run_sep(mpole_plan_t *p, const double *rho, double *phi, double *ang,
   const SepDev &S = p->sdev;
   hipError_t e = hipSuccess;
   if (p->any_alt) e = T(MPOLE_PHASE_PACK, [&] { return launch_sep_source(D, S, rho, s); });
-  if (e == hipSuccess) e = T(MPOLE_PHASE_MOMENT, [&] { return launch_sep_phi_anal(D, S, rho, s); });
+  if (e == hipSuccess) e = T(MPOLE_PHASE_MOMENT, [&] {
+    return p->sep_bf16 ? launch_sep_phi_anal_bf16(D, S, rho, s) : launch_sep_phi_anal(D, S, rho, s);
+  });
   if (e == hipSuccess) e = T(MPOLE_PHASE_REDUCE, [&] { return launch_sep_theta_anal(D, S, ang, s); });
   if (e == hipSuccess) e = T(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, p->prefix[2 * PH_SCAN + 1], s); });
   if (e == hipSuccess && phi) e = T(MPOLE_PHASE_SPLIT, [&] { return launch_sep_theta_syn(D, S, s); });
-  if (e == hipSuccess && phi) e = T(MPOLE_PHASE_EXPAND, [&] { return launch_sep_phi_syn(D, S, phi, s); });
+  if (e == hipSuccess && phi) e = T(MPOLE_PHASE_EXPAND, [&] {
+    return p->sep_bf16 ? launch_sep_phi_syn_bf16(D, S, phi, s) : launch_sep_phi_syn(D, S, phi, s);
+  });
   return e;
 }
 
@@ -1158,7 +1181,7 @@ int mpole_batch_solve(mpole_batch b, void *stream) {
   int wgs[PH_COUNT];
   for (int h = 0; h < PH_COUNT; ++h) wgs[h] = b->prefix[h * (nf + 1) + nf];
   hipError_t e;
-  if (b->precision == MPOLE_FP64_SEPARABLE) {
+  if (b->precision == MPOLE_FP64_SEPARABLE || b->precision == MPOLE_BF16X3_SEPARABLE) {
     // separable fields: each field's launch sequence in turn (the fields are
     // independent; every launch fills the device on its own), with a
     // completion stamp after each field

@@ -1,0 +1,342 @@
+// Separable form with BF16 x3 phi transforms.
+//
+// The separable path (the cell-averaged kernels and solid angles factor in
+// theta and phi, Eqs. AngularKernel_c / AngularKernel_s averaged over a cell)
+// computes, per shell i and theta row j,
+//   analysis   F_i[t][j]      = sum_k TW[t][k] rhohat_i[j][k],
+//   synthesis  Phihat_i[j][k] = sum_t G_i[t][j] TT[t][k],
+// with t the trig modes (t = 0: m = 0; 2m-1 / 2m: cos / sin m phi).  Here
+// the m >= 1 rows of both transforms run on v_mfma_f32_32x32x16_bf16 with
+// every FP64 operand written as hi + mid + lo bfloat16 planes (the remainders
+// taken exactly in FP64) and the six products hi.hi, hi.mid, mid.hi, hi.lo,
+// lo.hi, mid.mid accumulated in FP32; the m = 0 row (the density's
+// dphi-weighted row sum, and the potential's m = 0 term), which carries the
+// monopole, stays FP64.  The theta transforms and the radial sums are the
+// FP64 kernels of the separable path.
+//
+// MFMA v_mfma_f32_16x16x32_bf16 (16-row tiles, 32-deep K steps: many short
+// wavefronts to keep enough density loads in flight).  No LDS: each lane of a
+// wavefront loads exactly the 8 values of its own fragment and splits them in
+// registers.
+//   analysis:  the density fragment of lane l is row j0 + l % 16, phi cells
+//              32 ks + 8 (l / 16) .. +7 (64 contiguous bytes; the four lanes
+//              of a row cover its 256-byte run of the K step); the
+//              trig-weight fragments come from a bind-time table in fragment
+//              order.
+//   synthesis: the G fragment of lane l is theta row j0 + l % 16 at modes
+//              1 + 32 ks + 8 (l / 16) .. +7 (each load coalesced across 16
+//              rows); the trig fragments come from a table in fragment order.
+// 16x16x32 lane layout (gfx950, checked on the device): lane l supplies
+// X[l%16][8(l/16)..+7] and Y[l%16][same k]; result register r holds
+// out[4(l/16) + r][l%16] of out[m][n] = sum_k X[m][k] Y[n][k].
+//
+// Both transforms are HBM-bound: the analysis reads the density once (8 B per
+// cell) and the synthesis writes the potential once (8 B per cell).
+#include "device_util.h"
+#include "split_util.h"
+
+namespace mpole {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ inline f4 mma(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+// hi, mid, lo bfloat16 planes of 8 FP64 values, packed two per dword
+// (element e in the low half of dword e / 2 when e is even).  Each value is
+// rounded to FP32 first (relative error 2^-24, the precision of the three
+// planes together); the FP32 value is then exactly hi + mid + lo: hi is its
+// nearest bfloat16, the remainders are exact FP32 differences, and the last
+// one has at most 8 significant bits.
+__device__ inline uint32_t pack2(__bf16 a, __bf16 b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+__device__ inline void split8(const double (&v)[8], u4 (&p)[3]) {
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const float x0 = (float)v[2 * d], x1 = (float)v[2 * d + 1];
+    const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+    const float r0 = x0 - (float)h0, r1 = x1 - (float)h1;
+    const __bf16 m0 = (__bf16)r0, m1 = (__bf16)r1;
+    const float s0 = r0 - (float)m0, s1 = r1 - (float)m1;
+    p[0][d] = pack2(h0, h1);
+    p[1][d] = pack2(m0, m1);
+    p[2][d] = pack2((__bf16)s0, (__bf16)s1);
+  }
+}
+
+// the six kept products of two split fragments (the other three are below
+// 2^-24 of the product)
+__device__ inline f4 mma6(const u4 (&a)[3], const u4 (&b)[3], f4 c) {
+  c = mma(a[0], b[0], c);
+  c = mma(a[0], b[1], c);
+  c = mma(a[1], b[0], c);
+  c = mma(a[0], b[2], c);
+  c = mma(a[2], b[0], c);
+  c = mma(a[1], b[1], c);
+  return c;
+}
+
+__device__ inline u4 frag(const uint32_t *table, long entry, int lane) {
+  return *(const __attribute__((address_space(1))) u4 *)(table + (entry * 64 + lane) * 4);
+}
+
+// ---- bind-time fragment tables ---------------------------------------------
+
+// One thread per (K step, tile, lane) entry of either table: its 8 values,
+// split, into the three planes.
+__global__ __launch_bounds__(256) void k_sep_split_tables(PlanDev P, SepDev S) {
+  const long x = (long)blockIdx.x * 256 + threadIdx.x;
+  const long na = (long)S.ks_a * S.mt_a * 64, ns = (long)S.ks_s * S.nt_s * 64;
+  const int tmax = 2 * P.lmax;
+  const double *tw = S.tw, *tt = S.tw + (long)S.tpad * P.nphi;
+  double v[8];
+  uint32_t *dst;
+  long entry;
+  int lane;
+  if (x < na) {
+    lane = (int)(x % 64);
+    const long e2 = x / 64;   // ks * mt_a + mt
+    const int ks = (int)(e2 / S.mt_a), mt = (int)(e2 % S.mt_a);
+    const int t = 1 + 16 * mt + lane % 16;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 32 * ks + 8 * (lane / 16) + e;
+      v[e] = (t <= tmax && k < P.nphi) ? tw[(long)t * P.nphi + k] : 0.0;
+    }
+    dst = const_cast<uint32_t *>(S.twf);
+    entry = e2 * 3;
+  } else if (x < na + ns) {
+    const long y = x - na;
+    lane = (int)(y % 64);
+    const long e2 = y / 64;   // ks * nt_s + nt
+    const int ks = (int)(e2 / S.nt_s), nt = (int)(e2 % S.nt_s);
+    const int k = 16 * nt + lane % 16;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int t = 1 + 32 * ks + 8 * (lane / 16) + e;
+      v[e] = (t <= tmax && k < P.nphi) ? tt[(long)t * P.nphi + k] : 0.0;
+    }
+    dst = const_cast<uint32_t *>(S.ttf);
+    entry = e2 * 3;
+  } else {
+    return;
+  }
+  u4 p[3];
+  split8(v, p);
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) dst[((entry + q) * 64 + lane) * 4 + d] = p[q][d];
+}
+
+// ---- per-solve kernels ------------------------------------------------------
+
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) dv2 *gdv2;
+
+// 8 consecutive doubles from a 16-byte aligned global address
+__device__ inline void load8(const double *p, double (&v)[8]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const dv2 d = *(gdv2)(p + 2 * e);
+    v[2 * e] = d[0];
+    v[2 * e + 1] = d[1];
+  }
+}
+
+// Analysis: a wavefront per (shell blockIdx.y, 16 theta rows), all m >= 1
+// modes (MT tiles of 16); 4 wavefronts per workgroup on adjacent row tiles.
+// Rows past the mesh read its row j0 and store nothing (each output row
+// depends on its own density row only).  Steps whose 32 cells all lie inside
+// the row load without guards, two at a time (one ahead); a last partial step
+// loads element by element.
+template <int MT>
+__global__ __launch_bounds__(256) void k_sep_phi_anal_bf16(PlanDev P, SepDev S, const double *rho, int rho16) {
+  const int lane = threadIdx.x & 63, quad = lane >> 4;
+  const int i = blockIdx.y;
+  const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (j0 >= P.ntheta) return;   // wavefront-uniform; the kernel has no barrier
+  const int j = j0 + (lane & 15);
+  const bool jin = j < P.ntheta;
+  const int jr = jin ? j : j0;
+  const long o = (long)i * P.ncell + (long)jr * P.nphi;
+  const bool alt = S.rowalt != nullptr && S.rowalt[(long)i * P.ntheta + jr];
+  const double *row = (alt ? S.shat : rho) + o + 8 * quad;   // this lane's cells of step 0
+  const double *dphi = S.tw + 8 * quad;                      // TW row 0: dphi_k
+  const int np = P.nphi, nfull = np / 32;
+  const bool vec = rho16 && (np & 1) == 0;   // rows start 16-byte aligned
+
+  f4 acc[MT > 0 ? MT : 1];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = f4{};
+  double rs = 0.0;   // FP64 row sum of dphi_k rho over this lane's cells
+
+  auto load = [&](double (&v)[8], double (&d)[8], int ks) __attribute__((always_inline)) {
+    if (vec) {
+      load8(row + 32 * ks, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = *gmem(row + 32 * ks + e);
+    }
+    load8(dphi + 32 * ks, d);
+  };
+  auto step = [&](const double (&v)[8], const double (&d)[8], int ks) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rs += d[e] * v[e];
+    if constexpr (MT > 0) {
+      u4 b[3];
+      split8(v, b);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        u4 a[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a[q] = frag(S.twf, ((long)ks * MT + m) * 3 + q, lane);
+        acc[m] = mma6(a, b, acc[m]);
+      }
+    }
+  };
+  double va[8], da[8], vb[8], db[8];
+  if (nfull > 0) load(va, da, 0);
+  int ks = 0;
+  for (; ks + 2 <= nfull; ks += 2) {
+    load(vb, db, ks + 1);
+    step(va, da, ks);
+    if (ks + 2 < nfull) load(va, da, ks + 2);
+    step(vb, db, ks + 1);
+  }
+  if (ks < nfull) step(va, da, ks++);
+  if (ks < S.ks_a) {   // the partial last step
+    const int k0 = 32 * ks + 8 * quad;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool in = k0 + e < np;
+      va[e] = in ? *gmem(row + 32 * ks + e) : 0.0;
+      da[e] = in ? *gmem(dphi + 32 * ks + e) : 0.0;
+    }
+    step(va, da, ks);
+  }
+  // a row's four quarters sit in lanes l, l + 16, l + 32, l + 48
+  rs += __shfl_xor(rs, 16, 64);
+  rs += __shfl_xor(rs, 32, 64);
+  const auto F = gmem(S.f) + (long)i * S.tpad * P.ntheta;
+  if (!jin) return;
+  if (quad == 0) F[j] = rs;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = 1 + 16 * m + 4 * quad + r;
+      if (t <= 2 * P.lmax) F[(long)t * P.ntheta + j] = (double)acc[m][r];
+    }
+}
+
+// Synthesis: a wavefront per (shell blockIdx.y, 16 theta rows, 16 SYN_NT phi
+// cells); Phihat = G[0][j] TT[0][k] (FP64) + the m >= 1 sum.  Rows past the
+// mesh read its row j0 and store nothing; steps whose 32 modes are all at
+// most 2L load without guards.
+constexpr int SYN_NT = 4;   // 16-cell phi tiles per wavefront
+__global__ __launch_bounds__(256) void k_sep_phi_syn_bf16(PlanDev P, SepDev S, double *phi) {
+  const int lane = threadIdx.x & 63, quad = lane >> 4;
+  const int i = blockIdx.y;
+  const int ntj = (P.ntheta + 15) / 16, ntk = (P.nphi + 16 * SYN_NT - 1) / (16 * SYN_NT);
+  const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wt >= ntj * ntk) return;   // wavefront-uniform; no barrier
+  const int j0 = (wt % ntj) * 16, kt0 = (wt / ntj) * SYN_NT;
+  const int ja = min(j0 + (lane & 15), P.ntheta - 1);   // this lane's G row
+  const double *G = S.g + (long)i * S.tpad * P.ntheta;
+  const double *gcol = G + (long)(1 + 8 * quad) * P.ntheta + ja;   // mode 1 + 8 quad of row ja
+  const int tmax = 2 * P.lmax, nks = S.ks_s, nfull = tmax / 32;
+  const long tstride = P.ntheta;
+
+  f4 acc[SYN_NT];
+#pragma unroll
+  for (int n = 0; n < SYN_NT; ++n) acc[n] = f4{};
+  auto load = [&](double (&v)[8], int ks) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = *gmem(gcol + (32L * ks + e) * tstride);
+  };
+  auto step = [&](const double (&v)[8], int ks) __attribute__((always_inline)) {
+    u4 a[3];
+    split8(v, a);
+#pragma unroll
+    for (int n = 0; n < SYN_NT; ++n) {
+      const int nt = min(kt0 + n, S.nt_s - 1);   // tiles past the mesh are not stored
+      u4 b[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) b[q] = frag(S.ttf, ((long)ks * S.nt_s + nt) * 3 + q, lane);
+      acc[n] = mma6(a, b, acc[n]);
+    }
+  };
+  double va[8], vb[8];
+  if (nfull > 0) load(va, 0);
+  int ks = 0;
+  for (; ks + 2 <= nfull; ks += 2) {
+    load(vb, ks + 1);
+    step(va, ks);
+    if (ks + 2 < nfull) load(va, ks + 2);
+    step(vb, ks + 1);
+  }
+  if (ks < nfull) step(va, ks++);
+  if (ks < nks) {   // the partial last step
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int t = 1 + 32 * ks + 8 * quad + e;
+      va[e] = t <= tmax ? *gmem(gcol + (32L * ks + e) * tstride) : 0.0;
+    }
+    step(va, ks);
+  }
+  const auto tt0 = gmem(S.tw) + (long)S.tpad * P.nphi;   // TT row 0 (m = 0)
+  const auto out = gmem(phi) + (long)i * P.ncell;
+  const auto g0 = gmem(G);
+#pragma unroll
+  for (int n = 0; n < SYN_NT; ++n) {
+    const int k = 16 * (kt0 + n) + (lane & 15);
+    if (k >= P.nphi) continue;
+    const double c0 = tt0[k];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jj = j0 + 4 * quad + r;
+      if (jj < P.ntheta) out[(long)jj * P.nphi + k] = g0[jj] * c0 + (double)acc[n][r];
+    }
+  }
+}
+
+inline unsigned cdiv(long n, long d) { return (unsigned)((n + d - 1) / d); }
+
+}  // namespace
+
+hipError_t launch_sep_split_tables(const PlanDev &P, const SepDev &S, hipStream_t s) {
+  const long n = ((long)S.ks_a * S.mt_a + (long)S.ks_s * S.nt_s) * 64;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sep_split_tables, dim3(cdiv(n, 256)), dim3(256), 0, s, P, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_phi_anal_bf16(const PlanDev &P, const SepDev &S, const double *rho, hipStream_t s) {
+  const dim3 grid(cdiv(cdiv(P.ntheta, 16), 4), (unsigned)P.nr);
+  // 16-byte density loads need 16-byte aligned rows (the block-mean copy is)
+  const int rho16 = ((uintptr_t)rho % 16) == 0;
+  switch (S.mt_a) {
+#define MPOLE_ANAL(MT) \
+  case MT: hipLaunchKernelGGL(k_sep_phi_anal_bf16<MT>, grid, dim3(256), 0, s, P, S, rho, rho16); break;
+    MPOLE_ANAL(0) MPOLE_ANAL(1) MPOLE_ANAL(2) MPOLE_ANAL(3) MPOLE_ANAL(4)
+    MPOLE_ANAL(5) MPOLE_ANAL(6) MPOLE_ANAL(7) MPOLE_ANAL(8)
+#undef MPOLE_ANAL
+    default: return hipErrorInvalidValue;   // 2L <= 128
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_phi_syn_bf16(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s) {
+  const long waves = (long)cdiv(P.ntheta, 16) * cdiv(P.nphi, 16 * SYN_NT);
+  hipLaunchKernelGGL(k_sep_phi_syn_bf16, dim3(cdiv(waves, 4), (unsigned)P.nr), dim3(256), 0, s, P, S, phi);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? launch_sep_block_means(P, S, phi, s) : e;
+}
+
+}  // namespace mpole

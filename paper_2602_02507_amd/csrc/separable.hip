@@ -421,7 +421,12 @@ hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, double *phi, hi
   hipLaunchKernelGGL(k_sep_phi_syn, dim3(tiles(P.ntheta, BM) * tiles(P.nphi, BN), P.nr), dim3(NTHREADS), 0, s, P, S,
                      phi);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && S.max_avg > 0) {
+  return e == hipSuccess ? launch_sep_block_means(P, S, phi, s) : e;
+}
+
+hipError_t launch_sep_block_means(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (S.max_avg > 0) {
     hipLaunchKernelGGL(k_sep_block_mean, dim3(tiles(S.max_avg, 256), P.nr), dim3(256), 0, s, P, S, phi);
     e = hipGetLastError();
   }

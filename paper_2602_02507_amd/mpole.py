@@ -13,8 +13,9 @@ import numpy as np
 
 from . import build as _build
 
-FP64, BF16X3, FP16X2, FP64_SEPARABLE = 0, 1, 2, 3
-_PRECISIONS = {"fp64": FP64, "bf16x3": BF16X3, "fp16x2": FP16X2, "fp64sep": FP64_SEPARABLE}
+FP64, BF16X3, FP16X2, FP64_SEPARABLE, BF16X3_SEPARABLE = 0, 1, 2, 3, 4
+_PRECISIONS = {"fp64": FP64, "bf16x3": BF16X3, "fp16x2": FP16X2, "fp64sep": FP64_SEPARABLE,
+               "bf16x3sep": BF16X3_SEPARABLE}
 
 STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE_ERR_WORKSPACE",
           4: "MPOLE_ERR_DEVICE", 5: "MPOLE_ERR_UNSUPPORTED"}

@@ -81,7 +81,7 @@ def _device_name(device):
 
 def candidates(precision):
     """(moment candidates, expansion candidates) as partial tunings."""
-    if precision == "fp64sep":   # the separable path has no launch knobs
+    if precision in ("fp64sep", "bf16x3sep"):   # the separable paths have no launch knobs
         mom, exp = [{"moment_wgs": 0}], [{"expand_tile_m": 0}]
     elif precision == "fp64":
         mom = [{"moment_wgs": w, "moment_tile_m": 64} for w in (512, 1024, 2048, 4096)]

@@ -112,7 +112,7 @@ def test_batch_field_times_after_eager_solve():
     assert len(ms) == 4 and all(0 < x < 1e3 for x in ms), ms
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3", 1e-6), ("fp64sep", 1e-12)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3", 1e-6), ("fp64sep", 1e-12), ("bf16x3sep", 1e-6)])
 def test_batch_of_genasis_meshes(precision, tol):
     """GenASiS meshes (automatic coarsening: many classes, blocks up to whole
     shells) mixed with a production-rule mesh in one batch: the per-field

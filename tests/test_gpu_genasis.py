@@ -80,7 +80,7 @@ def test_coarsen_rectangular_and_arbitrary_block_maps():
     assert (coarsen_gpu(u, f) == f).all()
 
 
-SOLVE_CASES = [("fp64", 1e-12), ("fp64sep", 1e-12), ("bf16x3", 1e-6), ("fp16x2", 1e-6)]
+SOLVE_CASES = [("fp64", 1e-12), ("fp64sep", 1e-12), ("bf16x3", 1e-6), ("fp16x2", 1e-6), ("bf16x3sep", 1e-6)]
 
 
 @pytest.fixture(scope="module")

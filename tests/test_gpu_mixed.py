@@ -1,5 +1,5 @@
-"""GPU parity of the split-precision paths (BF16 x3, FP16 x2) against the
-FP64 oracle.  Bar: max relative error of the potential <= 1e-6 per cell
+"""GPU parity of the split-precision paths (BF16 x3, FP16 x2, and the
+separable form with BF16 x3 phi transforms) against the FP64 oracle.  Bar: max relative error of the potential <= 1e-6 per cell
 (positive densities), and angular moments within 1e-6 of the size of the
 summed terms of their shell."""
 import numpy as np
@@ -43,7 +43,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16x2"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x2", "bf16x3sep"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_split_precision_matches_oracle(case, precision):
     name, nr, nt, npf, L, r0, merged = case
@@ -59,7 +59,7 @@ def test_split_precision_matches_oracle(case, precision):
     assert ephi <= TOL and eang <= TOL, (ephi, eang)
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16x2"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x2", "bf16x3sep"])
 def test_production_l32_mixed_full(precision):
     """512 log shells x 128 x 256, lmax 32, coarsened: the mixed-precision
     benchmark workload, every cell against the oracle."""

@@ -65,6 +65,24 @@ def test_separable_matches_oracle(case):
         assert np.max(np.abs(got[k] - ref[k])) / scale <= TOL, k
 
 
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_separable_bf16x3_matches_oracle(case):
+    """The separable form with BF16 x3 phi transforms on the same meshes
+    (degenerate ones included: one shell row, one theta row, one phi cell,
+    lmax 0), to the mixed-precision bar of 1e-6 of the largest potential."""
+    name, nr, nt, npf, L, r0, merged = case
+    seed = sum(map(ord, name))
+    m = wl.random_mesh(seed, nr, nt, npf, L, r0=r0)
+    if merged:
+        m.shell_class, m.class_block = wl.random_merge(seed + 1, nr, nt, npf)
+    rho = wl.random_density(seed + 2, m.shape, positive=False)
+    got = run(m, rho, "bf16x3sep")
+    ref = oracle.solve(rho=rho, **m.oracle_kwargs())
+    ephi, eang = compare(m, rho, got, ref)
+    print(name, "bf16x3sep phi %.3e ang %.3e" % (ephi, eang))
+    assert ephi <= 1e-6 and eang <= 1e-6, (ephi, eang)
+
+
 @pytest.mark.parametrize("name", ["spheroid", "production"])
 def test_separable_workloads_full(name):
     m, rho = wl.workload(name)
