@@ -184,23 +184,37 @@ def main():
                                                                                    flush=True))
         tune_s = time.perf_counter() - t0
 
-    fp64 = None
-    if precision != "fp64" and not args.no_fp64:
-        # the plain FP64 GPU solve of the same workload, for the speedup figure
-        p64 = mpole.Plan.from_mesh(mesh, precision="fp64", device=dev, tuning=tunings.get("fp64"))
-        o64 = p64.empty_outputs()
+    def time_path(prec):
+        """Mean solve time of another precision path on the same workload (and its potential)."""
+        p2 = mpole.Plan.from_mesh(mesh, precision=prec, device=dev, tuning=tunings.get(prec))
+        o2 = p2.empty_outputs()
         for _ in range(args.warmup):
-            p64.solve_into(rho, **o64)
+            p2.solve_into(rho, **o2)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record(stream)
         for _ in range(args.steps):
-            p64.solve_into(rho, **o64)
+            p2.solve_into(rho, **o2)
         b.record(stream)
         torch.cuda.synchronize()
-        fp64 = {"ms_per_step": a.elapsed_time(b) / args.steps, "phi": o64["phi"]}
-        del p64
+        del p2
+        return {"ms_per_step": a.elapsed_time(b) / args.steps, "phi": o2["phi"]}
+
+    fp64 = None
+    if precision != "fp64" and not args.no_fp64:
+        # the plain FP64 GPU solve of the same workload, for the speedup figure
+        fp64 = time_path("fp64")
         print("bench: fp64 path %.4f ms/solve" % fp64["ms_per_step"], file=sys.stderr, flush=True)
+    # the separable forms of the same solve, reported beside the dense one
+    others = {}
+    if precision == "bf16x3" and fp64 is not None:
+        for prec in ("bf16x3sep", "fp64sep"):
+            r = time_path(prec)
+            err = float((r["phi"] - fp64["phi"]).abs().div(fp64["phi"].abs()).max())
+            others[prec] = {"ms_per_step": r["ms_per_step"], "speedup_vs_fp64": fp64["ms_per_step"] / r["ms_per_step"],
+                            "max_rel_err_vs_fp64_gpu": err}
+            print("bench: %s path %.4f ms/solve, max rel err vs FP64 %.2e" % (prec, r["ms_per_step"], err),
+                  file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -295,6 +309,8 @@ def main():
         result["fp64_ms_per_step"] = fp64["ms_per_step"]
         result["speedup_vs_fp64"] = fp64["ms_per_step"] / ms
         result["max_rel_err_vs_fp64_gpu"] = float((out["phi"] - fp64["phi"]).abs().div(fp64["phi"].abs()).max())
+    if others:
+        result["separable_paths"] = others
 
     if not (args.no_cpu_baseline and args.no_check):
         import oracle

@@ -21,6 +21,9 @@ constexpr int kLargeBlock = 64;
 // chunks whose partial sums are combined in chunk order).
 constexpr int kLargeChunk = 4096;
 // Rows of single cells copied per workgroup by the band kernel.
+// modes per workgroup of the radial scan (kScanModes x 8 bytes of each row;
+// namp is a multiple of 16)
+constexpr int kScanModes = 16;
 constexpr int kBandCopyRows = 8;
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.

@@ -600,7 +600,7 @@ int phase_wgs_host(const mpole_plan_t *p, int h) {
     case PH_SPLITROWS: return p->precision == MPOLE_FP16X2 ? p->nr : 0;
     case PH_MOMENT: return p->wg_mom;
     case PH_REDUCE: return (p->namp + 255) / 256 * p->nr;
-    case PH_SCAN: return p->namp / 16;
+    case PH_SCAN: return p->namp / kScanModes;
     case PH_COEF: return p->nplanes ? p->nr : 0;
     case PH_EXPAND: return p->wg_exp;
   }

@@ -12,8 +12,8 @@
 //             Solution C[i][n] = -Delta_m/(2l+1) (<r^l> M^I_c + <r^-(l+1)> M^R_c)
 //
 // The scan is a segmented prefix/suffix sum over radius, one segment per mode.
-// A workgroup owns 16 consecutive modes (coalesced 128-byte rows) and splits
-// radius into 64 chunks: each thread sums one chunk of one mode, then one
+// A workgroup owns kScanModes (16) consecutive modes (coalesced 128-byte row
+// segments) and splits radius into 64 chunks: each thread sums one chunk of one mode, then one
 // wavefront per mode scans the 64 chunk totals with lane shuffles (prefix for
 // the outward sums, suffix for the inward ones), and a second pass writes
 // edges and coefficients.  Chunk-boundary edges are always the scanned totals
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
   if (ang_out != nullptr && n < P.nam) ang_out[(size_t)i * P.nam + n] = s;
 }
 
-constexpr int SCAN_MODES = 16;    // modes per workgroup (one 128-byte row segment)
+constexpr int SCAN_MODES = kScanModes;   // modes per workgroup
 constexpr int SCAN_CHUNKS = 64;   // radial chunks per mode (one per lane of a wavefront)
 
 __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {

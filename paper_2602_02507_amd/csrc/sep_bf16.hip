@@ -235,74 +235,88 @@ __global__ __launch_bounds__(256) void k_sep_phi_anal_bf16(PlanDev P, SepDev S, 
     }
 }
 
-// Synthesis: a wavefront per (shell blockIdx.y, 16 theta rows, 16 SYN_NT phi
-// cells); Phihat = G[0][j] TT[0][k] (FP64) + the m >= 1 sum.  Rows past the
-// mesh read its row j0 and store nothing; steps whose 32 modes are all at
-// most 2L load without guards.
-constexpr int SYN_NT = 4;   // 16-cell phi tiles per wavefront
+// Synthesis: a wavefront per (shell blockIdx.y, 16 theta rows, a chunk of
+// SYN_NT phi tiles of 16); Phihat = G[0][j] TT[0][k] (FP64) + the m >= 1 sum.
+// The wavefront loads and splits its rows' NKS K steps of G once, then walks
+// its phi tiles two at a time, so the stores of one pair drain while the
+// next is computed.  Rows past the
+// mesh read its last row and store nothing.
+constexpr int SYN_NT = 16;   // 16-cell phi tiles per wavefront
+template <int NKS>
 __global__ __launch_bounds__(256) void k_sep_phi_syn_bf16(PlanDev P, SepDev S, double *phi) {
   const int lane = threadIdx.x & 63, quad = lane >> 4;
   const int i = blockIdx.y;
-  const int ntj = (P.ntheta + 15) / 16, ntk = (P.nphi + 16 * SYN_NT - 1) / (16 * SYN_NT);
-  const int wt = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wt >= ntj * ntk) return;   // wavefront-uniform; no barrier
-  const int j0 = (wt % ntj) * 16, kt0 = (wt / ntj) * SYN_NT;
+  const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (j0 >= P.ntheta) return;   // wavefront-uniform; no barrier
+  const int nt0 = blockIdx.z * SYN_NT, nt1 = min(nt0 + SYN_NT, S.nt_s);
   const int ja = min(j0 + (lane & 15), P.ntheta - 1);   // this lane's G row
   const double *G = S.g + (long)i * S.tpad * P.ntheta;
-  const double *gcol = G + (long)(1 + 8 * quad) * P.ntheta + ja;   // mode 1 + 8 quad of row ja
-  const int tmax = 2 * P.lmax, nks = S.ks_s, nfull = tmax / 32;
-  const long tstride = P.ntheta;
+  const int tmax = 2 * P.lmax;
 
-  f4 acc[SYN_NT];
+  // the split G fragments of every K step (modes 1 + 32 ks + 8 quad .. +7)
+  u4 a[NKS > 0 ? NKS : 1][3];
+  {
+    double v[NKS > 0 ? NKS : 1][8];
 #pragma unroll
-  for (int n = 0; n < SYN_NT; ++n) acc[n] = f4{};
-  auto load = [&](double (&v)[8], int ks) __attribute__((always_inline)) {
+    for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = *gmem(gcol + (32L * ks + e) * tstride);
-  };
-  auto step = [&](const double (&v)[8], int ks) __attribute__((always_inline)) {
-    u4 a[3];
-    split8(v, a);
+      for (int e = 0; e < 8; ++e) {
+        const int t = 1 + 32 * ks + 8 * quad + e;
+        v[ks][e] = t <= tmax ? *gmem(G + (long)t * P.ntheta + ja) : 0.0;
+      }
 #pragma unroll
-    for (int n = 0; n < SYN_NT; ++n) {
-      const int nt = min(kt0 + n, S.nt_s - 1);   // tiles past the mesh are not stored
-      u4 b[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) b[q] = frag(S.ttf, ((long)ks * S.nt_s + nt) * 3 + q, lane);
-      acc[n] = mma6(a, b, acc[n]);
-    }
-  };
-  double va[8], vb[8];
-  if (nfull > 0) load(va, 0);
-  int ks = 0;
-  for (; ks + 2 <= nfull; ks += 2) {
-    load(vb, ks + 1);
-    step(va, ks);
-    if (ks + 2 < nfull) load(va, ks + 2);
-    step(vb, ks + 1);
+    for (int ks = 0; ks < NKS; ++ks) split8(v[ks], a[ks]);
   }
-  if (ks < nfull) step(va, ks++);
-  if (ks < nks) {   // the partial last step
+  // m = 0 term of this lane's four output rows
+  double g0[4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int t = 1 + 32 * ks + 8 * quad + e;
-      va[e] = t <= tmax ? *gmem(gcol + (32L * ks + e) * tstride) : 0.0;
-    }
-    step(va, ks);
-  }
+  for (int r = 0; r < 4; ++r) g0[r] = *gmem(G + min(j0 + 4 * quad + r, P.ntheta - 1));
   const auto tt0 = gmem(S.tw) + (long)S.tpad * P.nphi;   // TT row 0 (m = 0)
   const auto out = gmem(phi) + (long)i * P.ncell;
-  const auto g0 = gmem(G);
+
+  auto load_b = [&](u4 (&b)[NKS > 0 ? NKS : 1][3], int nt) __attribute__((always_inline)) {
 #pragma unroll
-  for (int n = 0; n < SYN_NT; ++n) {
-    const int k = 16 * (kt0 + n) + (lane & 15);
-    if (k >= P.nphi) continue;
-    const double c0 = tt0[k];
+    for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int jj = j0 + 4 * quad + r;
-      if (jj < P.ntheta) out[(long)jj * P.nphi + k] = g0[jj] * c0 + (double)acc[n][r];
+      for (int q = 0; q < 3; ++q) b[ks][q] = frag(S.ttf, ((long)ks * S.nt_s + nt) * 3 + q, lane);
+  };
+  auto store = [&](f4 acc, int nt) __attribute__((always_inline)) {
+    const int k = 16 * nt + (lane & 15);
+    if (k < P.nphi) {
+      const double c0 = tt0[k];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jj = j0 + 4 * quad + r;
+        if (jj < P.ntheta) out[(long)jj * P.nphi + k] = g0[r] * c0 + (double)acc[r];
+      }
     }
+  };
+  // two tiles at a time, each product sum split over two accumulators (the
+  // leading and the small products): four independent MFMA chains
+  u4 ba[NKS > 0 ? NKS : 1][3], bb[NKS > 0 ? NKS : 1][3];
+  for (int nt = nt0; nt < nt1; nt += 2) {
+    const int nu = min(nt + 1, nt1 - 1);   // a single last tile is computed twice, stored once
+    load_b(ba, nt);
+    load_b(bb, nu);
+    f4 p0 = f4{}, q0 = f4{}, p1 = f4{}, q1 = f4{};
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const u4(&x)[3] = a[ks];
+      p0 = mma(x[0], ba[ks][0], p0);
+      q0 = mma(x[0], ba[ks][2], q0);
+      p1 = mma(x[0], bb[ks][0], p1);
+      q1 = mma(x[0], bb[ks][2], q1);
+      p0 = mma(x[0], ba[ks][1], p0);
+      q0 = mma(x[2], ba[ks][0], q0);
+      p1 = mma(x[0], bb[ks][1], p1);
+      q1 = mma(x[2], bb[ks][0], q1);
+      p0 = mma(x[1], ba[ks][0], p0);
+      q0 = mma(x[1], ba[ks][1], q0);
+      p1 = mma(x[1], bb[ks][0], p1);
+      q1 = mma(x[1], bb[ks][1], q1);
+    }
+    store(p0 + q0, nt);
+    if (nu != nt) store(p1 + q1, nu);
   }
 }
 
@@ -333,8 +347,14 @@ hipError_t launch_sep_phi_anal_bf16(const PlanDev &P, const SepDev &S, const dou
 }
 
 hipError_t launch_sep_phi_syn_bf16(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s) {
-  const long waves = (long)cdiv(P.ntheta, 16) * cdiv(P.nphi, 16 * SYN_NT);
-  hipLaunchKernelGGL(k_sep_phi_syn_bf16, dim3(cdiv(waves, 4), (unsigned)P.nr), dim3(256), 0, s, P, S, phi);
+  const dim3 grid(cdiv(cdiv(P.ntheta, 16), 4), (unsigned)P.nr, cdiv(S.nt_s, SYN_NT));
+  switch (S.ks_s) {
+#define MPOLE_SYN(NKS) \
+  case NKS: hipLaunchKernelGGL(k_sep_phi_syn_bf16<NKS>, grid, dim3(256), 0, s, P, S, phi); break;
+    MPOLE_SYN(0) MPOLE_SYN(1) MPOLE_SYN(2) MPOLE_SYN(3) MPOLE_SYN(4)
+#undef MPOLE_SYN
+    default: return hipErrorInvalidValue;   // 2L <= 128
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? launch_sep_block_means(P, S, phi, s) : e;
 }

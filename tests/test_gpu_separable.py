@@ -83,6 +83,33 @@ def test_separable_bf16x3_matches_oracle(case):
     assert ephi <= 1e-6 and eang <= 1e-6, (ephi, eang)
 
 
+def test_separable_bf16x3_unaligned_density_and_odd_phi():
+    """The BF16 x3 phi analysis loads 16 bytes at a time only from 16-byte
+    aligned rows: a density view starting one double into its storage, and a
+    mesh with an odd phi count, take the element-wise loads and give the
+    aligned result bitwise; both against the oracle at 1e-6."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_02507_amd import mpole
+    for npf in (26, 27):
+        m = wl.random_mesh(77 + npf, 40, 20, npf, 12, r0=0.01)
+        m.shell_class, m.class_block = wl.random_merge(78, 40, 20, npf)
+        rho = wl.random_density(79, m.shape, positive=False)
+        plan = mpole.Plan.from_mesh(m, precision="bf16x3sep")
+        a = plan.solve(torch.from_numpy(rho).cuda())["phi"]
+        store = torch.zeros(rho.size + 1, dtype=torch.float64, device="cuda")
+        view = store[1:].view(m.shape)
+        view.copy_(torch.from_numpy(rho).cuda())
+        assert view.data_ptr() % 16 == 8
+        b = plan.solve(view)["phi"]
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), npf
+        ref = oracle.solve(rho=rho, **m.oracle_kwargs())["phi"]
+        rel = np.max(np.abs(a.cpu().numpy() - ref)) / np.max(np.abs(ref))
+        assert rel <= 1e-6, (npf, rel)
+
+
 @pytest.mark.parametrize("name", ["spheroid", "production"])
 def test_separable_workloads_full(name):
     m, rho = wl.workload(name)
