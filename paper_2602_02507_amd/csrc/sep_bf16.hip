@@ -15,14 +15,14 @@
 // FP64 kernels of the separable path.
 //
 // MFMA v_mfma_f32_16x16x32_bf16 (16-row tiles, 32-deep K steps: many short
-// wavefronts to keep enough density loads in flight).  No LDS: each lane of a
-// wavefront loads exactly the 8 values of its own fragment and splits them in
-// registers.
+// wavefronts to keep enough density loads in flight).  Each lane of a
+// wavefront loads exactly the 8 values of its own density or G fragment and
+// splits them in registers:
 //   analysis:  the density fragment of lane l is row j0 + l % 16, phi cells
 //              32 ks + 8 (l / 16) .. +7 (64 contiguous bytes; the four lanes
 //              of a row cover its 256-byte run of the K step); the
 //              trig-weight fragments come from a bind-time table in fragment
-//              order.
+//              order, through LDS (one copy per workgroup and K step).
 //   synthesis: the G fragment of lane l is theta row j0 + l % 16 at modes
 //              1 + 32 ks + 8 (l / 16) .. +7 (each load coalesced across 16
 //              rows); the trig fragments come from a table in fragment order.
@@ -52,20 +52,22 @@ __device__ inline f4 mma(u4 a, u4 b, f4 c) {
 // planes together); the FP32 value is then exactly hi + mid + lo: hi is its
 // nearest bfloat16, the remainders are exact FP32 differences, and the last
 // one has at most 8 significant bits.
-__device__ inline uint32_t pack2(__bf16 a, __bf16 b) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
-}
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 __device__ inline void split8(const double (&v)[8], u4 (&p)[3]) {
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    const float x0 = (float)v[2 * d], x1 = (float)v[2 * d + 1];
-    const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
-    const float r0 = x0 - (float)h0, r1 = x1 - (float)h1;
-    const __bf16 m0 = (__bf16)r0, m1 = (__bf16)r1;
-    const float s0 = r0 - (float)m0, s1 = r1 - (float)m1;
-    p[0][d] = pack2(h0, h1);
-    p[1][d] = pack2(m0, m1);
-    p[2][d] = pack2((__bf16)s0, (__bf16)s1);
+    float x0 = (float)v[2 * d], x1 = (float)v[2 * d + 1];
+    // keep the two roundings apart (FP64 -> FP32, then FP32 -> BF16)
+    asm volatile("" : "+v"(x0), "+v"(x1));
+    const f2 x = {x0, x1};
+    const bf2 h = __builtin_convertvector(x, bf2);
+    const f2 r = x - __builtin_convertvector(h, f2);
+    const bf2 m = __builtin_convertvector(r, bf2);
+    const f2 t = r - __builtin_convertvector(m, f2);
+    p[0][d] = __builtin_bit_cast(uint32_t, h);
+    p[1][d] = __builtin_bit_cast(uint32_t, m);
+    p[2][d] = __builtin_bit_cast(uint32_t, __builtin_convertvector(t, bf2));
   }
 }
 
@@ -150,25 +152,30 @@ __device__ inline void load8(const double *p, double (&v)[8]) {
 }
 
 // Analysis: a wavefront per (shell blockIdx.y, 16 theta rows), all m >= 1
-// modes (MT tiles of 16); 4 wavefronts per workgroup on adjacent row tiles.
-// Rows past the mesh read its row j0 and store nothing (each output row
-// depends on its own density row only).  Steps whose 32 cells all lie inside
-// the row load without guards, two at a time (one ahead); a last partial step
-// loads element by element.
+// modes (MT tiles of 16); 4 wavefronts per workgroup on adjacent row tiles of
+// one shell.  The workgroup copies each K step's trig-weight fragments
+// (MT x 3 KB) to LDS once, one step ahead in registers, and its wavefronts
+// read them from there.  Rows past the mesh read its row j0 and store nothing
+// (each output row depends on its own density row only); a row tile wholly
+// past the mesh only helps with the copies.  Full steps (32 cells inside the
+// row) load without guards; a last partial step loads element by element.
 template <int MT>
 __global__ __launch_bounds__(256) void k_sep_phi_anal_bf16(PlanDev P, SepDev S, const double *rho, int rho16) {
+  constexpr int NF = MT > 0 ? MT * 3 * 64 : 64;   // fragment entries (16 bytes) per K step
+  constexpr int CP = (NF + 255) / 256;             // copied per thread
+  __shared__ u4 As[2][NF];
   const int lane = threadIdx.x & 63, quad = lane >> 4;
   const int i = blockIdx.y;
   const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (j0 >= P.ntheta) return;   // wavefront-uniform; the kernel has no barrier
+  const bool tile_in = j0 < P.ntheta;   // wavefront-uniform
   const int j = j0 + (lane & 15);
   const bool jin = j < P.ntheta;
-  const int jr = jin ? j : j0;
+  const int jr = jin ? j : (tile_in ? j0 : 0);
   const long o = (long)i * P.ncell + (long)jr * P.nphi;
   const bool alt = S.rowalt != nullptr && S.rowalt[(long)i * P.ntheta + jr];
   const double *row = (alt ? S.shat : rho) + o + 8 * quad;   // this lane's cells of step 0
   const double *dphi = S.tw + 8 * quad;                      // TW row 0: dphi_k
-  const int np = P.nphi, nfull = np / 32;
+  const int np = P.nphi, nks = S.ks_a;
   const bool vec = rho16 && (np & 1) == 0;   // rows start 16-byte aligned
 
   f4 acc[MT > 0 ? MT : 1];
@@ -177,49 +184,79 @@ __global__ __launch_bounds__(256) void k_sep_phi_anal_bf16(PlanDev P, SepDev S, 
   double rs = 0.0;   // FP64 row sum of dphi_k rho over this lane's cells
 
   auto load = [&](double (&v)[8], double (&d)[8], int ks) __attribute__((always_inline)) {
-    if (vec) {
-      load8(row + 32 * ks, v);
-    } else {
+    if (32 * ks + 32 <= np) {
+      if (vec) {
+        load8(row + 32 * ks, v);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = *gmem(row + 32 * ks + e);
-    }
-    load8(dphi + 32 * ks, d);
-  };
-  auto step = [&](const double (&v)[8], const double (&d)[8], int ks) __attribute__((always_inline)) {
+        for (int e = 0; e < 8; ++e) v[e] = *gmem(row + 32 * ks + e);
+      }
+      load8(dphi + 32 * ks, d);
+    } else {   // the partial last step
+      const int k0 = 32 * ks + 8 * quad;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) rs += d[e] * v[e];
-    if constexpr (MT > 0) {
-      u4 b[3];
-      split8(v, b);
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        u4 a[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) a[q] = frag(S.twf, ((long)ks * MT + m) * 3 + q, lane);
-        acc[m] = mma6(a, b, acc[m]);
+      for (int e = 0; e < 8; ++e) {
+        const bool in = k0 + e < np;
+        v[e] = in ? *gmem(row + 32 * ks + e) : 0.0;
+        d[e] = in ? *gmem(dphi + 32 * ks + e) : 0.0;
       }
     }
   };
-  double va[8], da[8], vb[8], db[8];
-  if (nfull > 0) load(va, da, 0);
-  int ks = 0;
-  for (; ks + 2 <= nfull; ks += 2) {
-    load(vb, db, ks + 1);
-    step(va, da, ks);
-    if (ks + 2 < nfull) load(va, da, ks + 2);
-    step(vb, db, ks + 1);
-  }
-  if (ks < nfull) step(va, da, ks++);
-  if (ks < S.ks_a) {   // the partial last step
-    const int k0 = 32 * ks + 8 * quad;
+  u4 fr[CP];   // this thread's share of a step's fragments, one step ahead
+  auto fetch = [&](int ks) __attribute__((always_inline)) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const bool in = k0 + e < np;
-      va[e] = in ? *gmem(row + 32 * ks + e) : 0.0;
-      da[e] = in ? *gmem(dphi + 32 * ks + e) : 0.0;
+    for (int c = 0; c < CP; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      if (MT > 0 && e < NF) fr[c] = frag(S.twf, (long)ks * (NF / 64) + e / 64, e % 64);
     }
-    step(va, da, ks);
+  };
+  auto put = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      if (MT > 0 && e < NF) As[buf][e] = fr[c];
+    }
+  };
+  double v[8], d[8], vn[8], dn[8];
+  if (nks > 0) {
+    fetch(0);
+    if (tile_in) load(v, d, 0);
+    put(0);
   }
+  __syncthreads();
+  for (int ks = 0; ks < nks; ++ks) {
+    const bool more = ks + 1 < nks;
+    if (more) {
+      fetch(ks + 1);
+      if (tile_in) load(vn, dn, ks + 1);
+    }
+    if (tile_in) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rs += d[e] * v[e];
+      if constexpr (MT > 0) {
+        u4 b[3];
+        split8(v, b);
+        const u4 *st = As[ks & 1];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          u4 a[3];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) a[q] = st[(m * 3 + q) * 64 + lane];
+          acc[m] = mma6(a, b, acc[m]);
+        }
+      }
+    }
+    if (more) {
+      put((ks + 1) & 1);   // that buffer was last read in step ks - 1
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        v[e] = vn[e];
+        d[e] = dn[e];
+      }
+    }
+    __syncthreads();
+  }
+  if (!tile_in) return;
   // a row's four quarters sit in lanes l, l + 16, l + 32, l + 48
   rs += __shfl_xor(rs, 16, 64);
   rs += __shfl_xor(rs, 32, 64);
