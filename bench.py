@@ -115,10 +115,31 @@ def copy_calibration(mib):
     print("copy calibration: 5 copies of %d MiB" % mib, flush=True)
 
 
+def roofline_hbm(plan, phases, workload):
+    """Roofline of the BF16 x3 separable path, whose phi transforms are bound
+    by HBM: algorithmic bytes of the dominant transform / its phase duration
+    (the synthesis phase includes the block means of the potential) against
+    the HBM peak.  Analysis: the density read once (8 B per cell) and F
+    written ((2L+1) x ntheta x 8 B per shell); synthesis: G read and the
+    potential written once."""
+    dom = max(("moment", "expand"), key=lambda k: phases[k][0])
+    dom_ms = phases[dom][0] / max(phases[dom][1], 1)
+    cells = float(plan.nr) * plan.shape[1] * plan.shape[2]
+    modes = (2 * plan.lmax + 1) * float(plan.nr) * plan.shape[1]
+    nbytes = 8.0 * cells + 8.0 * modes
+    achieved = nbytes / (dom_ms * 1e-3)
+    return {"bound": "hbm", "kernel": kernel_name("bf16x3sep", dom), "achieved": achieved / 1e9, "peak": 8000.0,
+            "unit": "GB/s", "frac": achieved / 8e12, "traffic": measured_traffic(workload, dom), "launch_ms": dom_ms,
+            "algorithmic_bytes_per_launch": nbytes,
+            "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
+
+
 def roofline(plan, phases, precision, workload):
     """Roofline position of the dominant contraction from the plan's per-phase
     HIP event timings: algorithmic flops of one launch / its mean duration
     against the MFMA peak of the arithmetic type."""
+    if precision == "bf16x3sep":
+        return roofline_hbm(plan, phases, workload)
     mflops, eflops, _ = plan.work()
     dom = max(("moment", "expand"), key=lambda k: phases[k][0])
     dom_ms = phases[dom][0] / max(phases[dom][1], 1)

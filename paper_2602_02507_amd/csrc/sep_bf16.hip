@@ -32,6 +32,8 @@
 //
 // Both transforms are HBM-bound: the analysis reads the density once (8 B per
 // cell) and the synthesis writes the potential once (8 B per cell).
+#include <algorithm>
+
 #include "device_util.h"
 #include "split_util.h"
 
@@ -273,19 +275,18 @@ __global__ __launch_bounds__(256) void k_sep_phi_anal_bf16(PlanDev P, SepDev S, 
 }
 
 // Synthesis: a wavefront per (shell blockIdx.y, 16 theta rows, a chunk of
-// SYN_NT phi tiles of 16); Phihat = G[0][j] TT[0][k] (FP64) + the m >= 1 sum.
+// ntw phi tiles of 16); Phihat = G[0][j] TT[0][k] (FP64) + the m >= 1 sum.
 // The wavefront loads and splits its rows' NKS K steps of G once, then walks
 // its phi tiles two at a time, so the stores of one pair drain while the
 // next is computed.  Rows past the
 // mesh read its last row and store nothing.
-constexpr int SYN_NT = 16;   // 16-cell phi tiles per wavefront
 template <int NKS>
-__global__ __launch_bounds__(256) void k_sep_phi_syn_bf16(PlanDev P, SepDev S, double *phi) {
+__global__ __launch_bounds__(256) void k_sep_phi_syn_bf16(PlanDev P, SepDev S, double *phi, int ntw) {
   const int lane = threadIdx.x & 63, quad = lane >> 4;
   const int i = blockIdx.y;
   const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
   if (j0 >= P.ntheta) return;   // wavefront-uniform; no barrier
-  const int nt0 = blockIdx.z * SYN_NT, nt1 = min(nt0 + SYN_NT, S.nt_s);
+  const int nt0 = blockIdx.z * ntw, nt1 = min(nt0 + ntw, S.nt_s);
   const int ja = min(j0 + (lane & 15), P.ntheta - 1);   // this lane's G row
   const double *G = S.g + (long)i * S.tpad * P.ntheta;
   const int tmax = 2 * P.lmax;
@@ -384,10 +385,15 @@ hipError_t launch_sep_phi_anal_bf16(const PlanDev &P, const SepDev &S, const dou
 }
 
 hipError_t launch_sep_phi_syn_bf16(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s) {
-  const dim3 grid(cdiv(cdiv(P.ntheta, 16), 4), (unsigned)P.nr, cdiv(S.nt_s, SYN_NT));
+  // all phi tiles of a row tile in one wavefront (G read once), unless that
+  // leaves fewer than 4096 wavefronts
+  const long rows = (long)cdiv(P.ntheta, 16) * P.nr;
+  const int chunks = (int)std::min<long>(std::max<long>(1, (4096 + rows - 1) / rows), std::max(S.nt_s, 1));
+  const int ntw = (int)cdiv(S.nt_s, chunks);
+  const dim3 grid(cdiv(cdiv(P.ntheta, 16), 4), (unsigned)P.nr, cdiv(S.nt_s, std::max(ntw, 1)));
   switch (S.ks_s) {
 #define MPOLE_SYN(NKS) \
-  case NKS: hipLaunchKernelGGL(k_sep_phi_syn_bf16<NKS>, grid, dim3(256), 0, s, P, S, phi); break;
+  case NKS: hipLaunchKernelGGL(k_sep_phi_syn_bf16<NKS>, grid, dim3(256), 0, s, P, S, phi, ntw); break;
     MPOLE_SYN(0) MPOLE_SYN(1) MPOLE_SYN(2) MPOLE_SYN(3) MPOLE_SYN(4)
 #undef MPOLE_SYN
     default: return hipErrorInvalidValue;   // 2L <= 128
