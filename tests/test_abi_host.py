@@ -150,3 +150,26 @@ def test_gradient_rejects_unbound_plan():
     assert L.mpole_gradient(None, 1, 1, 1, 1, None) == 1
     assert L.mpole_gradient(p.handle, 1, 1, 1, 1, None) == 1      # not bound: nothing launched
     assert b"not bound" in L.mpole_last_error()
+
+
+def test_bf16x3_separable_plan_host_side():
+    """MPOLE_BF16X3_SEPARABLE plans like the FP64 separable path, plus the
+    bind-time fragment-order trig tables: 64 lanes x 16 bytes per (K step,
+    16-row tile, plane), 3 planes; no launch knobs, no block x mode table."""
+    m = wl.production_mesh(32)
+    a = mpole.HostPlan.from_mesh(m, precision="fp64sep")
+    b = mpole.HostPlan.from_mesh(m, precision="bf16x3sep")
+    ks_a, mt_a = -(-m.nphi // 32), -(-2 * m.lmax // 16)
+    ks_s, nt_s = -(-2 * m.lmax // 32), -(-m.nphi // 16)
+    frag = 3 * 64 * 16
+    align = lambda x: -(-x // 256) * 256
+    extra = align(frag * ks_a * mt_a) + align(frag * ks_s * nt_s)
+    assert b.workspace_bytes == a.workspace_bytes + extra, (b.workspace_bytes, a.workspace_bytes, extra)
+    lib = mpole.lib()
+    assert lib.mpole_plan_tune(b.handle, mpole.Tuning(0, 128, 0)) == 5
+    assert lib.mpole_plan_copy_table(b.handle, 0, None, None, None) == 5
+    # lmax 0: no m >= 1 rows, empty fragment tables
+    m0 = wl.production_mesh(0)
+    a0 = mpole.HostPlan.from_mesh(m0, precision="fp64sep")
+    b0 = mpole.HostPlan.from_mesh(m0, precision="bf16x3sep")
+    assert b0.workspace_bytes == a0.workspace_bytes
