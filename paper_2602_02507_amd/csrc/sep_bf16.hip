@@ -6,13 +6,12 @@
 //   analysis   F_i[t][j]      = sum_k TW[t][k] rhohat_i[j][k],
 //   synthesis  Phihat_i[j][k] = sum_t G_i[t][j] TT[t][k],
 // with t the trig modes (t = 0: m = 0; 2m-1 / 2m: cos / sin m phi).  Here
-// the m >= 1 rows of both transforms run on v_mfma_f32_32x32x16_bf16 with
-// every FP64 operand written as hi + mid + lo bfloat16 planes (the remainders
-// taken exactly in FP64) and the six products hi.hi, hi.mid, mid.hi, hi.lo,
-// lo.hi, mid.mid accumulated in FP32; the m = 0 row (the density's
-// dphi-weighted row sum, and the potential's m = 0 term), which carries the
-// monopole, stays FP64.  The theta transforms and the radial sums are the
-// FP64 kernels of the separable path.
+// the m >= 1 rows of both transforms run on BF16 MFMA with every operand
+// written as hi + mid + lo bfloat16 planes (split8 below) and the six
+// products hi.hi, hi.mid, mid.hi, hi.lo, lo.hi, mid.mid accumulated in FP32;
+// the m = 0 row (the density's dphi-weighted row sum, and the potential's
+// m = 0 term), which carries the monopole, stays FP64.  The theta transforms
+// and the radial sums are the FP64 kernels of the separable path.
 //
 // MFMA v_mfma_f32_16x16x32_bf16 (16-row tiles, 32-deep K steps: many short
 // wavefronts to keep enough density loads in flight).  Each lane of a
