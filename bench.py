@@ -340,10 +340,18 @@ def main():
         tot = time.perf_counter() - t0
         t_tables, t_solve = ref["seconds"]
         if not args.no_cpu_baseline:
-            result["cpu_baseline"] = {"value": cell_modes / t_solve, "unit": UNIT, "cores": oracle.threads(),
+            # repeated full solves of the same workload until about 10 s of
+            # solve time have accumulated (the tables are built once per call
+            # and excluded)
+            reps, t_sum = 1, t_solve
+            while t_sum < 10.0 and reps < 64:
+                t_sum += oracle.solve(rho=rho_h, **mesh.oracle_kwargs())["seconds"][1]
+                reps += 1
+            result["cpu_baseline"] = {"value": reps * cell_modes / t_sum, "unit": UNIT, "cores": oracle.threads(),
                                       "kind": "oracle",
-                                      "sample": "one full solve of the same workload (tables excluded: %.2f s; "
-                                                "solve %.2f s; total %.2f s)" % (t_tables, t_solve, tot)}
+                                      "sample": "%d full solves of the same workload, %.2f s of solve time (tables "
+                                                "excluded: %.2f s per call; first call %.2f s in all)"
+                                                % (reps, t_sum, t_tables, tot)}
         if not args.no_check:
             torch.cuda.synchronize()
             phi = out["phi"].cpu().numpy()
