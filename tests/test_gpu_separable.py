@@ -167,7 +167,8 @@ def test_separable_graph_replay_and_restrictions():
         plan.table(0)
 
 
-def test_separable_batch_equals_single_plans_and_graph_replay():
+@pytest.mark.parametrize("precision,tol", [("fp64sep", TOL), ("bf16x3sep", 1e-6)])
+def test_separable_batch_equals_single_plans_and_graph_replay(precision, tol):
     """A batch of separable fields (uneven meshes, lmax, merged blocks)
     gives each field's single-plan result bitwise, eagerly and replayed from
     a HIP graph, and reports per-field completion times."""
@@ -177,15 +178,15 @@ def test_separable_batch_equals_single_plans_and_graph_replay():
     from paper_2602_02507_amd import mpole
     meshes = wl.batch_meshes(6, seed0=7100, nr=(8, 40), ntheta=(8, 24), lmax=(2, 12))
     rhos = [torch.from_numpy(r).cuda() for r in wl.batch_densities(meshes, seed0=7100)]
-    b = mpole.Batch(meshes, precision="fp64sep", rho=rhos)
+    b = mpole.Batch(meshes, precision=precision, rho=rhos)
     b.solve()
     torch.cuda.synchronize()
     for m, r, phi in zip(meshes, rhos, b.phi):
-        single = mpole.Plan.from_mesh(m, precision="fp64sep").solve(r)["phi"]
+        single = mpole.Plan.from_mesh(m, precision=precision).solve(r)["phi"]
         torch.cuda.synchronize()
         assert torch.equal(phi, single)
         ref = oracle.solve(rho=r.cpu().numpy(), **m.oracle_kwargs())["phi"]
-        assert np.max(np.abs(phi.cpu().numpy() - ref) / np.abs(ref)) <= TOL
+        assert np.max(np.abs(phi.cpu().numpy() - ref) / np.abs(ref)) <= tol
     eager = [p.clone() for p in b.phi]
     ms = b.field_ms()
     assert all(0.0 < t for t in ms) and max(ms) < 1e4
