@@ -103,7 +103,7 @@ __global__ __launch_bounds__(LB_THREADS) void k_large_fill(PlanDev P, double *ou
 // and writes the mean down its column.  Coalesced, no member lists; a thread
 // reads its columns before writing them, so in == out is safe.
 template <bool COPY>
-__global__ __launch_bounds__(LB_THREADS) void k_band(PlanDev P, const double *in_, double *out_) {
+__global__ __launch_bounds__(LB_THREADS) void k_band(PlanDev P, const double *in_, double *out_, int skip_nk) {
   const int i = blockIdx.y;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   if (C.bands == nullptr || (int)blockIdx.x >= C.nbands) return;
@@ -118,6 +118,7 @@ __global__ __launch_bounds__(LB_THREADS) void k_band(PlanDev P, const double *in
     return;
   }
   if (bd.w != 1) return;   // large blocks: launch_large
+  if (bd.y == 1 && bd.z <= skip_nk) return;   // averaged by the caller's own kernels
   const auto dom = gmem(P.dom);
   for (int k0 = 0; k0 < P.nphi; k0 += LB_THREADS) {
     const int k = k0 + threadIdx.x;
@@ -142,13 +143,13 @@ __global__ __launch_bounds__(LB_THREADS) void k_band(PlanDev P, const double *in
 
 }  // namespace
 
-hipError_t launch_bands(const PlanDev &P, int mode, const double *in, double *out, hipStream_t s) {
+hipError_t launch_bands(const PlanDev &P, int mode, const double *in, double *out, hipStream_t s, int skip_nk) {
   if (P.max_bands == 0 || P.nr == 0) return hipSuccess;
   const dim3 grid((unsigned)P.max_bands, (unsigned)P.nr), block(LB_THREADS);
   if (mode == kBandCoarsen)
-    hipLaunchKernelGGL(k_band<true>, grid, block, 0, s, P, in, out);
+    hipLaunchKernelGGL(k_band<true>, grid, block, 0, s, P, in, out, 0);
   else
-    hipLaunchKernelGGL(k_band<false>, grid, block, 0, s, P, in, out);
+    hipLaunchKernelGGL(k_band<false>, grid, block, 0, s, P, in, out, skip_nk);
   return hipGetLastError();
 }
 

@@ -24,6 +24,9 @@ constexpr int kLargeChunk = 4096;
 // modes per workgroup of the radial scan (kScanModes x 8 bytes of each row;
 // namp is a multiple of 16)
 constexpr int kScanModes = 16;
+// BF16 x3 separable: one-row blocks of up to this many phi cells are averaged
+// inside the phi transforms (a power of two, at most 8)
+constexpr int kSepFuseNk = 8;
 constexpr int kBandCopyRows = 8;
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.
@@ -147,6 +150,10 @@ struct SepDev {
   // (zero past t = 2L or k = nphi)
   const uint32_t *twf, *ttf;
   int32_t ks_a, mt_a, ks_s, nt_s;
+  // BF16 x3: rows whose blocks are one row of at most fuse_nk (<= 8) cells
+  // are averaged inside the phi transforms (rowalt = 1 + log2 nk there, 1 for
+  // rows read from shat); 0: none
+  int32_t fuse_nk;
 };
 // Per class: blocks on rows with a merged block (source means), and blocks
 // with more than one member (potential means); device lists, without the
@@ -205,7 +212,9 @@ hipError_t launch_large(const PlanDev &P, int mode, const double *in, double *ou
 // kBandMean only does the bands of merged blocks of at most kLargeBlock
 // cells (in == out allowed)
 enum BandMode { kBandCoarsen = 0, kBandMean = 1 };
-hipError_t launch_bands(const PlanDev &P, int mode, const double *in, double *out, hipStream_t s);
+// skip_nk > 0 leaves out the bands of one-row blocks of at most skip_nk
+// cells (the BF16 x3 separable path averages those inside its phi transforms)
+hipError_t launch_bands(const PlanDev &P, int mode, const double *in, double *out, hipStream_t s, int skip_nk = 0);
 
 // separable FP64 path (single plan)
 hipError_t launch_sep_tables(const PlanDev &P, const SepDev &S, hipStream_t s);

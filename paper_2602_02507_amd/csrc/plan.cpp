@@ -385,6 +385,16 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       p->max_src = std::max(p->max_src, (int)C.sep_src.size());
       p->max_avg = std::max(p->max_avg, (int)C.sep_avg.size());
     }
+    // BF16 x3: rows of one-row blocks of 2, 4 or 8 cells (bands with nj = 1)
+    // are averaged inside the phi transforms, code 1 + log2 nk
+    for (int c = 0; c < p->ncls && p->sep_bf16; ++c) {
+      const ClassHost &C = p->cls[c];
+      for (size_t q = 0; q + 3 < C.bands.size(); q += 4) {
+        const int j0 = C.bands[q], nj = C.bands[q + 1], nk = C.bands[q + 2], kind = C.bands[q + 3];
+        if (kind == 1 && nj == 1 && nk >= 2 && nk <= kSepFuseNk)
+          merged[c][j0] = (uint8_t)(nk == 2 ? 2 : nk == 4 ? 3 : 4);
+      }
+    }
     for (int i = 0; i < p->nr; ++i)
       for (int j = 0; j < p->nt; ++j) {
         p->rowalt[(size_t)i * p->nt + j] = merged[p->shell_class[i]][j];
@@ -748,6 +758,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     S.mt_a = p->mt_a;
     S.ks_s = p->ks_s;
     S.nt_s = p->nt_s;
+    S.fuse_nk = p->sep_bf16 ? kSepFuseNk : 0;
     p->scls.assign(p->ncls, SepClass{});
     for (int c = 0; c < p->ncls; ++c) {
       const ClassHost &H = p->cls[c];

@@ -173,8 +173,11 @@ __global__ __launch_bounds__(256) void k_sep_phi_anal_bf16(PlanDev P, SepDev S, 
   const bool jin = j < P.ntheta;
   const int jr = jin ? j : (tile_in ? j0 : 0);
   const long o = (long)i * P.ncell + (long)jr * P.nphi;
-  const bool alt = S.rowalt != nullptr && S.rowalt[(long)i * P.ntheta + jr];
-  const double *row = (alt ? S.shat : rho) + o + 8 * quad;   // this lane's cells of step 0
+  // row code: 0 the density, 1 the block means (shat), 2 + log2(nk / 2)
+  // one-row blocks of nk cells, averaged here in registers
+  const int code = S.rowalt != nullptr ? S.rowalt[(long)i * P.ntheta + jr] : 0;
+  const int fnk = code >= 2 ? 1 << (code - 1) : 1;
+  const double *row = (code == 1 ? S.shat : rho) + o + 8 * quad;   // this lane's cells of step 0
   const double *dphi = S.tw + 8 * quad;                      // TW row 0: dphi_k
   const int np = P.nphi, nks = S.ks_a;
   const bool vec = rho16 && (np & 1) == 0;   // rows start 16-byte aligned
@@ -232,6 +235,32 @@ __global__ __launch_bounds__(256) void k_sep_phi_anal_bf16(PlanDev P, SepDev S, 
       if (tile_in) load(vn, dn, ks + 1);
     }
     if (tile_in) {
+      if (fnk > 1) {   // dphi-weighted means of the lane's aligned groups of fnk cells
+        double g[8], dw[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          g[e] = d[e] * v[e];
+          dw[e] = d[e];
+        }
+        // butterfly within the groups: every cell ends with its group's sums
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1)
+          if (m < fnk) {
+            double tg[8], tw[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              tg[e] = g[e] + g[e ^ m];
+              tw[e] = dw[e] + dw[e ^ m];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              g[e] = tg[e];
+              dw[e] = tw[e];
+            }
+          }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = dw[e] > 0.0 ? g[e] / dw[e] : 0.0;
+      }
 #pragma unroll
       for (int e = 0; e < 8; ++e) rs += d[e] * v[e];
       if constexpr (MT > 0) {
@@ -317,14 +346,47 @@ __global__ __launch_bounds__(256) void k_sep_phi_syn_bf16(PlanDev P, SepDev S, d
 #pragma unroll
       for (int q = 0; q < 3; ++q) b[ks][q] = frag(S.ttf, ((long)ks * S.nt_s + nt) * 3 + q, lane);
   };
+  // rows of one-row blocks of fnk cells (row code 2 + log2(fnk / 2)) get the
+  // dphi-weighted block means here, over the fnk adjacent lanes that hold
+  // the block's cells; the shuffles run on every lane
+  int fnk[4];
+  bool any_fused = false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int jj = min(j0 + 4 * quad + r, P.ntheta - 1);
+    const int code = S.rowalt != nullptr ? S.rowalt[(long)i * P.ntheta + jj] : 0;
+    fnk[r] = code >= 2 ? 1 << (code - 1) : 1;
+    any_fused = any_fused || fnk[r] > 1;
+  }
+  any_fused = __any(any_fused);   // wavefront-uniform
   auto store = [&](f4 acc, int nt) __attribute__((always_inline)) {
     const int k = 16 * nt + (lane & 15);
-    if (k < P.nphi) {
-      const double c0 = tt0[k];
+    const bool kin = k < P.nphi;
+    const double c0 = kin ? tt0[k] : 0.0;
+    double y[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[r] = g0[r] * c0 + (double)acc[r];
+    if (any_fused) {
+      const double w = kin ? *gmem(S.tw + k) : 0.0;   // TW row 0: dphi_k
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double num = w * y[r], den = w;
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+          const double pn = __shfl_xor(num, m, 64), pd = __shfl_xor(den, m, 64);
+          if (m < fnk[r]) {
+            num += pn;
+            den += pd;
+          }
+        }
+        if (fnk[r] > 1) y[r] = den > 0.0 ? num / den : 0.0;
+      }
+    }
+    if (kin) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jj = j0 + 4 * quad + r;
-        if (jj < P.ntheta) out[(long)jj * P.nphi + k] = g0[r] * c0 + (double)acc[r];
+        if (jj < P.ntheta) out[(long)jj * P.nphi + k] = y[r];
       }
     }
   };

@@ -394,7 +394,7 @@ hipError_t launch_sep_source(const PlanDev &P, const SepDev &S, const double *rh
     hipLaunchKernelGGL(k_sep_source, dim3(tiles(S.max_src, 256), P.nr), dim3(256), 0, s, P, S, rho);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = launch_bands(P, kBandMean, rho, S.shat, s);
+  if (e == hipSuccess) e = launch_bands(P, kBandMean, rho, S.shat, s, S.fuse_nk);
   if (e == hipSuccess) e = launch_large(P, kLargeMean, rho, S.shat, s);
   return e;
 }
@@ -430,7 +430,7 @@ hipError_t launch_sep_block_means(const PlanDev &P, const SepDev &S, double *phi
     hipLaunchKernelGGL(k_sep_block_mean, dim3(tiles(S.max_avg, 256), P.nr), dim3(256), 0, s, P, S, phi);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = launch_bands(P, kBandMean, phi, phi, s);
+  if (e == hipSuccess) e = launch_bands(P, kBandMean, phi, phi, s, S.fuse_nk);
   if (e == hipSuccess) e = launch_large(P, kLargeMean, phi, phi, s);
   return e;
 }
