@@ -39,6 +39,7 @@ __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
   double s = 0.0;
   if (P.nplanes == 0) {
     const auto src = gmem(C.partial) + off;   // FP64 partials
+#pragma unroll 8
     for (int q = 0; q < C.splits; ++q) s += src[q * stride];
   } else if (n == 0) {
     // split precisions: the monopole moment, summed in FP64 by the packing
@@ -47,6 +48,7 @@ __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
     for (int q = 0; q < nparts; ++q) s += gmem(P.mono_part)[(size_t)i * P.mono_stride + q];
   } else {
     const auto src = gmem(reinterpret_cast<const float *>(C.partial)) + off;   // FP32 partials
+#pragma unroll 8
     for (int q = 0; q < C.splits; ++q) s += (double)src[q * stride];
     // the mean source density removed by the packing, times the column sum
     s += gmem(P.shift)[i] * gmem(C.tsum)[n];
