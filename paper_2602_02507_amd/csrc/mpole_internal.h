@@ -21,9 +21,10 @@ constexpr int kLargeBlock = 64;
 // chunks whose partial sums are combined in chunk order).
 constexpr int kLargeChunk = 4096;
 // Rows of single cells copied per workgroup by the band kernel.
-// modes per workgroup of the radial scan (kScanModes x 8 bytes of each row;
-// namp is a multiple of 16)
-constexpr int kScanModes = 16;
+// modes per workgroup of the radial scan (x 8 bytes of each row; namp is a
+// multiple of 16): 16 when that still gives a workgroup per CU, else 8 (twice
+// the workgroups, shorter row segments); every field of a batch takes 8
+constexpr int kScanModesWide = 16, kScanModesNarrow = 8, kScanWideMinWgs = 256;
 // BF16 x3 separable: one-row blocks of up to this many phi cells are averaged
 // inside the phi transforms (a power of two, at most 8)
 constexpr int kSepFuseNk = 8;
@@ -189,7 +190,7 @@ hipError_t launch_pack(const BatchDev &B, int precision, int wgs, hipStream_t s)
 hipError_t launch_split_rows(const BatchDev &B, int wgs, hipStream_t s);   // FP16 x2 only
 hipError_t launch_moment(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_reduce(const BatchDev &B, int wgs, hipStream_t s);
-hipError_t launch_scan(const BatchDev &B, int wgs, hipStream_t s);
+hipError_t launch_scan(const BatchDev &B, int wgs, int modes, hipStream_t s);
 hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,

@@ -127,6 +127,7 @@ struct mpole_plan_t {
   size_t off_litems = 0, off_lbase = 0, off_lsum = 0, off_lchunks = 0, off_lpart = 0;
   size_t off_shift = 0, off_tsum_part = 0;
   int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
+  int scan_modes = kScanModesWide;   // modes per radial-scan workgroup
   size_t off_plandev = 0, off_prefix = 0;
   int wg_mom = 0, wg_exp = 0;
   GaussRule rule{};
@@ -217,6 +218,7 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->nam = (m->lmax + 1) * (m->lmax + 1);
   p->kpad = kPadF64;
   p->namp = round_up(p->nam, p->kpad);
+  p->scan_modes = p->namp / kScanModesWide >= kScanWideMinWgs ? kScanModesWide : kScanModesNarrow;
   p->ncell = (int)ncell;
   p->precision = m->precision;
   p->nplanes = n_planes(m->precision);
@@ -610,7 +612,7 @@ int phase_wgs_host(const mpole_plan_t *p, int h) {
     case PH_SPLITROWS: return p->precision == MPOLE_FP16X2 ? p->nr : 0;
     case PH_MOMENT: return p->wg_mom;
     case PH_REDUCE: return (p->namp + 255) / 256 * p->nr;
-    case PH_SCAN: return p->namp / kScanModes;
+    case PH_SCAN: return p->namp / p->scan_modes;
     case PH_COEF: return p->nplanes ? p->nr : 0;
     case PH_EXPAND: return p->wg_exp;
   }
@@ -799,7 +801,8 @@ struct LargeJob {
 // `precision`; wgs[h] = total workgroups of phase h; phi == false skips the
 // potential (moments only).
 template <class Timer>
-hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, bool phi, const std::vector<LargeJob> &large,
+hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, int scan_modes, bool phi,
+                     const std::vector<LargeJob> &large,
                      hipStream_t s, Timer &&timed) {
   const int k = precision;
   hipError_t e = launch_stamp_reset(B, s);
@@ -813,7 +816,7 @@ hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, bool phi,
   });
   if (e == hipSuccess) e = timed(MPOLE_PHASE_MOMENT, [&] { return launch_moment(B, k, wgs[PH_MOMENT], s); });
   if (e == hipSuccess) e = timed(MPOLE_PHASE_REDUCE, [&] { return launch_reduce(B, wgs[PH_REDUCE], s); });
-  if (e == hipSuccess) e = timed(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], s); });
+  if (e == hipSuccess) e = timed(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], scan_modes, s); });
   if (e == hipSuccess && phi && k != 0)
     e = timed(MPOLE_PHASE_SPLIT, [&] { return launch_split_coef(B, k, wgs[PH_COEF], s); });
   if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] {
@@ -917,7 +920,7 @@ hipError_t run_sep(mpole_plan_t *p, const double *rho, double *phi, double *ang,
     return p->sep_bf16 ? launch_sep_phi_anal_bf16(D, S, rho, s) : launch_sep_phi_anal(D, S, rho, s);
   });
   if (e == hipSuccess) e = T(MPOLE_PHASE_REDUCE, [&] { return launch_sep_theta_anal(D, S, ang, s); });
-  if (e == hipSuccess) e = T(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, p->prefix[2 * PH_SCAN + 1], s); });
+  if (e == hipSuccess) e = T(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, p->prefix[2 * PH_SCAN + 1], p->scan_modes, s); });
   if (e == hipSuccess && phi) e = T(MPOLE_PHASE_SPLIT, [&] { return launch_sep_theta_syn(D, S, s); });
   if (e == hipSuccess && phi) e = T(MPOLE_PHASE_EXPAND, [&] {
     return p->sep_bf16 ? launch_sep_phi_syn_bf16(D, S, phi, s) : launch_sep_phi_syn(D, S, phi, s);
@@ -951,7 +954,7 @@ int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, doubl
   } else {
     std::vector<LargeJob> large;
     if (p->dev.n_litems > 0) large.push_back(LargeJob{&p->dev, rho, phi});
-    e = run_solve(B, p->precision, wgs, phi != nullptr, large, s,
+    e = run_solve(B, p->precision, wgs, p->scan_modes, phi != nullptr, large, s,
                   [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
   }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
@@ -1100,6 +1103,7 @@ int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *o
         std::string msg = g_error;
         return fail(rc, "field %d: %s", f, msg.c_str());
       }
+      p->scan_modes = kScanModesNarrow;
       b->plans.push_back(p);
     }
     b->precision = meshes[0].precision;
@@ -1208,7 +1212,7 @@ int mpole_batch_solve(mpole_batch b, void *stream) {
     std::vector<LargeJob> large;
     for (int f = 0; f < nf; ++f)
       if (b->plans[f]->dev.n_litems > 0) large.push_back(LargeJob{&b->plans[f]->dev, b->io[f].rho, b->io[f].phi});
-    e = run_solve(B, b->precision, wgs, true, large, (hipStream_t)stream, [](int, auto &&launch) { return launch(); });
+    e = run_solve(B, b->precision, wgs, kScanModesNarrow, true, large, (hipStream_t)stream, [](int, auto &&launch) { return launch(); });
   }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch solve: %s", hipGetErrorString(e));
   return ok();

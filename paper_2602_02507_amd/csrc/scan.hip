@@ -12,8 +12,8 @@
 //             Solution C[i][n] = -Delta_m/(2l+1) (<r^l> M^I_c + <r^-(l+1)> M^R_c)
 //
 // The scan is a segmented prefix/suffix sum over radius, one segment per mode.
-// A workgroup owns kScanModes (16) consecutive modes (coalesced 128-byte row
-// segments) and splits radius into 64 chunks: each thread sums one chunk of one mode, then one
+// A workgroup owns 16 or 8 consecutive modes (coalesced 128- or 64-byte row
+// segments; the count is the plan's) and splits radius into 64 chunks: each thread sums one chunk of one mode, then one
 // wavefront per mode scans the 64 chunk totals with lane shuffles (prefix for
 // the outward sums, suffix for the inward ones), and a second pass writes
 // edges and coefficients.  Chunk-boundary edges are always the scanned totals
@@ -57,9 +57,10 @@ __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
   if (ang_out != nullptr && n < P.nam) ang_out[(size_t)i * P.nam + n] = s;
 }
 
-constexpr int SCAN_MODES = kScanModes;   // modes per workgroup
 constexpr int SCAN_CHUNKS = 64;   // radial chunks per mode (one per lane of a wavefront)
+constexpr int SG = 8;             // shells whose operands are loaded together
 
+template <int SCAN_MODES>
 __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
   __shared__ double tot_r[SCAN_CHUNKS][SCAN_MODES], tot_i[SCAN_CHUNKS][SCAN_MODES];
   __shared__ double base_r[SCAN_CHUNKS + 1][SCAN_MODES], base_i[SCAN_CHUNKS + 1][SCAN_MODES];
@@ -126,12 +127,26 @@ __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
     for (int i = i0; i < i1; ++i) coef[(size_t)i * namp + n] = 0.0;
     return;
   }
-  // pass 2a: outward edges i0 .. i1-1; chunk boundaries come from base_r only
+  // pass 2a: outward edges i0 .. i1-1; chunk boundaries come from base_r only.
+  // Both passes load SG shells' operands before the group's stores, so the
+  // loads of a group are in flight together (the stores could alias them,
+  // which would otherwise order every load behind the previous shell's
+  // store); the arithmetic order is the plain sequential one.
   double mr = base_r[c][mode];
-#pragma unroll 8
-  for (int i = i0; i < i1; ++i) {
-    er[(size_t)i * ld_r + n] = mr;
-    mr += jr[i * L1 + l] * A[(size_t)i * namp + n];
+  for (int g0 = i0; g0 < i1; g0 += SG) {
+    double av[SG], jv[SG];
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+      const int i = min(g0 + u, i1 - 1);
+      av[u] = A[(size_t)i * namp + n];
+      jv[u] = jr[i * L1 + l];
+    }
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+      if (g0 + u >= i1) break;
+      er[(size_t)(g0 + u) * ld_r + n] = mr;
+      mr += jv[u] * av[u];
+    }
   }
   const double mr_end = base_r[c + 1][mode];
   const double mi_end = base_i[c + 1][mode];
@@ -143,14 +158,29 @@ __global__ __launch_bounds__(SCAN_MODES * SCAN_CHUNKS) void k_scan(BatchDev B) {
   const double dm = (n == l * l) ? 1.0 : 2.0;
   const double f = -dm / (2.0 * l + 1.0);
   double mi = mi_end, mr_hi = mr_end;
-  for (int i = i1 - 1; i >= i0; --i) {
-    const double mi_hi = mi;
-    mi = (i == i0) ? base_i[c][mode] : mi + ji[i * L1 + l] * A[(size_t)i * namp + n];
-    ei[(size_t)i * ld_i + n] = mi;
-    const double mr_lo = er[(size_t)i * ld_r + n];
-    const double mic = 0.5 * (mi + mi_hi), mrc = 0.5 * (mr_lo + mr_hi);
-    coef[(size_t)i * namp + n] = f * (rr[i * L1 + l] * mic + ri[i * L1 + l] * mrc);
-    mr_hi = mr_lo;
+  for (int g1 = i1 - 1; g1 >= i0; g1 -= SG) {
+    double av[SG], jv[SG], ev[SG], rv[SG], qv[SG];
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+      const int i = max(g1 - u, i0);
+      av[u] = A[(size_t)i * namp + n];
+      jv[u] = ji[i * L1 + l];
+      ev[u] = er[(size_t)i * ld_r + n];   // written by this thread in pass 2a
+      rv[u] = rr[i * L1 + l];
+      qv[u] = ri[i * L1 + l];
+    }
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+      const int i = g1 - u;
+      if (i < i0) break;
+      const double mi_hi = mi;
+      mi = (i == i0) ? base_i[c][mode] : mi + jv[u] * av[u];
+      ei[(size_t)i * ld_i + n] = mi;
+      const double mr_lo = ev[u];
+      const double mic = 0.5 * (mi + mi_hi), mrc = 0.5 * (mr_lo + mr_hi);
+      coef[(size_t)i * namp + n] = f * (rv[u] * mic + qv[u] * mrc);
+      mr_hi = mr_lo;
+    }
   }
 }
 
@@ -162,9 +192,12 @@ hipError_t launch_reduce(const BatchDev &B, int wgs, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const BatchDev &B, int wgs, hipStream_t s) {
+hipError_t launch_scan(const BatchDev &B, int wgs, int modes, hipStream_t s) {
   if (wgs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan, dim3(wgs), dim3(SCAN_MODES * SCAN_CHUNKS), 0, s, B);
+  if (modes == kScanModesWide)
+    hipLaunchKernelGGL(k_scan<kScanModesWide>, dim3(wgs), dim3(kScanModesWide * SCAN_CHUNKS), 0, s, B);
+  else
+    hipLaunchKernelGGL(k_scan<kScanModesNarrow>, dim3(wgs), dim3(kScanModesNarrow * SCAN_CHUNKS), 0, s, B);
   return hipGetLastError();
 }
 
