@@ -134,6 +134,47 @@ def roofline_hbm(plan, phases, workload):
             "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
 
 
+def solve_bound(plan, precision, ms):
+    """Whole-solve roofline: the sum over the solve's phases of max(executed
+    flops / the peak of their arithmetic, algorithmic bytes / the HBM peak),
+    set against the measured time per solve.  Bytes: the density read and the
+    potential written once (8 B per cell each), each narrow or FP64 operand
+    written and read once, the kernel table read once per contraction, the
+    moments, edge sums and coefficients once each; flops: 2 per multiply-add,
+    times the narrow products per multiply-add."""
+    hbm = 8e12
+    f64 = PEAK["f64"][0]
+    nr, nt, nph = plan.nr, plan.shape[1], plan.shape[2]
+    cells = float(nr) * nt * nph
+    nam = (plan.lmax + 1) ** 2
+    mflops, eflops, min_bytes = plan.work()
+    scan_bytes = 8.0 * nam * (nr + 3 * (nr + 1))
+    t = {}
+    if precision in ("fp64sep", "bf16x3sep"):
+        inter = 8.0 * (2 * plan.lmax + 1) * nr * nt   # F or G, [shell][trig mode][theta]
+        peak = PEAK[DTYPE[precision]][0]
+        prod = 6 if precision == "bf16x3sep" else 1
+        theta_flops = 2.0 * nr * nt * nam
+        t["phi_analysis"] = max(mflops * prod / peak, (8.0 * cells + inter) / hbm)
+        t["theta_analysis"] = max(theta_flops / f64, (inter + 8.0 * nr * nam) / hbm)
+        t["scan"] = scan_bytes / hbm
+        t["theta_synthesis"] = max(theta_flops / f64, (8.0 * nr * nam + inter) / hbm)
+        t["phi_synthesis"] = max(eflops * prod / peak, (inter + 8.0 * cells) / hbm)
+    else:
+        peak = PEAK[DTYPE[precision]][0]
+        prod = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
+        opb = {"fp64": 8.0, "bf16x3": 6.0, "fp16x2": 4.0}[precision]   # bytes per operand element
+        blocks = mflops / (2.0 * nam)                  # (shell, merged block) pairs
+        table = (min_bytes - 16.0 * cells) * opb / 8.0
+        t["pack"] = (8.0 * cells + opb * blocks) / hbm
+        t["moment"] = max(mflops * prod / peak, (opb * blocks + table) / hbm)
+        t["scan"] = scan_bytes / hbm
+        t["expand"] = max(eflops * prod / peak, (table + 8.0 * cells) / hbm)
+    bound = sum(t.values()) * 1e3
+    return {"bound_ms": bound, "measured_ms": ms, "frac": bound / ms,
+            "phase_bound_ms": {k: v * 1e3 for k, v in t.items()}}
+
+
 def roofline(plan, phases, precision, workload):
     """Roofline position of the dominant contraction from the plan's per-phase
     HIP event timings: algorithmic flops of one launch / its mean duration
@@ -218,8 +259,10 @@ def main():
             p2.solve_into(rho, **o2)
         b.record(stream)
         torch.cuda.synchronize()
+        ms2 = a.elapsed_time(b) / args.steps
+        bound = solve_bound(p2, prec, ms2)
         del p2
-        return {"ms_per_step": a.elapsed_time(b) / args.steps, "phi": o2["phi"]}
+        return {"ms_per_step": ms2, "phi": o2["phi"], "solve_roofline_frac": bound["frac"]}
 
     fp64 = None
     if precision != "fp64" and not args.no_fp64:
@@ -233,7 +276,7 @@ def main():
             r = time_path(prec)
             err = float((r["phi"] - fp64["phi"]).abs().div(fp64["phi"].abs()).max())
             others[prec] = {"ms_per_step": r["ms_per_step"], "speedup_vs_fp64": fp64["ms_per_step"] / r["ms_per_step"],
-                            "max_rel_err_vs_fp64_gpu": err}
+                            "max_rel_err_vs_fp64_gpu": err, "solve_roofline_frac": r["solve_roofline_frac"]}
             print("bench: %s path %.4f ms/solve, max rel err vs FP64 %.2e" % (prec, r["ms_per_step"], err),
                   file=sys.stderr, flush=True)
 
@@ -269,6 +312,7 @@ def main():
     cell_modes = float(mesh.ncells) * mesh.nmodes
     value = cell_modes / (ms * 1e-3)
     roof = roofline(plan, phases, precision, args.workload)
+    roof["solve"] = solve_bound(plan, precision, ms)
     dtype = DTYPE[precision]
 
     # the gradient of the potential for the gravitational sources (after the
@@ -453,6 +497,7 @@ def bench_large(args, precision):
     mflops, eflops, min_bytes = plan.work()
     products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1, "bf16x3sep": 6}[precision]
     roof = roofline(plan, phases, precision, args.workload)
+    roof["solve"] = solve_bound(plan, precision, solve_ms)
     result = {"metric": METRIC, "value": cell_modes / (solve_ms * 1e-3), "unit": UNIT, "n_gpus": 1,
               "steps": steps, "warmup": args.warmup, "ms_per_step": graph_ms / steps, "higher_is_better": True,
               "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[precision], "data": "synthetic",
