@@ -379,6 +379,7 @@ def main():
 
     if not (args.no_cpu_baseline and args.no_check):
         import oracle
+        oracle.set_threads(host_threads())
         t0 = time.perf_counter()
         ref = oracle.solve(rho=rho_h, **mesh.oracle_kwargs())
         tot = time.perf_counter() - t0
@@ -392,15 +393,60 @@ def main():
                 t_sum += oracle.solve(rho=rho_h, **mesh.oracle_kwargs())["seconds"][1]
                 reps += 1
             result["cpu_baseline"] = {"value": reps * cell_modes / t_sum, "unit": UNIT, "cores": oracle.threads(),
-                                      "kind": "oracle",
+                                      "kind": "oracle", "cpu_model": cpu_model(),
                                       "sample": "%d full solves of the same workload, %.2f s of solve time (tables "
                                                 "excluded: %.2f s per call; first call %.2f s in all)"
-                                                % (reps, t_sum, t_tables, tot)}
+                                                % (reps, t_sum, t_tables, tot),
+                                      "single_thread": single_thread_rate(mesh, rho_h)}
         if not args.no_check:
             torch.cuda.synchronize()
             phi = out["phi"].cpu().numpy()
             result["max_rel_err_vs_oracle"] = float(np.max(np.abs(phi - ref["phi"]) / np.abs(ref["phi"])))
     print(json.dumps(result), flush=True)
+
+
+def cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_threads():
+    """Threads for the multi-threaded oracle leg: the CPUs this process may
+    run on (the machine's CPU share, not the machine's core count)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def single_thread_rate(mesh, rho_h, shells=64):
+    """The oracle on one thread, on a bounded sample of the workload: one solve
+    of its outermost `shells` shells (same angular mesh, lmax and coarsening
+    class as there; the outer shells carry the most blocks per shell, so the
+    rate is, if anything, below the full mesh's).  Thread count restored
+    afterwards."""
+    import oracle
+    nr = mesh.nr
+    s0 = max(0, nr - shells)
+    sc = None if mesh.shell_class is None else np.ascontiguousarray(mesh.shell_class[s0:])
+    from paper_2602_02507_amd import workloads as wl
+    sub = wl.Mesh(mesh.r_edges[s0:], mesh.theta_edges, mesh.phi_edges, mesh.lmax, sc, mesh.class_block, mesh.G)
+    prev = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        ref = oracle.solve(rho=np.ascontiguousarray(rho_h[s0:]), **sub.oracle_kwargs())
+    finally:
+        oracle.set_threads(prev)
+    t = ref["seconds"][1]
+    return {"value": float(sub.ncells) * sub.nmodes / t, "unit": UNIT, "cores": 1,
+            "sample": "one solve of the outermost %d of %d shells on one thread, %.2f s (tables excluded)"
+                      % (nr - s0, nr, t)}
 
 
 def _tuning_summary(tunings):
@@ -525,6 +571,7 @@ def bench_large(args, precision):
         del p64
     if not args.no_cpu_baseline:
         import oracle
+        oracle.set_threads(host_threads())
         # bounded sample: the oracle on the 40 innermost shells of the same
         # angular mesh and lmax (merged like the full mesh), one solve
         sub = wl.large_mesh(nr=40)
@@ -533,7 +580,7 @@ def bench_large(args, precision):
                                      * wl.rotated_angular_factor(sub, np.eye(3), coef)[None])
         ref = oracle.solve(rho=rho_s, **sub.oracle_kwargs())
         result["cpu_baseline"] = {"value": float(sub.ncells) * sub.nmodes / ref["seconds"][1], "unit": UNIT,
-                                  "cores": oracle.threads(), "kind": "oracle",
+                                  "cores": oracle.threads(), "kind": "oracle", "cpu_model": cpu_model(),
                                   "sample": "one oracle solve of the 40 innermost shells of the same angular mesh and "
                                             "lmax (tables %.1f s excluded; solve %.1f s)" % tuple(ref["seconds"])}
     print(json.dumps(result), flush=True)
@@ -608,6 +655,7 @@ def bench_batch(args, precision):
                                                 for p, q in zip(batch.phi, phi64))
     if not (args.no_cpu_baseline and args.no_check):
         import oracle
+        oracle.set_threads(host_threads())
         # bounded sample: the oracle on the four smallest fields
         order = np.argsort([m.ncells * m.nmodes for m in meshes])[:4]
         t_solve, cm, err = 0.0, 0.0, 0.0
@@ -619,6 +667,7 @@ def bench_batch(args, precision):
             err = max(err, float(np.max(np.abs(got - ref["phi"]) / np.abs(ref["phi"]))))
         if not args.no_cpu_baseline:
             result["cpu_baseline"] = {"value": cm / t_solve, "unit": UNIT, "cores": oracle.threads(), "kind": "oracle",
+                                      "cpu_model": cpu_model(),
                                       "sample": "oracle solves of the 4 smallest fields (%.2e cell-modes, %.2f s)"
                                                 % (cm, t_solve)}
         if not args.no_check:

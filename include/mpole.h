@@ -39,10 +39,16 @@
  * pointers into the bound workspace; one plan serves one stream at a time
  * (solves that overlap on one workspace race).
  *
- * Errors.  Every call returns an mpole_status.  On an error nothing has been
- * enqueued and mpole_last_error() (per thread) describes it.  Faults inside
- * already-enqueued kernels surface at the caller's next stream
- * synchronisation.  No call aborts or throws.
+ * Errors.  Every call returns an mpole_status, and mpole_last_error() (per
+ * thread) describes a failure.  Every argument, size and state check of a
+ * call runs before its first enqueue, so MPOLE_ERR_INVALID, _RANGE,
+ * _WORKSPACE and _UNSUPPORTED mean that nothing was enqueued.
+ * MPOLE_ERR_DEVICE means that a HIP call or kernel launch failed while the
+ * call was enqueueing its work: the launches before it may already be on
+ * the stream (a partial solve or table build), so the outputs, and after a
+ * failed bind the tables, are undefined until a later call succeeds.
+ * Faults inside already-enqueued kernels surface at the caller's next
+ * stream synchronisation.  No call aborts or throws.
  */
 #ifndef MPOLE_H
 #define MPOLE_H
@@ -134,9 +140,9 @@ int mpole_plan_nmodes(mpole_plan plan);
  * on hip_stream (a hipStream_t; NULL = default stream): Legendre cell
  * averages by composite Gauss-Legendre quadrature in FP64, phi-cell
  * averages, merged-block kernel tables, radial kernel integrals and, for
- * the split precisions, their split planes (Sec. 2.2: kernels "computed once
- * and for all at the beginning").  The workspace must stay allocated while
- * the plan is used.  Rebinding is allowed.
+ * the split precisions, their split planes (Sec. 2.2: the angular and radial
+ * kernels are averaged once, before any solve).  The workspace must stay
+ * allocated while the plan is used.  Rebinding is allowed.
  */
 int mpole_plan_bind(mpole_plan plan, void *dev_workspace, size_t bytes, void *hip_stream);
 
@@ -359,6 +365,8 @@ typedef struct mpole_batch_t *mpole_batch;
 int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *out);
 int mpole_batch_tune(mpole_batch batch, const mpole_tuning *tunings);
 int mpole_batch_configure(mpole_batch batch, const int32_t *moment_wgs);
+/* Per-field launch tuning in use ([nfields]; moment_wgs = each field's target). */
+int mpole_batch_get_tuning(mpole_batch batch, mpole_tuning *tunings);
 size_t mpole_batch_workspace_bytes(mpole_batch batch);
 int mpole_batch_bind(mpole_batch batch, void *dev_workspace, size_t bytes, const double *const *rho,
                      double *const *phi, void *hip_stream);

@@ -37,6 +37,8 @@ def lib():
                                    dp, dp, dp, dp, dp, dp, dp]
         L.oracle_solve.restype = c_int
         L.oracle_gradient.argtypes = [c_int, c_int, c_int, dp, dp, dp, dp, dp, dp, dp]
+        L.oracle_set_threads.argtypes = [c_int]
+        L.oracle_set_threads.restype = c_int
         _lib = L
     return _lib
 
@@ -169,7 +171,10 @@ def gravity_sources(r_edges, theta_edges, phi_edges, phi, rho, v_r=None, v_theta
 
 
 def threads():
-    """OpenMP threads the oracle uses."""
-    import os
-    n = os.environ.get("OMP_NUM_THREADS")
-    return int(n) if n else os.cpu_count()
+    """OpenMP threads the oracle's parallel regions use."""
+    return lib().oracle_set_threads(0)
+
+
+def set_threads(n):
+    """Set the oracle's OpenMP thread count (n >= 1); returns the count in effect."""
+    return lib().oracle_set_threads(int(n))

@@ -490,3 +490,10 @@ void oracle_gradient(int nr, int ntheta, int nphi, const double *r, const double
     }
   }
 }
+
+/* Threads of the OpenMP regions above (n >= 1); returns the count in effect.
+   Used by the benchmark's CPU baseline to time the oracle single-threaded. */
+int oracle_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}

@@ -180,8 +180,8 @@ __global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
 
 }  // namespace
 
-__global__ void k_stamp_reset(unsigned long long *stamps, int nf) {
-  const int t = threadIdx.x;
+__global__ __launch_bounds__(256) void k_stamp_reset(unsigned long long *stamps, int nf) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
   if (t < nf) stamps[t] = 0ull;
   if (t == nf) stamps[nf] = ~0ull;
 }
@@ -198,7 +198,7 @@ hipError_t launch_stamp(unsigned long long *stamps, int idx, hipStream_t s) {
 
 hipError_t launch_stamp_reset(const BatchDev &B, hipStream_t s) {
   if (B.stamps == nullptr) return hipSuccess;
-  hipLaunchKernelGGL(k_stamp_reset, dim3(1), dim3(((B.nf + 1 + 63) / 64) * 64), 0, s, B.stamps, B.nf);
+  hipLaunchKernelGGL(k_stamp_reset, dim3((B.nf + 1 + 255) / 256), dim3(256), 0, s, B.stamps, B.nf);
   return hipGetLastError();
 }
 

@@ -1140,6 +1140,16 @@ int mpole_batch_tune(mpole_batch b, const mpole_tuning *tunings) {
   return ok();
 }
 
+int mpole_batch_get_tuning(mpole_batch b, mpole_tuning *tunings) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (!tunings) return fail(MPOLE_ERR_INVALID, "tunings is null");
+  for (size_t f = 0; f < b->plans.size(); ++f) {
+    const int rc = mpole_plan_get_tuning(b->plans[f], &tunings[f]);
+    if (rc) return rc;
+  }
+  return ok();
+}
+
 size_t mpole_batch_workspace_bytes(mpole_batch b) { return b ? b->ws_bytes : 0; }
 
 int mpole_batch_bind(mpole_batch b, void *dev_ws, size_t bytes, const double *const *rho, double *const *phi,

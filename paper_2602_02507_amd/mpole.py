@@ -26,7 +26,8 @@ EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_
            "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_gradient", "mpole_gravity_sources", "mpole_coarsen",
            "mpole_genasis_shape", "mpole_genasis_build", "mpole_plan_tune",
            "mpole_plan_get_tuning", "mpole_plan_configure", "mpole_plan_moment_wgs", "mpole_plan_destroy",
-           "mpole_batch_create", "mpole_batch_tune", "mpole_batch_configure", "mpole_batch_workspace_bytes",
+           "mpole_batch_create", "mpole_batch_tune", "mpole_batch_configure", "mpole_batch_get_tuning",
+           "mpole_batch_workspace_bytes",
            "mpole_batch_bind",
            "mpole_batch_solve", "mpole_batch_field_ms", "mpole_batch_destroy")
 PHASES = ("pack", "moment", "reduce", "scan", "split", "expand")
@@ -77,16 +78,19 @@ _lib = None
 
 
 def library_path():
-    return _build.LIB
+    """The library to load: $MPOLE_LIBRARY when set (e.g. a host-sanitized
+    build of the same sources), else the in-tree libmpole.so."""
+    return os.environ.get("MPOLE_LIBRARY") or _build.LIB
 
 
 def lib():
     """Load libmpole.so (building it first only if it is absent)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = library_path()
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.mpole_abi_version.restype = ctypes.c_int
         L.mpole_last_error.restype = ctypes.c_char_p
@@ -115,6 +119,7 @@ def lib():
         L.mpole_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(MeshC), ctypes.POINTER(vp)]
         L.mpole_batch_tune.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_batch_configure.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.mpole_batch_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.mpole_batch_workspace_bytes.argtypes = [vp]
         L.mpole_batch_workspace_bytes.restype = sz
         L.mpole_batch_bind.argtypes = [vp, vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -408,6 +413,12 @@ class Batch:
         import torch
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         _check(lib().mpole_batch_solve(self.handle, ctypes.c_void_p(s)))
+
+    def tunings(self):
+        """Per-field launch tunings in use, as dicts."""
+        arr = (Tuning * self.n)()
+        _check(lib().mpole_batch_get_tuning(self.handle, arr))
+        return [t.as_dict() for t in arr]
 
     def field_ms(self):
         out = (ctypes.c_double * self.n)()

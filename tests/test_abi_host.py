@@ -173,3 +173,64 @@ def test_bf16x3_separable_plan_host_side():
     a0 = mpole.HostPlan.from_mesh(m0, precision="fp64sep")
     b0 = mpole.HostPlan.from_mesh(m0, precision="bf16x3sep")
     assert b0.workspace_bytes == a0.workspace_bytes
+
+
+def test_workspace_errors_before_any_device_work():
+    """Every MPOLE_ERR_WORKSPACE path is decided on the host before a HIP call:
+    a null, misaligned or undersized workspace at bind (plan and batch), and
+    solves, table copies and field times of an unbound plan or batch.  The
+    fake device addresses below are never dereferenced."""
+    import ctypes
+    L = mpole.lib()
+    m = wl.production_mesh(4, nr=8, ntheta=8, nphi=8, merged=False)
+    p = mpole.HostPlan.from_mesh(m)
+    need = p.workspace_bytes
+    fake = ctypes.c_void_p(1 << 20)            # 256-byte aligned, never touched
+    assert L.mpole_plan_bind(p.handle, None, need, None) == 3
+    assert b"null" in L.mpole_last_error()
+    assert L.mpole_plan_bind(p.handle, ctypes.c_void_p((1 << 20) + 8), need, None) == 3
+    assert b"aligned" in L.mpole_last_error()
+    assert L.mpole_plan_bind(p.handle, fake, need - 1, None) == 3
+    assert b"needs" in L.mpole_last_error()
+    assert L.mpole_solve(p.handle, fake, fake, None, None, None, None) == 3
+    assert b"no bound workspace" in L.mpole_last_error()
+    out = np.zeros((64, p.nmodes))
+    n = ctypes.c_int64()
+    assert L.mpole_plan_copy_table(p.handle, 0, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n), None) == 3
+    # batches
+    descs = (mpole.MeshC * 2)()
+    keep = []
+    for f in range(2):
+        d, k = mpole.make_mesh(m.r_edges, m.theta_edges, m.phi_edges, 2 + f)
+        descs[f] = d
+        keep.append(k)
+    h = ctypes.c_void_p()
+    assert L.mpole_batch_create(2, descs, ctypes.byref(h)) == 0
+    bneed = L.mpole_batch_workspace_bytes(h)
+    ptrs = (ctypes.c_void_p * 2)(1 << 20, 1 << 21)
+    assert L.mpole_batch_bind(h, None, bneed, ptrs, ptrs, None) == 3
+    assert L.mpole_batch_bind(h, ctypes.c_void_p((1 << 20) + 64), bneed, ptrs, ptrs, None) == 3
+    assert L.mpole_batch_bind(h, fake, bneed - 256, ptrs, ptrs, None) == 3
+    assert L.mpole_batch_solve(h, None) == 3
+    ms = (ctypes.c_double * 2)()
+    assert L.mpole_batch_field_ms(h, ms) == 3
+    assert L.mpole_batch_destroy(h) == 0
+
+
+def test_batch_field_count_limits():
+    """Batches of 1..4096 fields are accepted (the per-field completion stamps
+    are reset by a grid of 256-thread workgroups, so 1024 fields and more
+    launch too); 0 and 4097 are rejected."""
+    import ctypes
+    L = mpole.lib()
+    m = wl.production_mesh(1, nr=2, ntheta=2, nphi=2, merged=False)
+    d, keep = mpole.make_mesh(m.r_edges, m.theta_edges, m.phi_edges, 1)
+    h = ctypes.c_void_p()
+    descs = (mpole.MeshC * 4097)(*([d] * 4097))
+    assert L.mpole_batch_create(0, descs, ctypes.byref(h)) == 1
+    assert L.mpole_batch_create(4097, descs, ctypes.byref(h)) == 1
+    assert L.mpole_batch_create(4096, descs, ctypes.byref(h)) == 0
+    t = (mpole.Tuning * 4096)()
+    assert L.mpole_batch_get_tuning(h, t) == 0
+    assert all(t[f].moment_wgs >= 1 for f in range(4096))
+    assert L.mpole_batch_destroy(h) == 0

@@ -140,3 +140,61 @@ def test_batch_of_genasis_meshes(precision, tol):
         ref = oracle.solve(rho=rho[f].cpu().numpy(), **m.oracle_kwargs())["phi"]
         rel = np.max(np.abs(batch.phi[f].cpu().numpy() - ref) / np.abs(ref))
         assert rel <= tol, (f, rel)
+
+
+# fields of the 64-field uneven workload (seeds 4000 + f): the smallest, a
+# mid-sized one, the one with the most cells (and theta rows), the one with
+# the most shells and one at the largest lmax
+CONFIG4_FIELDS = (58, 24, 5, 44, 51)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x2"])
+def test_batch_real_uneven_draws_match_oracle(precision):
+    """Five real draws of the 64-field workload (up to 933 x 240 x 480 cells,
+    1020 shells, lmax 32) solved as one batch: every cell of every field
+    within 1e-6 of the oracle, and each field bitwise equal to its
+    single-plan solve under the same launch tuning."""
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    allm = wl.batch_meshes(64)
+    # the workload's densities use seed 4000 + f
+    dens = [wl.production_density(allm[f], seed=4000 + f) for f in CONFIG4_FIELDS]
+    meshes = [allm[f] for f in CONFIG4_FIELDS]
+    rho = [torch.from_numpy(r).cuda() for r in dens]
+    batch = mpole.Batch(meshes, precision=precision, rho=rho)
+    batch.solve()
+    torch.cuda.synchronize()
+    tunings = batch.tunings()
+    for f, m in enumerate(meshes):
+        print("field %d: %d x %d x %d lmax %d" % (CONFIG4_FIELDS[f], m.nr, m.ntheta, m.nphi, m.lmax), flush=True)
+        single = mpole.Plan.from_mesh(m, precision=precision, tuning=tunings[f]).solve(rho[f])["phi"]
+        torch.cuda.synchronize()
+        assert torch.equal(single, batch.phi[f]), f
+        del single
+        ref = oracle.solve(rho=dens[f], **m.oracle_kwargs())["phi"]
+        rel = np.max(np.abs(batch.phi[f].cpu().numpy() - ref) / np.abs(ref))
+        print("  max rel err vs oracle %.3e" % rel, flush=True)
+        assert rel <= 1e-6, (f, rel)
+
+
+def test_batch_of_1100_tiny_fields():
+    """More fields than a workgroup has threads (the completion stamps are
+    reset by a grid of workgroups): 1100 tiny fields in one batch, each
+    bitwise equal to its single-plan solve (sampled) and the completion times
+    all recorded."""
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    n = 1100
+    base = wl.Mesh(wl.log_edges(0.1, 1.0, 4), wl.uniform_edges(0.0, np.pi, 4), wl.uniform_edges(0.0, 2 * np.pi, 8), 2)
+    meshes = [base.with_lmax(1 + f % 3) for f in range(n)]
+    rho = [torch.from_numpy(wl.random_density(f, base.shape) + 0.5).cuda() for f in range(n)]
+    batch = mpole.Batch(meshes, precision="fp64", rho=rho)
+    batch.solve()
+    torch.cuda.synchronize()
+    tun = batch.tunings()
+    for f in (0, 1, 511, 1023, 1024, n - 1):
+        single = mpole.Plan.from_mesh(meshes[f], precision="fp64", tuning=tun[f]).solve(rho[f])["phi"]
+        torch.cuda.synchronize()
+        assert torch.equal(single, batch.phi[f]), f
+    ms = batch.field_ms()
+    assert len(ms) == n and all(x > 0 for x in ms), min(ms)

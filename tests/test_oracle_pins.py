@@ -94,6 +94,35 @@ def test_theta_average_matches_mpmath_quadrature(cell):
             assert abs(v[oracle.plm_index(l, m)] - ref) <= 1e-14 * bound(l), (l, m)
 
 
+@pytest.mark.parametrize("row", [0, 1, 127, 128, 254, 255])
+def test_theta_average_l64_matches_mpmath_on_256_row_mesh(row):
+    """lmax 64 (the repeated-solve workload): the two cells at each pole, the
+    two equatorial cells of a 256-row uniform theta mesh and their
+    neighbours, against 30-digit mpmath quadrature of P~ sin(theta), and
+    Romberg converged below its level cap.  The bar is 3e-16 x max(l, 24) x
+    the bound of P~: the FP64 rounding of the degree-l three-term recurrence
+    grows about linearly with l (the degree-24 pin above uses 1e-14 x the
+    bound); a truncated or unconverged quadrature misses it by orders of
+    magnitude."""
+    L = 64
+    t0, t1 = np.pi * row / 256, np.pi * (row + 1) / 256
+    v, k = oracle.theta_average(L, t0, t1)
+    assert k < 20, k
+    with mp.workdps(30):
+        w = 2 * mp.sin((t0 + t1) / 2) * mp.sin((t1 - t0) / 2)
+        for l, m in [(1, 1), (33, 0), (40, 17), (57, 56), (63, 2), (64, 0), (64, 1), (64, 32), (64, 64)]:
+            f = lambda t: mp.re(mp.spherharm(l, m, t, 0)) * mp.sin(t)
+            ref = float(mp.quad(f, mp.linspace(t0, t1, 5)) / w)
+            assert abs(v[oracle.plm_index(l, m)] - ref) <= 3e-16 * max(l, 24) * bound(l), (row, l, m)
+
+
+def test_theta_average_l64_converges_on_every_row():
+    """No theta cell of the 256-row mesh reaches the Romberg level cap at lmax 64."""
+    e = np.linspace(0.0, np.pi, 257)
+    ks = [oracle.theta_average(64, e[j], e[j + 1])[1] for j in range(256)]
+    assert max(ks) < 20, max(ks)
+
+
 def test_phi_average_matches_quadrature():
     rng = np.random.default_rng(2)
     for _ in range(10):
