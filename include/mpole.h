@@ -142,7 +142,11 @@ int mpole_plan_nmodes(mpole_plan plan);
  * averages, merged-block kernel tables, radial kernel integrals and, for
  * the split precisions, their split planes (Sec. 2.2: the angular and radial
  * kernels are averaged once, before any solve).  The workspace must stay
- * allocated while the plan is used.  Rebinding is allowed.
+ * allocated while the plan is used.  Rebinding is allowed.  Returns after
+ * the table construction has completed on hip_stream (the call
+ * synchronises it).  The part of the workspace a solve uses for its
+ * intermediates is filled with NaN bit patterns here; every solve writes it
+ * before reading it.
  */
 int mpole_plan_bind(mpole_plan plan, void *dev_workspace, size_t bytes, void *hip_stream);
 
@@ -160,6 +164,28 @@ int mpole_plan_bind(mpole_plan plan, void *dev_workspace, size_t bytes, void *hi
  */
 int mpole_solve(mpole_plan plan, const double *rho, double *phi, double *ang_moments,
                 double *interior, double *exterior, void *hip_stream);
+
+/*
+ * mpole_solve for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, kernels and results, but the solve's intermediates (packed
+ * operands, split-K partials, moments, coefficients, edge sums) live in a
+ * static device array of the library, 256 MiB on each device it runs on,
+ * held until the process ends, instead of in the plan's workspace.  The
+ * call allocates nothing, host or device, and records no timing events.
+ * The plan must be bound (its tables stay in its workspace) on the device
+ * that is current at the call.  Every static solve on a device shares that
+ * device's array, which keeps the last solve's contents (each solve writes
+ * what it reads first), so static solves that overlap on one device race;
+ * serialise them (one stream, or events).
+ * Errors: MPOLE_ERR_UNSUPPORTED when a solve of this plan needs more than
+ * the array holds (checked first, also for an unbound plan),
+ * MPOLE_ERR_WORKSPACE for an unbound plan, MPOLE_ERR_INVALID for a null rho
+ * or another current device, MPOLE_ERR_DEVICE if the array could not be
+ * located at bind or a launch fails.
+ */
+int mpole_solve_static(mpole_plan plan, const double *rho, double *phi, double *ang_moments,
+                       double *interior, double *exterior, void *hip_stream);
 
 /*
  * Copy the FP64 block-averaged kernel table of coarsening class cls

@@ -178,6 +178,7 @@ enum SplitKind { kSplitBf16x3 = 1, kSplitFp16x2 = 2 };
 // ---- launchers (all asynchronous on `s`; return hipSuccess or the launch error)
 // bind time, per plan
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_word(void *p, size_t bytes, uint32_t word, hipStream_t s);   // every 32-bit word = word
 hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s);
 hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g, bool dense,
                          hipStream_t s);

@@ -141,15 +141,21 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
 #pragma unroll
   for (int u = 0; u < PACK_UNROLL; ++u) {
     const int b = b0 + u * PACK_THREADS;
+    // the FP64 row including its zero padding up to nblocks_pad (the padding
+    // lies in the span of the last block: spans are multiples of 16 long)
+    if (MODE != kSplitBf16x3 && b < C.nblocks_pad)
+      gmem(C.pack)[(size_t)row * C.nblocks_pad + b] = b < C.nblocks ? dev[u] : 0.0;
     if (b >= C.nblocks) continue;
-    if (MODE != kSplitBf16x3) gmem(C.pack)[(size_t)row * C.nblocks_pad + b] = dev[u];
     if (MODE != 0) {
       mono += s[u] * gmem(C.tcol0)[b];
       mx = fmax(mx, fabs(dev[u]));
     }
   }
   if (MODE != 0) {
-    if (bx == 0 && threadIdx.x == 0) gmem(P.shift)[i] = shift;
+    if (bx == 0 && threadIdx.x == 0) {
+      gmem(P.shift)[i] = shift;
+      if (MODE == kSplitBf16x3) gmem(C.pscale)[row] = 1.0;   // BF16 x3 rows are not scaled
+    }
     mono = block_sum(mono, red);
     if (MODE == kSplitFp16x2) mx = block_max(mx, red);
     if (threadIdx.x == 0) {
@@ -173,8 +179,9 @@ __global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
   const double scale = row_scale(mx);
   const double inv = 1.0 / scale;   // exact: a power of two
   const double *__restrict__ prow = C.pack + (size_t)row * C.nblocks_pad;
-  for (int b = threadIdx.x; b < C.nblocks; b += 256)
-    split_store<kSplitFp16x2>(prow[b] * inv, C.ppacks + slab_index<kSplitFp16x2>(row, b, C.nrows), 16);
+  for (int b = threadIdx.x; b < C.nblocks_pad; b += 256)   // zero planes past the last block
+    split_store<kSplitFp16x2>(b < C.nblocks ? prow[b] * inv : 0.0,
+                              C.ppacks + slab_index<kSplitFp16x2>(row, b, C.nrows), 16);
   if (threadIdx.x == 0) C.pscale[row] = scale;
 }
 

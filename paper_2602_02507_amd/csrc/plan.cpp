@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,20 +19,33 @@ using namespace mpole;
 
 namespace mpole {
 
-thread_local std::string g_error;
+// Per-solve scratch of mpole_solve_static: one copy of this array on every
+// device the library runs on, held until the process ends.  Every static
+// solve on a device uses it from the start (it keeps the last solve's
+// contents; the solve writes everything before reading it), so static
+// solves that overlap on one device race.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+}  // namespace mpole
+
+namespace mpole {
+
+// fixed-size per-thread message buffer: setting it never allocates
+thread_local char g_error[512];
 
 int fail(int code, const char *fmt, ...) {
-  char buf[512];
+  char buf[sizeof g_error];   // formatted apart, so that g_error may be an argument
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_error = buf;
+  std::memcpy(g_error, buf, sizeof buf);
   return code;
 }
 
 int ok() {
-  g_error.clear();
+  g_error[0] = '\0';
   return MPOLE_OK;
 }
 
@@ -129,6 +143,8 @@ struct mpole_plan_t {
   int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
   int scan_modes = kScanModesWide;   // modes per radial-scan workgroup
   size_t off_plandev = 0, off_prefix = 0;
+  size_t solve_off = 0, solve_bytes = 0;        // per-solve region: start in the workspace, size
+  size_t off_plandev_s = 0, off_classes_s = 0;  // device views of the static-scratch solve
   int wg_mom = 0, wg_exp = 0;
   GaussRule rule{};
   // per-phase timing events (host objects), recorded while timing is on
@@ -141,6 +157,13 @@ struct mpole_plan_t {
   char *ws = nullptr;
   PlanDev dev{};
   std::vector<ClassDev> cdev;
+  // mpole_solve_static: the same views with the per-solve region in the
+  // static scratch array of the bound device (valid when static_ok)
+  bool static_ok = false;
+  int static_dev = -1;
+  PlanDev dev_s{};
+  std::vector<ClassDev> cdev_s;
+  SepDev sdev_s{};
   std::vector<int32_t> prefix;   // [PH_COUNT][2] single-plan phase prefix sums
 };
 
@@ -455,11 +478,19 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->wg_mom = wm;
   p->wg_exp = we;
 
-  // workspace layout
-  size_t off = 0;
+  // workspace layout: the bind-time region (tables, maps, device views)
+  // first, then the per-solve region (everything a solve writes before it
+  // reads it: packed operands, partials, moments, coefficients, edge sums);
+  // per-solve offsets are relative to the start of their region
+  size_t off = 0, soff = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off = align256(off + bytes);
+    return o;
+  };
+  auto stake = [&](size_t bytes) {
+    const size_t o = soff;
+    soff = align256(soff + bytes);
     return o;
   };
   const int nplm = (p->L + 1) * (p->L + 2) / 2;
@@ -477,26 +508,26 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->off_ji = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
   p->off_rr = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
   p->off_ri = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
-  p->off_ang = take(sizeof(double) * (size_t)p->nr * p->namp);
-  p->off_coef = take(sizeof(double) * (size_t)p->nr * p->namp);
-  p->off_edge_r = take(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
-  p->off_edge_i = take(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
-  p->off_cplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * p->nr * p->namp);
-  p->off_cscale = take(sizeof(double) * (size_t)p->nr);
+  p->off_ang = stake(sizeof(double) * (size_t)p->nr * p->namp);
+  p->off_coef = stake(sizeof(double) * (size_t)p->nr * p->namp);
+  p->off_edge_r = stake(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
+  p->off_edge_i = stake(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
+  p->off_cplanes = stake(sizeof(uint16_t) * (size_t)p->nplanes * p->nr * p->namp);
+  p->off_cscale = stake(sizeof(double) * (size_t)p->nr);
   {
     int maxb = 0;
     for (auto &C : p->cls) maxb = std::max(maxb, C.nblocks);
     p->mono_stride = (maxb + kPackSpan - 1) / kPackSpan;
   }
-  p->off_mono = take(sizeof(double) * (size_t)p->nr * p->mono_stride);
-  p->off_max = take(sizeof(double) * (size_t)p->nr * p->mono_stride);
-  p->off_shift = take(sizeof(double) * (size_t)p->nr);
+  p->off_mono = stake(sizeof(double) * (size_t)p->nr * p->mono_stride);
+  p->off_max = stake(sizeof(double) * (size_t)p->nr * p->mono_stride);
+  p->off_shift = stake(sizeof(double) * (size_t)p->nr);
   p->off_tsum_part = take(sizeof(double) * (size_t)kTsumChunks * p->namp);
   p->off_litems = take(sizeof(int32_t) * p->litems.size());
   p->off_lbase = take(sizeof(int32_t) * p->lbase.size());
-  p->off_lsum = take(p->sep ? 0 : sizeof(double) * (p->litems.size() / 2));
+  p->off_lsum = stake(p->sep ? 0 : sizeof(double) * (p->litems.size() / 2));
   p->off_lchunks = take(sizeof(int32_t) * p->lchunks.size());
-  p->off_lpart = take(sizeof(double) * 2 * (p->lchunks.size() / 4));
+  p->off_lpart = stake(sizeof(double) * 2 * (p->lchunks.size() / 4));
   for (auto &C : p->cls) {
     const size_t nrows = C.rows.size();
     C.off_rows = take(sizeof(int32_t) * std::max<size_t>(nrows, 1));
@@ -511,25 +542,25 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_tcol0 = take(dense * sizeof(double) * (size_t)C.nblocks_pad);
     C.off_wsum = take(sizeof(double) * (size_t)C.nblocks_pad);
     C.off_tsum = take(dense * sizeof(double) * (size_t)p->namp);
-    C.off_pack = take(dense * sizeof(double) * nrows * C.nblocks_pad);
+    C.off_pack = stake(dense * sizeof(double) * nrows * C.nblocks_pad);
     // split-K partials: FP64 for the f64 kernel, FP32 (the accumulator type) for split precisions
-    C.off_partial = take(dense * (p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp);
+    C.off_partial = stake(dense * (p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp);
     C.off_sep_src = take(sizeof(int32_t) * C.sep_src.size());
     C.off_sep_avg = take(sizeof(int32_t) * C.sep_avg.size());
     C.off_tplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
     C.off_ttplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
-    C.off_ppacks = take(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.nblocks_pad);
-    C.off_pscale = take(sizeof(double) * std::max<size_t>(nrows, 1));
+    C.off_ppacks = stake(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.nblocks_pad);
+    C.off_pscale = stake(sizeof(double) * std::max<size_t>(nrows, 1));
   }
   if (p->sep) {
     const size_t L1 = p->L + 1, nrt = (size_t)p->nr * p->nt;
     p->off_tw = take(sizeof(double) * 2 * (size_t)p->tpad * p->np);
     p->off_pw = take(sizeof(double) * L1 * p->nt * L1);
     p->off_pt = take(sizeof(double) * L1 * L1 * p->nt);
-    p->off_shat = take(p->any_alt ? sizeof(double) * (size_t)p->nr * p->ncell : 0);
+    p->off_shat = stake(p->any_alt ? sizeof(double) * (size_t)p->nr * p->ncell : 0);
     p->off_rowalt = take(nrt);
-    p->off_f = take(sizeof(double) * nrt * p->tpad);
-    p->off_g = take(sizeof(double) * nrt * p->tpad);
+    p->off_f = stake(sizeof(double) * nrt * p->tpad);
+    p->off_g = stake(sizeof(double) * nrt * p->tpad);
     p->off_scls = take(sizeof(SepClass) * p->ncls);
     // fragment-order split tables (64 lanes x 16 bytes per K step, tile and plane)
     p->ks_a = (p->np + 31) / 32;
@@ -540,10 +571,16 @@ void layout_plan(mpole_plan_t *p, int target) {
     p->off_twf = take(p->sep_bf16 ? frag * p->ks_a * p->mt_a : 0);
     p->off_ttf = take(p->sep_bf16 ? frag * p->ks_s * p->nt_s : 0);
   }
-  // the single-plan view of the batched kernels: one device plan, phase prefix sums
+  // the single-plan view of the batched kernels: one device plan, phase prefix
+  // sums; and the view of mpole_solve_static (per-solve region in the static
+  // scratch array): its own device plan and class views
   p->off_plandev = take(sizeof(PlanDev));
   p->off_prefix = take(sizeof(int32_t) * PH_COUNT * 2);
-  p->ws_bytes = off;
+  p->off_plandev_s = take(sizeof(PlanDev));
+  p->off_classes_s = take(sizeof(ClassDev) * p->ncls);
+  p->solve_off = off;
+  p->solve_bytes = soff;
+  p->ws_bytes = off + soff;
 }
 
 // Runs one phase launch, bracketed by timing events when timing is on.
@@ -578,7 +615,7 @@ extern "C" {
 
 int mpole_abi_version(void) { return MPOLE_ABI_VERSION; }
 
-const char *mpole_last_error(void) { return g_error.c_str(); }
+const char *mpole_last_error(void) { return g_error; }
 
 int mpole_plan_create(const mpole_mesh *mesh, mpole_plan *out) {
   if (!out) return fail(MPOLE_ERR_INVALID, "out is null");
@@ -619,17 +656,11 @@ int phase_wgs_host(const mpole_plan_t *p, int h) {
   return 0;
 }
 
-// Device view of a plan in workspace ws, table construction and the
-// single-plan batch view (device plan copy + prefix sums), all enqueued on s.
-int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
-  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
-  if (!dev_ws) return fail(MPOLE_ERR_WORKSPACE, "workspace is null");
-  if (((uintptr_t)dev_ws & 255) != 0) return fail(MPOLE_ERR_WORKSPACE, "workspace is not 256-byte aligned");
-  if (bytes < p->ws_bytes)
-    return fail(MPOLE_ERR_WORKSPACE, "workspace has %zu bytes, plan needs %zu", bytes, p->ws_bytes);
-  hipStream_t s = (hipStream_t)stream;
-  char *ws = (char *)dev_ws;
-  PlanDev &D = p->dev;
+// Device views of plan p: the bind-time region of the workspace at ws, the
+// per-solve region at sv (the workspace's own, or the static scratch array),
+// the class views at device address classes_dev.
+void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev, PlanDev &D,
+                std::vector<ClassDev> &cd, SepDev &S) {
   D = PlanDev{};
   D.pack_parts = p->mono_stride;
   D.wg_mom = p->wg_mom;
@@ -651,7 +682,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   D.phi_edges = (const double *)(ws + p->off_ph);
   D.shell_class = (const int32_t *)(ws + p->off_shell_class);
   D.shell_row = (const int32_t *)(ws + p->off_shell_row);
-  D.classes = (ClassDev *)(ws + p->off_classes);
+  D.classes = classes_dev;
   D.pavg = (double *)(ws + p->off_pavg);
   D.trig = (double *)(ws + p->off_trig);
   D.weight = (double *)(ws + p->off_weight);
@@ -660,28 +691,28 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   D.ji = (double *)(ws + p->off_ji);
   D.rr = (double *)(ws + p->off_rr);
   D.ri = (double *)(ws + p->off_ri);
-  D.ang = (double *)(ws + p->off_ang);
-  D.coef = (double *)(ws + p->off_coef);
-  D.edge_r = (double *)(ws + p->off_edge_r);
-  D.edge_i = (double *)(ws + p->off_edge_i);
-  D.cplanes = (uint16_t *)(ws + p->off_cplanes);
-  D.cscale = (double *)(ws + p->off_cscale);
-  D.mono_part = p->nplanes ? (double *)(ws + p->off_mono) : nullptr;
-  D.max_part = (double *)(ws + p->off_max);
+  D.ang = (double *)(sv + p->off_ang);
+  D.coef = (double *)(sv + p->off_coef);
+  D.edge_r = (double *)(sv + p->off_edge_r);
+  D.edge_i = (double *)(sv + p->off_edge_i);
+  D.cplanes = (uint16_t *)(sv + p->off_cplanes);
+  D.cscale = (double *)(sv + p->off_cscale);
+  D.mono_part = p->nplanes ? (double *)(sv + p->off_mono) : nullptr;
+  D.max_part = (double *)(sv + p->off_max);
   D.mono_stride = p->mono_stride;
-  D.shift = (double *)(ws + p->off_shift);
+  D.shift = (double *)(sv + p->off_shift);
   D.tsum_part = (double *)(ws + p->off_tsum_part);
   D.litems = (const int2 *)(ws + p->off_litems);
   D.lbase = (const int32_t *)(ws + p->off_lbase);
-  D.lsum = p->sep ? nullptr : (double *)(ws + p->off_lsum);
+  D.lsum = p->sep ? nullptr : (double *)(sv + p->off_lsum);
   D.n_litems = (int32_t)(p->litems.size() / 2);
   D.lchunks = (const int4 *)(ws + p->off_lchunks);
-  D.lpart = (double *)(ws + p->off_lpart);
+  D.lpart = (double *)(sv + p->off_lpart);
   D.n_lchunks = (int32_t)(p->lchunks.size() / 4);
-  p->cdev.assign(p->ncls, ClassDev{});
+  cd.assign(p->ncls, ClassDev{});
   for (int c = 0; c < p->ncls; ++c) {
     const ClassHost &H = p->cls[c];
-    ClassDev &C = p->cdev[c];
+    ClassDev &C = cd[c];
     C.rows = (const int32_t *)(ws + H.off_rows);
     C.moff = (const int32_t *)(ws + H.off_moff);
     C.mem = (const int32_t *)(ws + H.off_mem);
@@ -695,12 +726,12 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     C.tcol0 = (double *)(ws + H.off_tcol0);
     C.wsum = (double *)(ws + H.off_wsum);
     C.tsum = (double *)(ws + H.off_tsum);
-    C.pack = (double *)(ws + H.off_pack);
-    C.partial = (double *)(ws + H.off_partial);
+    C.pack = (double *)(sv + H.off_pack);
+    C.partial = (double *)(sv + H.off_partial);
     C.tplanes = (uint16_t *)(ws + H.off_tplanes);
     C.ttplanes = (uint16_t *)(ws + H.off_ttplanes);
-    C.ppacks = (uint16_t *)(ws + H.off_ppacks);
-    C.pscale = (double *)(ws + H.off_pscale);
+    C.ppacks = (uint16_t *)(sv + H.off_ppacks);
+    C.pscale = (double *)(sv + H.off_pscale);
     C.nrows = (int)H.rows.size();
     C.nblocks = H.nblocks;
     C.nblocks_pad = H.nblocks_pad;
@@ -713,9 +744,84 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     C.wg_mom_begin = H.wg_mom_begin;
     C.wg_exp_begin = H.wg_exp_begin;
   }
+  S = SepDev{};
+  if (p->sep) {
+    S.tpad = p->tpad;
+    S.tw = (double *)(ws + p->off_tw);
+    S.pw = (double *)(ws + p->off_pw);
+    S.pt = (double *)(ws + p->off_pt);
+    S.shat = p->any_alt ? (double *)(sv + p->off_shat) : nullptr;
+    S.rowalt = p->any_alt ? (const uint8_t *)(ws + p->off_rowalt) : nullptr;
+    S.f = (double *)(sv + p->off_f);
+    S.g = (double *)(sv + p->off_g);
+    S.dom = D.dom;
+    S.cls = (const SepClass *)(ws + p->off_scls);
+    S.max_src = p->max_src;
+    S.max_avg = p->max_avg;
+    S.twf = p->sep_bf16 ? (const uint32_t *)(ws + p->off_twf) : nullptr;
+    S.ttf = p->sep_bf16 ? (const uint32_t *)(ws + p->off_ttf) : nullptr;
+    S.ks_a = p->ks_a;
+    S.mt_a = p->mt_a;
+    S.ks_s = p->ks_s;
+    S.nt_s = p->nt_s;
+    S.fuse_nk = p->sep_bf16 ? kSepFuseNk : 0;
+  }
+}
+
+// Bind-time set-up of the allocation-free entry point: the device address
+// of the current device's copy of the static scratch array, or null if it
+// cannot be resolved.  The address is looked up once per device, with that
+// device current, and kept; host code uses it, never the array's name (in
+// host code the name is only a stand-in for the symbol).
+char *scratch_address() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static char *addr[kMaxDevices] = {};
+  static bool tried[kMaxDevices] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!tried[dev]) {
+    tried[dev] = true;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess)
+      addr[dev] = (char *)ptr;
+    else
+      (void)hipGetLastError();   // leave no sticky error for the launches that follow
+  }
+  return addr[dev];
+}
+
+// Device views of a plan in workspace ws, table construction and the
+// single-plan batch view (device plan copy + prefix sums), all enqueued on s.
+int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (!dev_ws) return fail(MPOLE_ERR_WORKSPACE, "workspace is null");
+  if (((uintptr_t)dev_ws & 255) != 0) return fail(MPOLE_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < p->ws_bytes)
+    return fail(MPOLE_ERR_WORKSPACE, "workspace has %zu bytes, plan needs %zu", bytes, p->ws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)dev_ws;
+  make_views(p, ws, ws + p->solve_off, (ClassDev *)(ws + p->off_classes), p->dev, p->cdev, p->sdev);
+  const PlanDev &D = p->dev;
+  // the static-scratch views, when the per-solve region fits the array
+  p->static_ok = false;
+  if (p->solve_bytes <= kScratchBytes) {
+    char *sc = scratch_address();
+    if (sc != nullptr) {
+      make_views(p, ws, sc, (ClassDev *)(ws + p->off_classes_s), p->dev_s, p->cdev_s, p->sdev_s);
+      p->static_ok = hipGetDevice(&p->static_dev) == hipSuccess;
+    }
+  }
   hipError_t e = hipSuccess;
-  // zero the whole workspace first: padding rows/columns of every operand must be 0
-  if (e == hipSuccess) e = launch_fill_zero(ws, p->ws_bytes, s);
+  // the bind-time region starts zeroed (padding rows and columns of every
+  // table are 0); the per-solve region is filled with NaN bit patterns, so a
+  // read of anything a solve has not written first shows up in its results
+  if (e == hipSuccess) e = launch_fill_zero(ws, p->solve_off, s);
+  if (e == hipSuccess) e = launch_fill_word(ws + p->solve_off, p->solve_bytes, 0xFFFFFFFFu, s);
   if (e == hipSuccess) e = upload(ws, p->off_r, p->r.data(), sizeof(double) * p->r.size(), s);
   if (e == hipSuccess) e = upload(ws, p->off_th, p->th.data(), sizeof(double) * p->th.size(), s);
   if (e == hipSuccess) e = upload(ws, p->off_ph, p->ph.data(), sizeof(double) * p->ph.size(), s);
@@ -740,27 +846,11 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   for (int h = 0; h < PH_COUNT; ++h) p->prefix[2 * h + 1] = phase_wgs_host(p, h);
   if (e == hipSuccess) e = upload(ws, p->off_plandev, &p->dev, sizeof(PlanDev), s);
   if (e == hipSuccess) e = upload(ws, p->off_prefix, p->prefix.data(), sizeof(int32_t) * p->prefix.size(), s);
+  if (e == hipSuccess && p->static_ok) {
+    e = upload(ws, p->off_plandev_s, &p->dev_s, sizeof(PlanDev), s);
+    if (e == hipSuccess) e = upload(ws, p->off_classes_s, p->cdev_s.data(), sizeof(ClassDev) * p->ncls, s);
+  }
   if (p->sep) {
-    SepDev &S = p->sdev;
-    S.tpad = p->tpad;
-    S.tw = (double *)(ws + p->off_tw);
-    S.pw = (double *)(ws + p->off_pw);
-    S.pt = (double *)(ws + p->off_pt);
-    S.shat = p->any_alt ? (double *)(ws + p->off_shat) : nullptr;
-    S.rowalt = p->any_alt ? (const uint8_t *)(ws + p->off_rowalt) : nullptr;
-    S.f = (double *)(ws + p->off_f);
-    S.g = (double *)(ws + p->off_g);
-    S.dom = D.dom;
-    S.cls = (const SepClass *)(ws + p->off_scls);
-    S.max_src = p->max_src;
-    S.max_avg = p->max_avg;
-    S.twf = p->sep_bf16 ? (const uint32_t *)(ws + p->off_twf) : nullptr;
-    S.ttf = p->sep_bf16 ? (const uint32_t *)(ws + p->off_ttf) : nullptr;
-    S.ks_a = p->ks_a;
-    S.mt_a = p->mt_a;
-    S.ks_s = p->ks_s;
-    S.nt_s = p->nt_s;
-    S.fuse_nk = p->sep_bf16 ? kSepFuseNk : 0;
     p->scls.assign(p->ncls, SepClass{});
     for (int c = 0; c < p->ncls; ++c) {
       const ClassHost &H = p->cls[c];
@@ -776,11 +866,12 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   if (e == hipSuccess && p->sep) e = launch_sep_tables(D, p->sdev, s);
   if (e == hipSuccess && p->sep_bf16) e = launch_sep_split_tables(D, p->sdev, s);
   if (e == hipSuccess && p->nplanes) e = launch_split_tables(D, p->cdev.data(), p->precision, s);
-  // unit row scales (BF16 x3 operands are not scaled; FP16 x2 rows overwrite theirs)
-  for (int c = 0; c < p->ncls && e == hipSuccess; ++c)
-    e = launch_fill_value(p->cdev[c].pscale, std::max<size_t>(p->cls[c].rows.size(), 1), 1.0, s);
+  // the uploads above read host memory of this plan that later calls may
+  // change (rebinding, tuning): wait for them before returning
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     p->bound = false;
+    p->static_ok = false;
     return fail(MPOLE_ERR_DEVICE, "bind: %s", hipGetErrorString(e));
   }
   p->ws = ws;
@@ -802,14 +893,12 @@ struct LargeJob {
 // potential (moments only).
 template <class Timer>
 hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, int scan_modes, bool phi,
-                     const std::vector<LargeJob> &large,
-                     hipStream_t s, Timer &&timed) {
+                     const LargeJob *large, int nlarge, hipStream_t s, Timer &&timed) {
   const int k = precision;
   hipError_t e = launch_stamp_reset(B, s);
   if (e == hipSuccess) e = timed(MPOLE_PHASE_PACK, [&] {
     hipError_t r = hipSuccess;
-    for (const LargeJob &j : large)
-      if (r == hipSuccess) r = launch_large(*j.P, kLargeSum, j.rho, nullptr, s);
+    for (int q = 0; q < nlarge && r == hipSuccess; ++q) r = launch_large(*large[q].P, kLargeSum, large[q].rho, nullptr, s);
     if (r == hipSuccess) r = launch_pack(B, k, wgs[PH_PACK], s);
     if (r == hipSuccess) r = launch_split_rows(B, wgs[PH_SPLITROWS], s);
     return r;
@@ -821,8 +910,7 @@ hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, int scan_
     e = timed(MPOLE_PHASE_SPLIT, [&] { return launch_split_coef(B, k, wgs[PH_COEF], s); });
   if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] {
     hipError_t r = launch_expand(B, k, wgs[PH_EXPAND], s);
-    for (const LargeJob &j : large)
-      if (r == hipSuccess) r = launch_large(*j.P, kLargeBcast, nullptr, j.phi, s);
+    for (int q = 0; q < nlarge && r == hipSuccess; ++q) r = launch_large(*large[q].P, kLargeBcast, nullptr, large[q].phi, s);
     return r;
   });
   return e;
@@ -902,18 +990,19 @@ int mpole_plan_bind(mpole_plan p, void *dev_ws, size_t bytes, void *stream) {
 namespace {
 
 // The separable solve of one plan on stream s (phi == null: moments only).
+// (scratch: the static-scratch views of mpole_solve_static)
 template <class Timer>
 hipError_t run_sep(mpole_plan_t *p, const double *rho, double *phi, double *ang, double *interior, double *exterior,
-                   hipStream_t s, Timer &&T) {
+                   hipStream_t s, Timer &&T, bool scratch = false) {
   BatchDev B{};
-  B.plans = (const PlanDev *)(p->ws + p->off_plandev);
+  B.plans = (const PlanDev *)(p->ws + (scratch ? p->off_plandev_s : p->off_plandev));
   B.io = nullptr;
   B.io1 = SolveIO{rho, phi, ang, interior, exterior};
   B.prefix = (const int32_t *)(p->ws + p->off_prefix);
   B.nf = 1;
   B.stamps = nullptr;
-  const PlanDev &D = p->dev;
-  const SepDev &S = p->sdev;
+  const PlanDev &D = scratch ? p->dev_s : p->dev;
+  const SepDev &S = scratch ? p->sdev_s : p->sdev;
   hipError_t e = hipSuccess;
   if (p->any_alt) e = T(MPOLE_PHASE_PACK, [&] { return launch_sep_source(D, S, rho, s); });
   if (e == hipSuccess) e = T(MPOLE_PHASE_MOMENT, [&] {
@@ -928,6 +1017,34 @@ hipError_t run_sep(mpole_plan_t *p, const double *rho, double *phi, double *ang,
   return e;
 }
 
+// One solve of plan p on stream s through its workspace views (scratch =
+// false) or its static-scratch views; arguments already checked.
+int solve_views(mpole_plan_t *p, const double *rho, double *phi, double *ang, double *interior, double *exterior,
+                hipStream_t s, bool scratch) {
+  BatchDev B{};
+  B.plans = (const PlanDev *)(p->ws + (scratch ? p->off_plandev_s : p->off_plandev));
+  B.io = nullptr;
+  B.io1 = SolveIO{rho, phi, ang, interior, exterior};
+  B.prefix = (const int32_t *)(p->ws + p->off_prefix);
+  B.nf = 1;
+  B.stamps = nullptr;
+  int wgs[PH_COUNT];
+  for (int h = 0; h < PH_COUNT; ++h) wgs[h] = p->prefix[2 * h + 1];
+  // the static-scratch solve records no timing events (creating them would
+  // allocate host objects)
+  auto timer = [&](int phase, auto &&launch) { return scratch ? launch() : timed(p, phase, s, launch); };
+  hipError_t e;
+  if (p->sep) {
+    e = run_sep(p, rho, phi, ang, interior, exterior, s, timer, scratch);
+  } else {
+    const LargeJob large{scratch ? &p->dev_s : &p->dev, rho, phi};
+    e = run_solve(B, p->precision, wgs, p->scan_modes, phi != nullptr, &large, p->dev.n_litems > 0 ? 1 : 0, s,
+                  timer);
+  }
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
+  return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -937,28 +1054,24 @@ int mpole_solve(mpole_plan p, const double *rho, double *phi, double *ang, doubl
   if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
   if (!p->bound) return fail(MPOLE_ERR_WORKSPACE, "plan has no bound workspace");
   if (!rho) return fail(MPOLE_ERR_INVALID, "rho is null");
-  hipStream_t s = (hipStream_t)stream;
-  BatchDev B{};
-  B.plans = (const PlanDev *)(p->ws + p->off_plandev);
-  B.io = nullptr;
-  B.io1 = SolveIO{rho, phi, ang, interior, exterior};
-  B.prefix = (const int32_t *)(p->ws + p->off_prefix);
-  B.nf = 1;
-  B.stamps = nullptr;
-  int wgs[PH_COUNT];
-  for (int h = 0; h < PH_COUNT; ++h) wgs[h] = p->prefix[2 * h + 1];
-  hipError_t e;
-  if (p->sep) {
-    e = run_sep(p, rho, phi, ang, interior, exterior, s,
-                [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
-  } else {
-    std::vector<LargeJob> large;
-    if (p->dev.n_litems > 0) large.push_back(LargeJob{&p->dev, rho, phi});
-    e = run_solve(B, p->precision, wgs, p->scan_modes, phi != nullptr, large, s,
-                  [&](int phase, auto &&launch) { return timed(p, phase, s, launch); });
-  }
-  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve: %s", hipGetErrorString(e));
-  return ok();
+  return solve_views(p, rho, phi, ang, interior, exterior, (hipStream_t)stream, false);
+}
+
+int mpole_solve_static(mpole_plan p, const double *rho, double *phi, double *ang, double *interior,
+                       double *exterior, void *stream) {
+  if (!p) return fail(MPOLE_ERR_INVALID, "plan is null");
+  if (p->solve_bytes > kScratchBytes)
+    return fail(MPOLE_ERR_UNSUPPORTED, "a solve of this plan needs %zu bytes of scratch; the static array holds %zu",
+                p->solve_bytes, kScratchBytes);
+  if (!p->bound) return fail(MPOLE_ERR_WORKSPACE, "plan has no bound workspace");
+  if (!rho) return fail(MPOLE_ERR_INVALID, "rho is null");
+  if (!p->static_ok) return fail(MPOLE_ERR_DEVICE, "the static scratch array was not resolved when the plan was bound");
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "solve_static: %s", hipGetErrorString(e));
+  if (dev != p->static_dev)
+    return fail(MPOLE_ERR_INVALID, "current device %d is not the device %d the plan was bound on", dev, p->static_dev);
+  return solve_views(p, rho, phi, ang, interior, exterior, (hipStream_t)stream, true);
 }
 
 int mpole_plan_copy_table(mpole_plan p, int32_t cls, double *host_out, int64_t *nblocks, void *stream) {
@@ -1100,7 +1213,7 @@ int mpole_batch_create(int32_t nfields, const mpole_mesh *meshes, mpole_batch *o
       if (rc != MPOLE_OK) {
         delete p;
         delete b;
-        std::string msg = g_error;
+        const std::string msg(g_error);
         return fail(rc, "field %d: %s", f, msg.c_str());
       }
       p->scan_modes = kScanModesNarrow;
@@ -1132,7 +1245,7 @@ int mpole_batch_tune(mpole_batch b, const mpole_tuning *tunings) {
     for (size_t f = 0; f < b->plans.size(); ++f) {
       const int rc = check_tuning(b->plans[f], &tunings[f]);
       if (rc) {
-        const std::string msg = g_error;
+        const std::string msg(g_error);
         return fail(rc, "field %zu: %s", f, msg.c_str());
       }
     }
@@ -1168,7 +1281,7 @@ int mpole_batch_bind(mpole_batch b, void *dev_ws, size_t bytes, const double *co
   for (int f = 0; f < nf; ++f) {
     const int rc = bind_plan(b->plans[f], ws + b->off[f], b->plans[f]->ws_bytes, stream);
     if (rc != MPOLE_OK) {
-      std::string msg = g_error;
+      const std::string msg(g_error);
       return fail(rc, "field %d: %s", f, msg.c_str());
     }
   }
@@ -1222,7 +1335,8 @@ int mpole_batch_solve(mpole_batch b, void *stream) {
     std::vector<LargeJob> large;
     for (int f = 0; f < nf; ++f)
       if (b->plans[f]->dev.n_litems > 0) large.push_back(LargeJob{&b->plans[f]->dev, b->io[f].rho, b->io[f].phi});
-    e = run_solve(B, b->precision, wgs, kScanModesNarrow, true, large, (hipStream_t)stream, [](int, auto &&launch) { return launch(); });
+    e = run_solve(B, b->precision, wgs, kScanModesNarrow, true, large.data(), (int)large.size(), (hipStream_t)stream,
+                  [](int, auto &&launch) { return launch(); });
   }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch solve: %s", hipGetErrorString(e));
   return ok();

@@ -307,7 +307,8 @@ __global__ __launch_bounds__(NTHREADS) void k_sep_phi_syn(PlanDev P, SepDev S, d
   const KRows A{S.g, (long)S.tpad * P.ntheta, P.ntheta};
   const KRows Bop{S.tw + (long)S.tpad * P.nphi, 0, P.nphi};   // TT follows TW
   d4 acc[2][2];
-  tile_product<false, false>(A, A.ld, Bop, Bop.ld, i, P.ntheta, P.nphi, S.tpad, m0, n0, acc, As, Bs);
+  // K = the 2L + 1 trig modes G holds (its padding rows are never written)
+  tile_product<false, false>(A, A.ld, Bop, Bop.ld, i, P.ntheta, P.nphi, 2 * P.lmax + 1, m0, n0, acc, As, Bs);
   const auto out = gmem(phi) + (long)i * P.ncell;
 #pragma unroll
   for (int t = 0; t < 2; ++t)

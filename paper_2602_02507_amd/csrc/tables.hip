@@ -184,9 +184,9 @@ __global__ void k_radial(PlanDev P) {
   P.ri[t] = ji / v3;
 }
 
-__global__ void k_fill_zero(uint4 *p, size_t n16) {
+__global__ void k_fill_word(uint4 *p, size_t n16, uint32_t w) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
-    p[i] = make_uint4(0, 0, 0, 0);
+    p[i] = make_uint4(w, w, w, w);
 }
 
 __global__ void k_fill_value(double *p, size_t n, double v) {
@@ -197,14 +197,16 @@ inline unsigned grid_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs);
 
 }  // namespace
 
-hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+hipError_t launch_fill_word(void *p, size_t bytes, uint32_t word, hipStream_t s) {
   // callers pass 16-byte multiples of 256-byte aligned workspace regions
   const size_t n16 = bytes / 16;
   if (n16 == 0) return hipSuccess;
   const unsigned g = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, (uint4 *)p, n16);
+  hipLaunchKernelGGL(k_fill_word, dim3(g), dim3(256), 0, s, (uint4 *)p, n16, word);
   return hipGetLastError();
 }
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) { return launch_fill_word(p, bytes, 0u, s); }
 
 hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s) {
   if (n == 0) return hipSuccess;
