@@ -148,6 +148,9 @@ def solve_bound(plan, precision, ms):
     cells = float(nr) * nt * nph
     nam = (plan.lmax + 1) ** 2
     mflops, eflops, min_bytes = plan.work()
+    # a folded plan contracts block pairs: half the multiply-adds and half the
+    # kernel table of the algorithmic count
+    fold = 0.5 if getattr(plan, "folded", False) else 1.0
     scan_bytes = 8.0 * nam * (nr + 3 * (nr + 1))
     t = {}
     if precision in ("fp64sep", "bf16x3sep"):
@@ -165,11 +168,11 @@ def solve_bound(plan, precision, ms):
         prod = {"fp64": 1, "bf16x3": 6, "fp16x2": 3}[precision]
         opb = {"fp64": 8.0, "bf16x3": 6.0, "fp16x2": 4.0}[precision]   # bytes per operand element
         blocks = mflops / (2.0 * nam)                  # (shell, merged block) pairs
-        table = (min_bytes - 16.0 * cells) * opb / 8.0
+        table = (min_bytes - 16.0 * cells) * opb / 8.0 * fold
         t["pack"] = (8.0 * cells + opb * blocks) / hbm
-        t["moment"] = max(mflops * prod / peak, (opb * blocks + table) / hbm)
+        t["moment"] = max(mflops * fold * prod / peak, (opb * blocks + table) / hbm)
         t["scan"] = scan_bytes / hbm
-        t["expand"] = max(eflops * prod / peak, (table + 8.0 * cells) / hbm)
+        t["expand"] = max(eflops * fold * prod / peak, (table + 8.0 * cells) / hbm)
     bound = sum(t.values()) * 1e3
     return {"bound_ms": bound, "measured_ms": ms, "frac": bound / ms,
             "phase_bound_ms": {k: v * 1e3 for k, v in t.items()}}
@@ -190,11 +193,14 @@ def roofline(plan, phases, precision, workload):
     # executed MFMA work: the split precisions run `products` narrow products per
     # algorithmic multiply-add, over padded tiles
     products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1, "bf16x3sep": 6}[precision]
+    # a folded plan executes half the algorithmic multiply-adds (block pairs)
+    fold = 0.5 if getattr(plan, "folded", False) else 1.0
     return {"bound": "mfma", "kernel": kernel_name(precision, dom),
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
             "traffic": measured_traffic(workload, dom), "launch_ms": dom_ms,
             "algorithmic_flops_per_launch": flops, "narrow_products_per_madd": products,
-            "executed_frac_lower_bound": achieved * products / peak,
+            "mirror_fold": fold < 1.0, "executed_flops_per_launch": flops * fold * products,
+            "executed_frac_lower_bound": achieved * fold * products / peak,
             "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
 
 

@@ -135,6 +135,21 @@ size_t mpole_plan_workspace_bytes(mpole_plan plan);
 int mpole_plan_nmodes(mpole_plan plan);
 
 /*
+ * 1 if the plan's dense contractions run folded over mirror pairs, else 0
+ * (also for a null plan).  A mesh whose theta edges are symmetric about the
+ * equator and whose coarsening blocks map onto blocks under theta -> pi -
+ * theta has kernels that differ between a block and its mirror image only
+ * by the sign (-1)^(l+m) (P~_l^m is even or odd in cos theta); the moment
+ * contraction then runs over the sums (even l+m) and differences (odd l+m)
+ * of the two blocks' sources, and the expansion over the even and odd mode
+ * sums of one block of each pair, giving both blocks' potentials: the same
+ * sums of Eqs. AngularMomentsDiscrete and Solution with about half the
+ * multiply-adds.  Dense precisions only; the environment variable
+ * MPOLE_FOLD=0 at plan creation turns it off.
+ */
+int mpole_plan_folded(mpole_plan plan);
+
+/*
  * Bind a device workspace (256-byte aligned, at least
  * mpole_plan_workspace_bytes) and enqueue the one-time table construction
  * on hip_stream (a hipStream_t; NULL = default stream): Legendre cell

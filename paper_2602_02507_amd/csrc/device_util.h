@@ -4,6 +4,9 @@
 
 namespace mpole {
 
+// int pair as a plain vector type (loads through global address-space pointers)
+typedef int i2v __attribute__((ext_vector_type(2)));
+
 // Linear workgroup id -> logical tile id such that XCD x (which receives the
 // hardware ids w = x mod 8 of a launch) owns the contiguous logical ids
 // [x*q + min(x, r), ...): tiles that share operand panels then share an L2.
@@ -33,6 +36,30 @@ __device__ inline T ld_const(const T *p) {
 template <class T>
 __device__ inline __attribute__((address_space(1))) T *gmem(T *p) {
   return (__attribute__((address_space(1))) T *)p;
+}
+
+// (l, m, a) of natural mode n = l^2 (m = 0), l^2 + 2m - 1 (cos), l^2 + 2m (sin).
+__device__ inline void mode_lma(int n, int &l, int &m, int &a) {
+  l = (int)sqrt((double)n);
+  while ((l + 1) * (l + 1) <= n) ++l;
+  while (l * l > n) --l;
+  const int d = n - l * l;
+  m = (d + 1) >> 1;
+  a = (d > 0 && (d & 1) == 0) ? 1 : 0;
+}
+
+// Kernel of natural mode n for pair q of a class: the rep block's table
+// entry; zero for padding, and for the odd modes of a block that is its own
+// mirror image when the plan is folded (their cell averages vanish).
+__device__ inline double pair_kernel(const PlanDev &P, const ClassDev &C, int q, int n) {
+  if (q >= C.npair || n < 0 || n >= P.nam) return 0.0;
+  const int2 pr = C.pairs[q];
+  if (P.fold && pr.x == pr.y) {
+    int l, m, a;
+    mode_lma(n, l, m, a);
+    if ((l + m) & 1) return 0.0;
+  }
+  return C.table[(size_t)pr.x * P.namp + n];
 }
 
 // cos t0 - cos t1 as a product, exact for thin theta cells.

@@ -64,10 +64,11 @@ __global__ __launch_bounds__(NTHREADS) void k_moment_f64(BatchDev B) {
   const int split = rest / C.n_tiles_mom;
   const int m0 = mt * BM, n0 = nt * BN;
   const int kbeg = split * C.kchunk;
-  const int kend = min(kbeg + C.kchunk, C.nblocks_pad);
-  const int nrows = C.nrows, ldp = C.nblocks_pad, namp = P.namp;
-  const double *__restrict__ Pk = C.pack;
-  const double *__restrict__ T = C.table;
+  const int kend = min(kbeg + C.kchunk, C.npair_pad);
+  // K = pairs, N = moment mode columns; odd columns contract the odd packed source
+  const int nrows = C.nrows, ldp = C.npair_pad, namp = P.namp_m;
+  const double *__restrict__ Pk = n0 >= P.odd_m0 ? C.pack_o : C.pack;
+  const double *__restrict__ T = C.tm;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -146,9 +147,10 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
   const int mt = local % C.m_tiles_exp;
   const int nt = local / C.m_tiles_exp;
   const int m0 = mt * BM, n0 = nt * BN;
-  const int nrows = C.nrows, namp = P.namp;
-  const double *__restrict__ T = C.table;
-  const double *__restrict__ coef = P.coef;
+  // N = pairs, K = expansion mode columns (even columns, then odd ones)
+  const int nrows = C.nrows, namp = P.namp_e;
+  const double *__restrict__ T = C.te;
+  const double *__restrict__ coef = P.coef_e;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -156,18 +158,19 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
   const int lr = tid >> 2, lk = (tid & 3) * 4;
   const bool a_ok = (m0 + lr) < nrows;
   const int shell_a = a_ok ? gmem(C.rows)[m0 + lr] : 0;
-  const bool b_ok = (n0 + lr) < C.nblocks_pad;
+  const bool b_ok = (n0 + lr) < C.npair_pad;
   const double *arow = coef + (size_t)shell_a * namp;
   const double *brow = T + (size_t)(b_ok ? n0 + lr : 0) * namp;
 
-  d4 acc[2][2];
+  // even-column and odd-column sums (the odd ones stay 0 when unfolded)
+  d4 acc[2][2], acco[2][2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < 2; ++u) acc[t][u] = acco[t][u] = d4{0.0, 0.0, 0.0, 0.0};
 
   double av[4], bv[4];
-  const int nk = namp / BK;
+  const int nk = namp / BK, nk_even = P.odd_e0 / BK;
   load4(arow + lk, av);
   load4(brow + lk, bv);
 #pragma unroll
@@ -183,7 +186,10 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
       load4(arow + k + lk, av);
       load4(brow + k + lk, bv);
     }
-    mfma_stage<true, true>(As[cur], Bs[cur], wm, wn, lane, acc);
+    if (kt < nk_even)
+      mfma_stage<true, true>(As[cur], Bs[cur], wm, wn, lane, acc);
+    else
+      mfma_stage<true, true>(As[cur], Bs[cur], wm, wn, lane, acco);
     if (more) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) As[cur ^ 1][lr * RK + lk + e] = a_ok ? av[e] : 0.0;
@@ -193,27 +199,35 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
     __syncthreads();
   }
 
-  // epilogue: the block potential goes to every member cell of the block.
-  // This lane's two blocks are resolved once for all its rows (rect: first
-  // cell and extent; CSR: member range in bcell .. bnj); a block of more than
-  // kLargeBlock cells only gets its first cell here, launch_large copies it.
-  bool bok[2];
-  int bcell[2] = {0, 0}, bnj[2] = {0, 0}, bnk[2] = {0, 0};
+  // epilogue: a pair's potentials go to every member cell of its blocks,
+  // even + odd sums to the rep block, even - odd to its mirror.  This lane's
+  // two pairs are resolved once for all its rows ([.][0] rep, [.][1] mirror;
+  // rect: first cell and extent; CSR: member range in bcell .. bnj); a block
+  // of more than kLargeBlock cells only gets its first cell here,
+  // launch_large copies it.
+  bool bok[2], bmir[2] = {false, false};
+  int bcell[2][2] = {}, bnj[2][2] = {}, bnk[2][2] = {};
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const int b = n0 + wn * 32 + u * 16 + (lane & 15);
-    bok[u] = b < C.nblocks;
+    const int q = n0 + wn * 32 + u * 16 + (lane & 15);
+    bok[u] = q < C.npair;
     if (!bok[u]) continue;
-    if (C.rect != nullptr) {
-      const auto rect = gmem(reinterpret_cast<const int *>(C.rect));   // (j0, k0, nj, nk) per block
-      bcell[u] = rect[4 * b] * P.nphi + rect[4 * b + 1];
-      bnj[u] = rect[4 * b + 2];
-      bnk[u] = rect[4 * b + 3];
-      if (bnj[u] * bnk[u] > kLargeBlock) bnj[u] = bnk[u] = 1;   // first cell only; launch_large broadcasts
-    } else {
-      bcell[u] = gmem(C.moff)[b];
-      bnj[u] = gmem(C.moff)[b + 1];
-      if (bnj[u] - bcell[u] > kLargeBlock) bnj[u] = bcell[u] + 1;
+    const i2v pr = gmem(reinterpret_cast<const i2v *>(C.pairs))[q];
+    bmir[u] = pr.y != pr.x;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = h ? pr.y : pr.x;
+      if (C.rect != nullptr) {
+        const auto rect = gmem(reinterpret_cast<const int *>(C.rect));   // (j0, k0, nj, nk) per block
+        bcell[u][h] = rect[4 * b] * P.nphi + rect[4 * b + 1];
+        bnj[u][h] = rect[4 * b + 2];
+        bnk[u][h] = rect[4 * b + 3];
+        if (bnj[u][h] * bnk[u][h] > kLargeBlock) bnj[u][h] = bnk[u][h] = 1;   // first cell; launch_large broadcasts
+      } else {
+        bcell[u][h] = gmem(C.moff)[b];
+        bnj[u][h] = gmem(C.moff)[b + 1];
+        if (bnj[u][h] - bcell[u][h] > kLargeBlock) bnj[u][h] = bcell[u][h] + 1;
+      }
     }
   }
   const auto mem = gmem(C.mem);
@@ -227,16 +241,20 @@ __global__ __launch_bounds__(NTHREADS) void k_expand_f64(BatchDev B) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         if (!bok[u]) continue;
-        const double v = acc[t][u][r];
-        if (C.rect != nullptr) {
-          if (bnj[u] == 1 && bnk[u] == 1) {
-            dst[bcell[u]] = v;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1 && !bmir[u]) break;
+          const double v = h ? acc[t][u][r] - acco[t][u][r] : acc[t][u][r] + acco[t][u][r];
+          if (C.rect != nullptr) {
+            if (bnj[u][h] == 1 && bnk[u][h] == 1) {
+              dst[bcell[u][h]] = v;
+            } else {
+              for (int j = 0; j < bnj[u][h]; ++j)
+                for (int k = 0; k < bnk[u][h]; ++k) dst[bcell[u][h] + j * P.nphi + k] = v;
+            }
           } else {
-            for (int j = 0; j < bnj[u]; ++j)
-              for (int k = 0; k < bnk[u]; ++k) dst[bcell[u] + j * P.nphi + k] = v;
+            for (int e = bcell[u][h]; e < bnj[u][h]; ++e) dst[mem[e]] = v;
           }
-        } else {
-          for (int e = bcell[u]; e < bnj[u]; ++e) dst[mem[e]] = v;
         }
       }
     }

@@ -92,23 +92,24 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   }
   const int m0 = mt * TMV, n0 = nt * TN;
   const int M = C.nrows;
-  const int N = EXPAND ? C.nblocks : P.namp;
+  const int N = EXPAND ? C.npair : P.namp_m;
   int kbeg, kend;
   if (EXPAND) {
     kbeg = 0;
-    kend = P.namp;
+    kend = P.namp_e;
   } else {
     kbeg = split * C.kchunk;
-    kend = min(kbeg + C.kchunk, C.nblocks_pad);
+    kend = min(kbeg + C.kchunk, C.npair_pad);
   }
-  // operands, k-slab major with interleaved planes
+  // operands, k-slab major with interleaved planes; a moment tile of odd mode
+  // columns contracts the odd (difference) packed source
   Operand X, Y;
   if (EXPAND) {
     X = {P.cplanes, P.nr};
-    Y = {C.tplanes, C.nblocks_pad};
+    Y = {C.tplanes, C.npair_pad};
   } else {
-    X = {C.ppacks, C.nrows};
-    Y = {C.ttplanes, P.namp};
+    X = {n0 >= P.odd_m0 ? C.ppacks_o : C.ppacks, C.nrows};
+    Y = {C.ttplanes, P.namp_m};
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -125,7 +126,7 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   // Y tile (128 rows) is moved by all threads, chunks t + 256 u; the X tile by
   // the first 2 TMV threads, chunks t + 2 TMV u (u < NP).
   const bool x_loader = tid < 2 * TMV;
-  const int yrow_max = EXPAND ? C.nblocks_pad : P.namp;
+  const int yrow_max = EXPAND ? C.npair_pad : P.namp_m;
   int lx_slot[NP], ly_slot[NP];
   bool x_ok[NP], y_ok[NP];
   size_t x_off[NP], y_off[NP];   // element offsets within a k slab
@@ -143,11 +144,19 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   }
   const size_t x_slab = (size_t)X.rows * 16 * NP, y_slab = (size_t)Y.rows * 16 * NP;
 
-  f16v acc[AT][2];
+  // accumulators: every stage goes to acc; a folded expansion parks its even
+  // mode sums in acco at the parity boundary and sums the odd ones in acc
+  f16v acc[AT][2], acco[EXPAND ? AT : 1][2];
 #pragma unroll
   for (int a = 0; a < AT; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
+#pragma unroll
+  for (int a = 0; a < (EXPAND ? AT : 1); ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acco[a][b] = f16v{};
+  const int kodd = EXPAND ? P.odd_e0 : kend;   // first K of the odd mode columns
+  const bool parked = EXPAND && kodd < kend;   // the K range holds odd columns
 
   // two register sets of staged operands: the loads of stage k+2 are issued
   // before stage k is computed and land in LDS only after stage k+1 is, so
@@ -174,7 +183,7 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
       Ys[(BUF) * CH * TN + ly_slot[u]] = y_ok[u] ? YV[u] : zero;                      \
     }                                                                                \
   }
-  auto compute = [&](int buf) __attribute__((always_inline)) {
+  auto stage = [&](int buf, f16v (&ac)[AT][2]) __attribute__((always_inline)) {
     u4 fa[AT][NP], fb[2][NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -188,7 +197,24 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
 #pragma unroll
       for (int a = 0; a < AT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = S::mfma(fa[a][S::px[q]], fb[b][S::py[q]], acc[a][b]);
+        for (int b = 0; b < 2; ++b) ac[a][b] = S::mfma(fa[a][S::px[q]], fb[b][S::py[q]], ac[a][b]);
+  };
+  // stage kt of this tile (k = kbeg + kt TK); after the last even stage of a
+  // folded expansion the even sums are parked in acco and acc restarts at 0
+  // for the odd stages (a workgroup-uniform branch)
+  auto compute = [&](int buf, int kt) __attribute__((always_inline)) {
+    stage(buf, acc);
+    if constexpr (EXPAND) {
+      if (parked && kbeg + (kt + 1) * TK == kodd) {
+#pragma unroll
+        for (int a = 0; a < AT; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acco[a][b] = acc[a][b];
+            acc[a][b] = f16v{};
+          }
+      }
+    }
   };
 
   const int nk = (kend - kbeg) / TK;
@@ -203,18 +229,18 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   for (; kt + 1 < nk; kt += 2) {
     // even stage kt from LDS 0; register set b holds stage kt+1
     GLOAD(xa, ya, min(kbeg + (kt + 2) * TK, klast));
-    compute(0);
+    compute(0, kt);
     LSTORE(xb, yb, 1);
     __syncthreads();
     // odd stage kt+1 from LDS 1; register set a holds stage kt+2
     GLOAD(xb, yb, min(kbeg + (kt + 3) * TK, klast));
-    compute(1);
+    compute(1, kt + 1);
     if (kt + 2 < nk) LSTORE(xa, ya, 0);
     __syncthreads();
   }
 #undef GLOAD
 #undef LSTORE
-  if (kt < nk) compute(0);   // odd stage count: the last stage sits in LDS 0
+  if (kt < nk) compute(0, kt);   // odd stage count: the last stage sits in LDS 0
 
   // epilogue: undo the row scale in FP64
   const auto rows = gmem(C.rows);
@@ -224,29 +250,36 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   const auto cscale = gmem(P.cscale), coef = gmem(P.coef);
   const auto pscale = gmem(C.pscale);
   const auto part = gmem(reinterpret_cast<float *>(C.partial));
-  // this lane's two expansion blocks, read once for all its rows: l = 0
-  // table column and member cells (rect: first cell and extent; CSR: member
-  // range in bcell .. bnj; a block of more than kLargeBlock cells only gets
-  // its first cell here, launch_large copies it to the rest)
-  bool bok[2] = {false, false};
+  // this lane's two expansion pairs, read once for all its rows: l = 0
+  // kernel and the member cells of both blocks, [0] the rep and [1] the
+  // mirror (rect: first cell and extent; CSR: member range in bcell .. bnj;
+  // a block of more than kLargeBlock cells only gets its first cell here,
+  // launch_large copies it to the rest)
+  bool bok[2] = {false, false}, bmir[2] = {false, false};
   double bt0[2] = {0.0, 0.0};
-  int bcell[2] = {0, 0}, bnj[2] = {0, 0}, bnk[2] = {0, 0};
+  int bcell[2][2] = {}, bnj[2][2] = {}, bnk[2][2] = {};
   if (EXPAND) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int blk = n0 + wn * 64 + b * 32 + (lane & 31);
-      bok[b] = blk < N;
+      const int q = n0 + wn * 64 + b * 32 + (lane & 31);
+      bok[b] = q < N;
       if (!bok[b]) continue;
-      bt0[b] = tcol0[blk];
-      if (C.rect != nullptr) {
-        bcell[b] = rect[4 * blk] * P.nphi + rect[4 * blk + 1];
-        bnj[b] = rect[4 * blk + 2];
-        bnk[b] = rect[4 * blk + 3];
-        if (bnj[b] * bnk[b] > kLargeBlock) bnj[b] = bnk[b] = 1;   // first cell only; launch_large broadcasts
-      } else {
-        bcell[b] = moff[blk];
-        bnj[b] = moff[blk + 1];
-        if (bnj[b] - bcell[b] > kLargeBlock) bnj[b] = bcell[b] + 1;
+      bt0[b] = tcol0[q];
+      const i2v pr = gmem(reinterpret_cast<const i2v *>(C.pairs))[q];
+      bmir[b] = pr.y != pr.x;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int blk = h ? pr.y : pr.x;
+        if (C.rect != nullptr) {
+          bcell[b][h] = rect[4 * blk] * P.nphi + rect[4 * blk + 1];
+          bnj[b][h] = rect[4 * blk + 2];
+          bnk[b][h] = rect[4 * blk + 3];
+          if (bnj[b][h] * bnk[b][h] > kLargeBlock) bnj[b][h] = bnk[b][h] = 1;   // first cell; launch_large broadcasts
+        } else {
+          bcell[b][h] = moff[blk];
+          bnj[b][h] = moff[blk + 1];
+          if (bnj[b][h] - bcell[b][h] > kLargeBlock) bnj[b][h] = bcell[b][h] + 1;
+        }
       }
     }
   }
@@ -264,22 +297,30 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           if (!bok[b]) continue;
-          const double v = c0 * bt0[b] + sc * (double)acc[a][b][r];
-          if (C.rect != nullptr) {
-            if (bnj[b] == 1 && bnk[b] == 1) {
-              dst[bcell[b]] = v;
+          // rep block: even + odd parts; its mirror: even - odd (once parked,
+          // acco holds the even sums and acc the odd ones)
+          const double x0 = (double)acc[a][b][r], x1 = EXPAND ? (double)acco[a][b][r] : 0.0;
+          const double ev = parked ? x1 : x0, od = parked ? x0 : 0.0;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !bmir[b]) break;
+            const double v = c0 * bt0[b] + sc * (h ? ev - od : ev + od);
+            if (C.rect != nullptr) {
+              if (bnj[b][h] == 1 && bnk[b][h] == 1) {
+                dst[bcell[b][h]] = v;
+              } else {
+                for (int j = 0; j < bnj[b][h]; ++j)
+                  for (int k = 0; k < bnk[b][h]; ++k) dst[bcell[b][h] + j * P.nphi + k] = v;
+              }
             } else {
-              for (int j = 0; j < bnj[b]; ++j)
-                for (int k = 0; k < bnk[b]; ++k) dst[bcell[b] + j * P.nphi + k] = v;
+              for (int e = bcell[b][h]; e < bnj[b][h]; ++e) dst[mem[e]] = v;
             }
-          } else {
-            for (int e = bcell[b]; e < bnj[b]; ++e) dst[mem[e]] = v;
           }
         }
       } else {
         // FP32 partial sums (the accumulator type; the row scale is a power of two)
         const float sc = (float)pscale[row];
-        const auto out = part + ((size_t)split * M + row) * P.namp;
+        const auto out = part + ((size_t)split * M + row) * P.namp_m;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const int col = n0 + wn * 64 + b * 32 + (lane & 31);
@@ -290,7 +331,7 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
 }
 
 template <int KIND, bool EXPAND>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_split(BatchDev B) {
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(EXPAND ? 2 : 3))) void k_gemm_split(BatchDev B) {
   constexpr int CH = 2 * Split<KIND>::planes;
   // LDS stage layout: [chunk][row], chunk = 2 plane + k half, with the rows
   // of each chunk rotated within aligned groups of 8 by sig[chunk].  16-byte

@@ -42,7 +42,8 @@ struct ClassDev {
   const int32_t *moff;   // [nblocks+1] CSR offsets of block members
   const int32_t *mem;    // [ncell] member fine-cell index j*nphi+k, ascending per block
   const int4 *rect;      // [nblocks] (j0, k0, nj, nk) when every block is a theta-phi rectangle, else null
-  const int32_t *span0;  // [ceil(nblocks / kPackSpan)] first cell of a packing span of consecutive single cells, else -1
+  const int32_t *span0;  // [ceil(npair / kPackSpan)] first rep cell of a packing span of pairs whose rep blocks
+                         // are single cells at consecutive cells (their mirrors then are the mirror cells), else -1
   const int32_t *lidx;   // [nblocks] index of a large block in the class's large-block list, else -1; null if none
   // theta bands when every block is an nj x nk rectangle at a phi column
   // that is a multiple of nk, uniform within the band: (j0, nj, nk, kind),
@@ -51,18 +52,29 @@ struct ClassDev {
   // for other block maps
   const int4 *bands;
   int32_t nbands;
-  double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, zero padded
-  double *tcol0;         // [nblocks_pad] copy of the table's l = 0 column (contiguous)
-  uint16_t *tplanes;     // [nplanes][nblocks_pad][namp] split planes of table (expansion operand)
-  uint16_t *ttplanes;    // [nplanes][namp][nblocks_pad] split planes of the transposed table (moment operand)
-  double *pack;          // [nrows][nblocks_pad] FP64 packed S*dOmega (FP64 path)
-  uint16_t *ppacks;      // [nplanes][nrows][nblocks_pad] split planes of the packed source
+  // The contractions run over block pairs.  With the mirror fold (PlanDev::
+  // fold) a pair is a block and its mirror image about the equator (theta ->
+  // pi - theta), whose kernels differ only by the sign (-1)^(l+m); a block
+  // that is its own mirror, and every block of an unfolded plan, is a pair
+  // (b, b).  Pairs are ordered by their first block.
+  const int2 *pairs;     // [npair] (rep, mir) block ids
+  int32_t npair, npair_pad;
+  double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, natural mode order, zero padded
+  double *tm, *te;       // FP64 contraction operands over pairs: [npair_pad][namp_m] (moment) and
+                         // [npair_pad][namp_e] (expansion); both the table itself when unfolded
+  double *tcol0;         // [npair_pad] l = 0 kernel of each pair (contiguous)
+  uint16_t *tplanes;     // [nplanes] split planes of te, rows = pairs, k = expansion mode column
+  uint16_t *ttplanes;    // [nplanes] split planes of tm transposed, rows = moment mode column, k = pairs
+  // packed sources over pairs: even = S(rep) + S(mir), odd = S(rep) - S(mir)
+  // (the mirror's own source is left out of a pair (b, b)); odd only folded
+  double *pack, *pack_o;        // [nrows][npair_pad] FP64 (FP64 and FP16 x2 paths)
+  uint16_t *ppacks, *ppacks_o;  // [nplanes] split planes, rows = class rows, k = pairs
   double *pscale;        // [nrows] power-of-two row scales of the packed source
-  double *partial;       // [splits][nrows][namp] split-K partial moments
+  double *partial;       // [splits][nrows][namp_m] split-K partial moments (moment mode columns)
   double *wsum;          // [nblocks_pad] 4 pi G dOmega of each block (sum over its cells)
   double *tsum;          // [namp] sum_b wsum[b] table[b][n], summed over b in order
   int32_t nrows, nblocks, nblocks_pad;
-  int32_t splits, kchunk;             // moment split-K: splits x kchunk >= nblocks_pad
+  int32_t splits, kchunk;             // moment split-K over pairs: splits x kchunk >= npair_pad
   int32_t m_tiles_mom, m_tiles_exp, n_tiles_mom, n_tiles_exp;   // tiles of the contractions
   int32_t wg_mom_begin, wg_exp_begin;  // prefix sums over classes
 };
@@ -83,7 +95,19 @@ struct PlanDev {
   double *rr, *ri;   // [nr][lmax+1] volume-averaged r^l, r^-(l+1)
   double *ang;       // [nr][namp] reduced angular moments
   double *coef;      // [nr][namp] expansion coefficients
-  uint16_t *cplanes; // [nplanes][nr][namp] split planes of coef
+  // Mode columns of the contractions.  Folded: the moment N dimension holds
+  // the even modes (l + m even) padded to odd_m0 (a multiple of the tile
+  // width, so that every output tile has one parity), then the odd modes,
+  // namp_m columns in all; the expansion K dimension holds the even modes
+  // padded to odd_e0 (a multiple of 16), then the odd modes, namp_e in all.
+  // Unfolded: natural order, namp_m = namp_e = odd_m0 = odd_e0 = namp, null maps.
+  int32_t fold;
+  int32_t namp_m, odd_m0, namp_e, odd_e0;
+  const int32_t *pos_m;    // [namp] natural mode -> moment column, -1 past nam (null: identity)
+  const int32_t *perm_m;   // [namp_m] moment column -> natural mode or -1 (null: identity)
+  const int32_t *perm_e;   // [namp_e] expansion column -> natural mode or -1 (null: identity)
+  double *coef_e;    // [nr][namp_e] coefficients in expansion columns (FP64 folded), else coef
+  uint16_t *cplanes; // [nplanes] split planes of coef, rows = shells, k = expansion column
   double *cscale;    // [nr] row scales of coef
   double *mono_part; // [nr][mono_stride] FP64 partial monopole moments (split precisions), or null
   double *max_part;  // [nr][mono_stride] partial row maxima of the packed source (FP16 x2)
@@ -183,6 +207,9 @@ hipError_t launch_fill_value(double *p, size_t n, double v, hipStream_t s);
 hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const GaussRule &g, bool dense,
                          hipStream_t s);
 hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, int kind, hipStream_t s);
+// per-pair tables of the dense paths: the l = 0 kernel of each pair, and for
+// the folded FP64 path the operands tm and te (after launch_tables)
+hipError_t launch_pair_tables(const PlanDev &P, const ClassDev *host_classes, hipStream_t s);
 // solve time, one launch per phase covering every field of B; wgs = total workgroups
 // (prefix[h][nf]); precision = the fields' common precision (0 = FP64)
 hipError_t launch_stamp_reset(const BatchDev &B, hipStream_t s);

@@ -2,12 +2,15 @@
 // shell gets its share of the source, the sum over members of
 // 4 pi G dOmega rho, i.e. dOmega_b S_b with S_b the solid-angle weighted block
 // mean (GenASiS II Sec. 2.1 coarsening blocks; Eq. AngularMomentsDiscrete
-// weights dOmega S).
+// weights dOmega S).  The contractions run over block pairs (a block and its
+// mirror image about the equator on a folded plan, else the block alone), so
+// each pair gets the sum (even modes) and the difference (odd modes) of its
+// two blocks' sources.
 //
-// One thread per block of a shell, PACK_UNROLL blocks per thread spaced
-// PACK_THREADS apart; single-cell blocks (the common case) take a branch-free
-// path whose loads are all issued before any is consumed, so enough bytes are
-// in flight to stream rho at HBM rate.  Output by precision:
+// One thread per pair of a shell, PACK_UNROLL pairs per thread spaced
+// PACK_THREADS apart; runs of single-cell pairs (the common case) take a
+// branch-free path whose loads are all issued before any is consumed, so
+// enough bytes are in flight to stream rho at HBM rate.  Output by precision:
 //   FP64      the packed row in FP64 (operand of the f64 moment contraction);
 //   BF16 x3   the split planes of the deviation from the shell's mean
 //             (below; bfloat16 has the exponent range of FP32, so the row
@@ -27,6 +30,32 @@ namespace {
 constexpr int PACK_THREADS = 256, PACK_UNROLL = 4, PACK_SPAN = PACK_THREADS * PACK_UNROLL;
 static_assert(PACK_SPAN == kPackSpan, "packing span");
 
+// Source sum 4 pi G dOmega rho and weight 4 pi G dOmega of block b (< 0:
+// none) of shell i: a single cell directly, larger blocks from their member
+// list or, past kLargeBlock cells, from the sum launch_large wrote.
+__device__ __forceinline__ void block_sw(const PlanDev &P, const ClassDev &C, int i, int b, const double *w,
+                                         const double *src, double &s, double &wt) {
+  s = 0.0;
+  wt = 0.0;
+  if (b < 0) return;
+  int n;
+  if (C.rect != nullptr) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 r = gmem(reinterpret_cast<const i4 *>(C.rect))[b];   // (j0, k0, nj, nk)
+    if (r.z * r.w == 1) {
+      const int q = r.x * P.nphi + r.y;
+      wt = gmem(w)[q];
+      s = wt * gmem(src)[q];
+      return;
+    }
+    n = r.z * r.w;
+  } else {
+    n = gmem(C.moff)[b + 1] - gmem(C.moff)[b];
+  }
+  s = n > kLargeBlock ? large_source(P, C, i, b) : block_source(C, w, src, P.nphi, b);
+  wt = gmem(C.wsum)[b];
+}
+
 template <int MODE>   // 0 = FP64, kSplitBf16x3, kSplitFp16x2
 __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   __shared__ double red[PACK_THREADS / 64];
@@ -37,12 +66,13 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   const int bx = J.local % P.pack_parts, i = J.local / P.pack_parts;   // (part, shell)
   const double *__restrict__ rho = J.io.rho;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
-  const int b0 = bx * PACK_SPAN + threadIdx.x;
-  if (bx * PACK_SPAN >= C.nblocks) return;   // whole workgroup idle for this class
+  const int q0 = bx * PACK_SPAN + threadIdx.x;   // this thread's first pair
+  if (bx * PACK_SPAN >= C.npair) return;   // whole workgroup idle for this class
   const int row = ld_const(P.shell_row + i);
   const double *__restrict__ src = rho + (size_t)i * P.ncell;
   const double *__restrict__ w = P.weight;
   const auto srcg = gmem(src), wg = gmem(w);
+  const bool fold = P.fold != 0;
   // Split precisions carry only the deviation of the source from c times the
   // block weight, c a per-shell reference density (exact identity, l >= 1):
   //   sum_b P_b T_bn = sum_b (P_b - c W_b) T_bn + c sum_b W_b T_bn,
@@ -66,89 +96,90 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     }
     shift = wsm > 0.0 ? a / wsm : 0.0;   // stored at the end: no store ahead of the loads
   }
-  double s[PACK_UNROLL], wb[PACK_UNROLL];   // block source and block weight
+  // per pair (rep, mir): the even and odd combinations of the two blocks'
+  // sources and weights (the mirror's part left out when mir == rep)
+  double se[PACK_UNROLL], so[PACK_UNROLL], we[PACK_UNROLL], wo[PACK_UNROLL];
   const int run0 = ld_const(C.span0 + bx);
   if (run0 >= 0) {
-    // the span is a run of single-cell blocks at consecutive cells: coalesced
-    // loads, no block descriptors
+    // the span's rep blocks are single cells at consecutive cells and their
+    // mirrors the mirror cells: coalesced loads, no block descriptors
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
-      const int b = b0 + u * PACK_THREADS;
-      const int q = run0 + threadIdx.x + u * PACK_THREADS;
-      wb[u] = (b < C.nblocks) ? wg[q] : 0.0;
-      s[u] = (b < C.nblocks) ? wb[u] * srcg[q] : 0.0;
-    }
-  } else if (C.rect != nullptr) {
-    typedef int i4 __attribute__((ext_vector_type(4)));
-    const auto rect = gmem(reinterpret_cast<const i4 *>(C.rect));   // (j0, k0, nj, nk) per block
-    i4 r[PACK_UNROLL];
-#pragma unroll
-    for (int u = 0; u < PACK_UNROLL; ++u) {
-      const int b = b0 + u * PACK_THREADS;
-      r[u] = (b < C.nblocks) ? rect[b] : i4{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int u = 0; u < PACK_UNROLL; ++u) {
-      const int q = r[u].x * P.nphi + r[u].y;
-      const bool one = r[u].z == 1 && r[u].w == 1;
-      wb[u] = one ? wg[q] : 0.0;
-      s[u] = one ? wb[u] * srcg[q] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < PACK_UNROLL; ++u) {
-      const int b = b0 + u * PACK_THREADS;
-      if (b < C.nblocks && (r[u].z != 1 || r[u].w != 1)) {
-        s[u] = r[u].z * r[u].w > kLargeBlock ? large_source(P, C, i, b) : block_source(C, w, src, P.nphi, b);
-        wb[u] = gmem(C.wsum)[b];
-      }
+      const bool ok = q0 + u * PACK_THREADS < C.npair;
+      const int c = run0 + threadIdx.x + u * PACK_THREADS;
+      const int cm = fold ? (P.ntheta - 1 - c / P.nphi) * P.nphi + c % P.nphi : c;
+      const double wr = ok ? wg[c] : 0.0;
+      const double wm = (ok && cm != c) ? wg[cm] : 0.0;
+      const double sr = wr * srcg[ok ? c : run0], sm = wm * srcg[ok ? cm : run0];
+      se[u] = sr + sm;
+      so[u] = sr - sm;
+      we[u] = wr + wm;
+      wo[u] = wr - wm;
     }
   } else {
-    const auto moff = gmem(C.moff);
+    const auto prs = gmem(reinterpret_cast<const i2v *>(C.pairs));
+    i2v pr[PACK_UNROLL];
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
-      const int b = b0 + u * PACK_THREADS;
-      s[u] = 0.0;
-      if (b < C.nblocks)
-        s[u] = moff[b + 1] - moff[b] > kLargeBlock ? large_source(P, C, i, b) : block_source(C, w, src, P.nphi, b);
-      wb[u] = (b < C.nblocks && MODE != 0) ? gmem(C.wsum)[b] : 0.0;
+      const int q = q0 + u * PACK_THREADS;
+      pr[u] = q < C.npair ? prs[q] : i2v{-1, -1};
+    }
+#pragma unroll
+    for (int u = 0; u < PACK_UNROLL; ++u) {
+      double sr, wr, sm, wm;
+      block_sw(P, C, i, pr[u].x, w, src, sr, wr);
+      block_sw(P, C, i, pr[u].y != pr[u].x ? pr[u].y : -1, w, src, sm, wm);
+      se[u] = sr + sm;
+      so[u] = sr - sm;
+      we[u] = wr + wm;
+      wo[u] = wr - wm;
     }
   }
-  double dev[PACK_UNROLL];
+  double de[PACK_UNROLL], dod[PACK_UNROLL];
 #pragma unroll
-  for (int u = 0; u < PACK_UNROLL; ++u) dev[u] = MODE != 0 ? s[u] - shift * wb[u] : s[u];
+  for (int u = 0; u < PACK_UNROLL; ++u) {
+    de[u] = MODE != 0 ? se[u] - shift * we[u] : se[u];
+    dod[u] = MODE != 0 ? so[u] - shift * wo[u] : so[u];
+  }
   double mono = 0.0, mx = 0.0;
   if (MODE == kSplitBf16x3) {
-    // split into an LDS copy of this workgroup's 64 k-slab groups of 16
-    // blocks, [group][plane][16], then write each group's 96 contiguous bytes
-    __shared__ uint16_t stage[PACK_SPAN / 16][3][16];
+    // split into LDS copies of this workgroup's 64 k-slab groups of 16 pairs,
+    // [group][plane][16], then write each group's 96 contiguous bytes
+    __shared__ uint16_t stage[2][PACK_SPAN / 16][3][16];
 #pragma unroll
     for (int u = 0; u < PACK_UNROLL; ++u) {
-      const int bl = threadIdx.x + u * PACK_THREADS;   // block within this workgroup
-      const int b = b0 + u * PACK_THREADS;
-      split_store<kSplitBf16x3>(b < C.nblocks ? dev[u] : 0.0, &stage[bl >> 4][0][bl & 15], 16);
+      const int ql = threadIdx.x + u * PACK_THREADS;   // pair within this workgroup
+      const bool ok = q0 + u * PACK_THREADS < C.npair;
+      split_store<kSplitBf16x3>(ok ? de[u] : 0.0, &stage[0][ql >> 4][0][ql & 15], 16);
+      if (fold) split_store<kSplitBf16x3>(ok ? dod[u] : 0.0, &stage[1][ql >> 4][0][ql & 15], 16);
     }
     __syncthreads();
     const int g0 = bx * (PACK_SPAN / 16);                        // first k slab of the workgroup
-    const int ngroups = min(PACK_SPAN / 16, C.nblocks_pad / 16 - g0);
+    const int ngroups = min(PACK_SPAN / 16, C.npair_pad / 16 - g0);
     typedef unsigned u4 __attribute__((ext_vector_type(4)));
-    const u4 *st = reinterpret_cast<const u4 *>(&stage[0][0][0]);
-    for (int v = threadIdx.x; v < ngroups * 6; v += PACK_THREADS) {   // 6 x 16 B per group
-      const int g = v / 6, part = v % 6;
-      const auto dst = gmem(reinterpret_cast<u4 *>(C.ppacks + ((size_t)(g0 + g) * C.nrows + row) * 48));
-      dst[part] = st[g * 6 + part];
+    for (int par = 0; par < (fold ? 2 : 1); ++par) {
+      const u4 *st = reinterpret_cast<const u4 *>(&stage[par][0][0][0]);
+      uint16_t *dst0 = par ? C.ppacks_o : C.ppacks;
+      for (int v = threadIdx.x; v < ngroups * 6; v += PACK_THREADS) {   // 6 x 16 B per group
+        const int g = v / 6, part = v % 6;
+        const auto dst = gmem(reinterpret_cast<u4 *>(dst0 + ((size_t)(g0 + g) * C.nrows + row) * 48));
+        dst[part] = st[g * 6 + part];
+      }
     }
   }
 #pragma unroll
   for (int u = 0; u < PACK_UNROLL; ++u) {
-    const int b = b0 + u * PACK_THREADS;
-    // the FP64 row including its zero padding up to nblocks_pad (the padding
-    // lies in the span of the last block: spans are multiples of 16 long)
-    if (MODE != kSplitBf16x3 && b < C.nblocks_pad)
-      gmem(C.pack)[(size_t)row * C.nblocks_pad + b] = b < C.nblocks ? dev[u] : 0.0;
-    if (b >= C.nblocks) continue;
+    const int q = q0 + u * PACK_THREADS;
+    // the FP64 rows including their zero padding up to npair_pad (the padding
+    // lies in the span of the last pair: spans are multiples of 16 long)
+    if (MODE != kSplitBf16x3 && q < C.npair_pad) {
+      gmem(C.pack)[(size_t)row * C.npair_pad + q] = q < C.npair ? de[u] : 0.0;
+      if (fold) gmem(C.pack_o)[(size_t)row * C.npair_pad + q] = q < C.npair ? dod[u] : 0.0;
+    }
+    if (q >= C.npair) continue;
     if (MODE != 0) {
-      mono += s[u] * gmem(C.tcol0)[b];
-      mx = fmax(mx, fabs(dev[u]));
+      mono += se[u] * gmem(C.tcol0)[q];
+      mx = fmax(mx, fmax(fabs(de[u]), fold ? fabs(dod[u]) : 0.0));
     }
   }
   if (MODE != 0) {
@@ -173,15 +204,17 @@ __global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
   const int i = J.local;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   const int row = ld_const(P.shell_row + i);
-  const int nparts = (C.nblocks + PACK_SPAN - 1) / PACK_SPAN;
+  const int nparts = (C.npair + PACK_SPAN - 1) / PACK_SPAN;
   double mx = 0.0;
   for (int q = 0; q < nparts; ++q) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);
   const double scale = row_scale(mx);
   const double inv = 1.0 / scale;   // exact: a power of two
-  const double *__restrict__ prow = C.pack + (size_t)row * C.nblocks_pad;
-  for (int b = threadIdx.x; b < C.nblocks_pad; b += 256)   // zero planes past the last block
-    split_store<kSplitFp16x2>(b < C.nblocks ? prow[b] * inv : 0.0,
-                              C.ppacks + slab_index<kSplitFp16x2>(row, b, C.nrows), 16);
+  for (int par = 0; par < (P.fold ? 2 : 1); ++par) {
+    const double *__restrict__ prow = (par ? C.pack_o : C.pack) + (size_t)row * C.npair_pad;
+    uint16_t *dst = par ? C.ppacks_o : C.ppacks;
+    for (int q = threadIdx.x; q < C.npair_pad; q += 256)   // the row's zero padding included
+      split_store<kSplitFp16x2>(prow[q] * inv, dst + slab_index<kSplitFp16x2>(row, q, C.nrows), 16);
+  }
   if (threadIdx.x == 0) C.pscale[row] = scale;
 }
 

@@ -95,6 +95,10 @@ struct ClassHost {
   std::vector<int32_t> sep_src, sep_avg;   // separable path: blocks on merged rows, blocks with > 1 member
   std::vector<int32_t> large, lidx;        // blocks of more than kLargeBlock cells; index in `large` per block
   std::vector<int32_t> bands;              // theta bands (j0, nj, nk, kind), or empty
+  std::vector<int32_t> mirb;               // mirror block of each block (theta -> pi - theta), or empty
+  std::vector<int32_t> pairs;              // (rep, mir) per pair
+  int npair = 0, npair_pad = 0;
+  size_t off_pairs = 0, off_tm = 0, off_te = 0, off_pack_o = 0, off_ppacks_o = 0;
   size_t off_lidx = 0, off_bands = 0;
   size_t off_sep_src = 0, off_sep_avg = 0;
   size_t off_span0 = 0;
@@ -141,6 +145,11 @@ struct mpole_plan_t {
   size_t off_litems = 0, off_lbase = 0, off_lsum = 0, off_lchunks = 0, off_lpart = 0;
   size_t off_shift = 0, off_tsum_part = 0;
   int nplanes = 0, tm_mom = 64, tm_exp = 64, tile_n = 64, kpad = 16, moment_target = 0;
+  // mirror fold of the dense contractions: mode columns of both contractions
+  bool fold = false;
+  int namp_m = 0, odd_m0 = 0, namp_e = 0, odd_e0 = 0;
+  std::vector<int32_t> pos_m, perm_m, perm_e;
+  size_t off_pos_m = 0, off_perm_m = 0, off_perm_e = 0, off_coef_e = 0;
   int scan_modes = kScanModesWide;   // modes per radial-scan workgroup
   size_t off_plandev = 0, off_prefix = 0;
   size_t solve_off = 0, solve_bytes = 0;        // per-solve region: start in the workspace, size
@@ -186,18 +195,18 @@ constexpr int kMaxSplitChunk = 2048;
 
 void choose_splits(mpole_plan_t &p, int target) {
   double total = 0.0;
-  for (auto &c : p.cls) total += (double)c.rows.size() * c.nblocks_pad;
+  for (auto &c : p.cls) total += (double)c.rows.size() * c.npair_pad;
   for (auto &c : p.cls) {
     const int tiles = c.m_tiles_mom * c.n_tiles_mom;
-    const double share = total > 0 ? target * (double)c.rows.size() * c.nblocks_pad / total : 1.0;
+    const double share = total > 0 ? target * (double)c.rows.size() * c.npair_pad / total : 1.0;
     int s = (int)std::lround(share / std::max(tiles, 1));
     // FP32-accumulated contractions: no split longer than kMaxSplitChunk
-    // blocks, so the rounding of one accumulator chain stays bounded; the
+    // pairs, so the rounding of one accumulator chain stays bounded; the
     // partials are summed in FP64
-    if (p.precision != MPOLE_FP64) s = std::max(s, (c.nblocks_pad + kMaxSplitChunk - 1) / kMaxSplitChunk);
-    s = std::max(1, std::min(s, c.nblocks_pad / p.kpad));
-    c.kchunk = round_up((c.nblocks_pad + s - 1) / s, p.kpad);
-    c.splits = (c.nblocks_pad + c.kchunk - 1) / c.kchunk;
+    if (p.precision != MPOLE_FP64) s = std::max(s, (c.npair_pad + kMaxSplitChunk - 1) / kMaxSplitChunk);
+    s = std::max(1, std::min(s, c.npair_pad / p.kpad));
+    c.kchunk = round_up((c.npair_pad + s - 1) / s, p.kpad);
+    c.splits = (c.npair_pad + c.kchunk - 1) / c.kchunk;
   }
 }
 
@@ -248,6 +257,10 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   p->sep = m->precision == MPOLE_FP64_SEPARABLE || m->precision == MPOLE_BF16X3_SEPARABLE;
   p->sep_bf16 = m->precision == MPOLE_BF16X3_SEPARABLE;
   p->tpad = round_up(2 * m->lmax + 1, 16);
+  // theta edges symmetric about the equator (the mirror fold's first condition)
+  bool theta_sym = true;
+  for (int j = 0; j <= m->ntheta && theta_sym; ++j)
+    theta_sym = std::fabs(m->theta_edges[j] + m->theta_edges[m->ntheta - j] - kPi) <= 1e-13 * kPi;
   // output tiles of the contraction kernels: 64 x 64 (f64 MFMA); 128 x 128
   // (split; the height may be tuned to 64)
   p->tm_mom = p->tm_exp = p->nplanes ? 128 : 64;
@@ -341,20 +354,18 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       }
       if (!ok) C.bands.clear();
     }
-    // packing spans whose blocks are single cells at consecutive cell indices:
-    // span0[s] = cell of the span's first block, else -1
-    const int nspan = (nb + kPackSpan - 1) / kPackSpan;
-    C.span0.assign(nspan, -1);
-    for (int sp = 0; sp < nspan; ++sp) {
-      const int bb = sp * kPackSpan, be = std::min(nb, bb + kPackSpan);
-      const int first = C.mem[C.moff[bb]];
-      bool affine = true;
-      for (int b = bb; b < be && affine; ++b)
-        affine = C.moff[b + 1] - C.moff[b] == 1 && C.mem[C.moff[b]] == first + (b - bb);
-      if (affine) C.span0[sp] = first;
+    // mirror image of every block about the equator (row j -> ntheta-1-j),
+    // when the map is symmetric: the mirror cells of a block's members are
+    // exactly the members of one block
+    C.mirb.clear();
+    if (theta_sym) {
+      C.mirb.assign(nb, -1);
+      auto mcell = [&](int q) { return (p->nt - 1 - q / p->np) * p->np + q % p->np; };
+      for (int b = 0; b < nb; ++b) C.mirb[b] = id[mcell(C.mem[C.moff[b]])];
+      bool sym = true;
+      for (int q = 0; q < p->ncell && sym; ++q) sym = id[mcell(q)] == C.mirb[id[q]];
+      if (!sym) C.mirb.clear();
     }
-    C.n_tiles_mom = (p->namp + p->tile_n - 1) / p->tile_n;
-    C.n_tiles_exp = (C.nblocks + p->tile_n - 1) / p->tile_n;
     // blocks too large for one thread: a workgroup each (launch_large)
     C.large.clear();
     for (int b = 0; b < nb; ++b)
@@ -364,6 +375,71 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       C.lidx.assign(nb, -1);
       for (size_t l = 0; l < C.large.size(); ++l) C.lidx[C.large[l]] = (int32_t)l;
     }
+  }
+  // the mirror fold: dense precisions, every class symmetric (MPOLE_FOLD=0
+  // turns it off, for comparisons)
+  p->fold = !p->sep && theta_sym;
+  for (const auto &C : p->cls) p->fold = p->fold && !C.mirb.empty();
+  if (const char *env = std::getenv("MPOLE_FOLD")) p->fold = p->fold && std::atoi(env) != 0;
+  for (int c = 0; c < p->ncls; ++c) {
+    ClassHost &C = p->cls[c];
+    C.pairs.clear();
+    for (int b = 0; b < C.nblocks; ++b) {
+      const int mb = p->fold ? C.mirb[b] : b;
+      if (mb >= b) C.pairs.insert(C.pairs.end(), {b, mb});
+    }
+    C.npair = (int)(C.pairs.size() / 2);
+    C.npair_pad = round_up(C.npair, p->kpad);
+    // packing spans of pairs whose rep blocks are single cells at consecutive
+    // cell indices: span0[s] = cell of the span's first rep, else -1 (their
+    // mirror blocks are then the single mirror cells)
+    const int nspan = (C.npair + kPackSpan - 1) / kPackSpan;
+    C.span0.assign(nspan, -1);
+    for (int sp = 0; sp < nspan; ++sp) {
+      const int qb = sp * kPackSpan, qe = std::min(C.npair, qb + kPackSpan);
+      const int first = C.mem[C.moff[C.pairs[2 * qb]]];
+      bool affine = true;
+      for (int q = qb; q < qe && affine; ++q) {
+        const int b = C.pairs[2 * q], mb = C.pairs[2 * q + 1];
+        affine = C.moff[b + 1] - C.moff[b] == 1 && C.mem[C.moff[b]] == first + (q - qb) &&
+                 C.moff[mb + 1] - C.moff[mb] == 1;
+      }
+      if (affine) C.span0[sp] = first;
+    }
+  }
+  // mode columns: folded, even parity (l + m) first, then odd
+  p->pos_m.clear();
+  p->perm_m.clear();
+  p->perm_e.clear();
+  if (p->fold) {
+    std::vector<int32_t> ev, od;
+    for (int l = 0; l <= p->L; ++l)
+      for (int d = 0; d <= 2 * l; ++d) {
+        const int mm = (d + 1) / 2;
+        ((l + mm) % 2 == 0 ? ev : od).push_back(l * l + d);
+      }
+    p->odd_m0 = round_up((int)ev.size(), p->tile_n);
+    p->namp_m = p->odd_m0 + round_up((int)od.size(), p->kpad);
+    p->odd_e0 = round_up((int)ev.size(), p->kpad);
+    p->namp_e = p->odd_e0 + round_up((int)od.size(), p->kpad);
+    p->perm_m.assign(p->namp_m, -1);
+    p->perm_e.assign(p->namp_e, -1);
+    p->pos_m.assign(p->namp, -1);
+    for (size_t t = 0; t < ev.size(); ++t) {
+      p->perm_m[t] = p->perm_e[t] = ev[t];
+      p->pos_m[ev[t]] = (int32_t)t;
+    }
+    for (size_t t = 0; t < od.size(); ++t) {
+      p->perm_m[p->odd_m0 + t] = od[t];
+      p->perm_e[p->odd_e0 + t] = od[t];
+      p->pos_m[od[t]] = (int32_t)(p->odd_m0 + t);
+    }
+  } else {
+    p->namp_m = p->odd_m0 = p->namp_e = p->odd_e0 = p->namp;
+  }
+  for (auto &C : p->cls) {
+    C.n_tiles_mom = (p->namp_m + p->tile_n - 1) / p->tile_n;
+    C.n_tiles_exp = (C.npair + p->tile_n - 1) / p->tile_n;
   }
   p->litems.clear();
   p->lbase.assign(p->nr + 1, 0);
@@ -512,11 +588,16 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->off_coef = stake(sizeof(double) * (size_t)p->nr * p->namp);
   p->off_edge_r = stake(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
   p->off_edge_i = stake(sizeof(double) * (size_t)(p->nr + 1) * p->namp);
-  p->off_cplanes = stake(sizeof(uint16_t) * (size_t)p->nplanes * p->nr * p->namp);
+  p->off_cplanes = stake(sizeof(uint16_t) * (size_t)p->nplanes * p->nr * p->namp_e);
+  // FP64 folded expansion: coefficients in expansion columns
+  p->off_coef_e = stake(p->fold && p->nplanes == 0 ? sizeof(double) * (size_t)p->nr * p->namp_e : 0);
+  p->off_pos_m = take(sizeof(int32_t) * p->pos_m.size());
+  p->off_perm_m = take(sizeof(int32_t) * p->perm_m.size());
+  p->off_perm_e = take(sizeof(int32_t) * p->perm_e.size());
   p->off_cscale = stake(sizeof(double) * (size_t)p->nr);
   {
     int maxb = 0;
-    for (auto &C : p->cls) maxb = std::max(maxb, C.nblocks);
+    for (auto &C : p->cls) maxb = std::max(maxb, C.npair);
     p->mono_stride = (maxb + kPackSpan - 1) / kPackSpan;
   }
   p->off_mono = stake(sizeof(double) * (size_t)p->nr * p->mono_stride);
@@ -539,17 +620,25 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_bands = take(sizeof(int32_t) * C.bands.size());
     const size_t dense = p->sep ? 0 : 1;   // the separable path has no block x mode tables
     C.off_table = take(dense * sizeof(double) * (size_t)C.nblocks_pad * p->namp);
-    C.off_tcol0 = take(dense * sizeof(double) * (size_t)C.nblocks_pad);
+    C.off_pairs = take(sizeof(int32_t) * C.pairs.size());
+    // FP64 folded operands over pairs (unfolded: the table itself)
+    const size_t f64fold = (dense && p->fold && p->nplanes == 0) ? 1 : 0;
+    C.off_tm = take(f64fold * sizeof(double) * (size_t)C.npair_pad * p->namp_m);
+    C.off_te = take(f64fold * sizeof(double) * (size_t)C.npair_pad * p->namp_e);
+    C.off_tcol0 = take(dense * sizeof(double) * (size_t)C.npair_pad);
     C.off_wsum = take(sizeof(double) * (size_t)C.nblocks_pad);
     C.off_tsum = take(dense * sizeof(double) * (size_t)p->namp);
-    C.off_pack = stake(dense * sizeof(double) * nrows * C.nblocks_pad);
+    const size_t odd = p->fold ? 1 : 0;
+    C.off_pack = stake(dense * sizeof(double) * nrows * C.npair_pad);
+    C.off_pack_o = stake(dense * odd * sizeof(double) * nrows * C.npair_pad);
     // split-K partials: FP64 for the f64 kernel, FP32 (the accumulator type) for split precisions
-    C.off_partial = stake(dense * (p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp);
+    C.off_partial = stake(dense * (p->nplanes ? sizeof(float) : sizeof(double)) * (size_t)C.splits * nrows * p->namp_m);
     C.off_sep_src = take(sizeof(int32_t) * C.sep_src.size());
     C.off_sep_avg = take(sizeof(int32_t) * C.sep_avg.size());
-    C.off_tplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
-    C.off_ttplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.nblocks_pad * p->namp);
-    C.off_ppacks = stake(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.nblocks_pad);
+    C.off_tplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.npair_pad * p->namp_e);
+    C.off_ttplanes = take(sizeof(uint16_t) * (size_t)p->nplanes * C.npair_pad * p->namp_m);
+    C.off_ppacks = stake(sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.npair_pad);
+    C.off_ppacks_o = stake(odd * sizeof(uint16_t) * (size_t)p->nplanes * nrows * C.npair_pad);
     C.off_pscale = stake(sizeof(double) * std::max<size_t>(nrows, 1));
   }
   if (p->sep) {
@@ -639,6 +728,8 @@ size_t mpole_plan_workspace_bytes(mpole_plan p) { return p ? p->ws_bytes : 0; }
 
 int mpole_plan_nmodes(mpole_plan p) { return p ? p->nam : 0; }
 
+int mpole_plan_folded(mpole_plan p) { return p && p->fold ? 1 : 0; }
+
 }  // extern "C"
 
 namespace {
@@ -650,7 +741,7 @@ int phase_wgs_host(const mpole_plan_t *p, int h) {
     case PH_MOMENT: return p->wg_mom;
     case PH_REDUCE: return (p->namp + 255) / 256 * p->nr;
     case PH_SCAN: return p->namp / p->scan_modes;
-    case PH_COEF: return p->nplanes ? p->nr : 0;
+    case PH_COEF: return (p->nplanes || (p->fold && !p->sep)) ? p->nr : 0;
     case PH_EXPAND: return p->wg_exp;
   }
   return 0;
@@ -693,6 +784,15 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
   D.ri = (double *)(ws + p->off_ri);
   D.ang = (double *)(sv + p->off_ang);
   D.coef = (double *)(sv + p->off_coef);
+  D.fold = p->fold ? 1 : 0;
+  D.namp_m = p->namp_m;
+  D.odd_m0 = p->odd_m0;
+  D.namp_e = p->namp_e;
+  D.odd_e0 = p->odd_e0;
+  D.pos_m = p->fold ? (const int32_t *)(ws + p->off_pos_m) : nullptr;
+  D.perm_m = p->fold ? (const int32_t *)(ws + p->off_perm_m) : nullptr;
+  D.perm_e = p->fold ? (const int32_t *)(ws + p->off_perm_e) : nullptr;
+  D.coef_e = (p->fold && p->nplanes == 0) ? (double *)(sv + p->off_coef_e) : D.coef;
   D.edge_r = (double *)(sv + p->off_edge_r);
   D.edge_i = (double *)(sv + p->off_edge_i);
   D.cplanes = (uint16_t *)(sv + p->off_cplanes);
@@ -723,14 +823,22 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
     C.nbands = (int32_t)(H.bands.size() / 4);
     D.max_bands = std::max(D.max_bands, C.nbands);
     C.table = (double *)(ws + H.off_table);
+    C.pairs = (const int2 *)(ws + H.off_pairs);
+    C.npair = H.npair;
+    C.npair_pad = H.npair_pad;
+    const bool f64fold = p->fold && p->nplanes == 0;
+    C.tm = f64fold ? (double *)(ws + H.off_tm) : C.table;
+    C.te = f64fold ? (double *)(ws + H.off_te) : C.table;
     C.tcol0 = (double *)(ws + H.off_tcol0);
     C.wsum = (double *)(ws + H.off_wsum);
     C.tsum = (double *)(ws + H.off_tsum);
     C.pack = (double *)(sv + H.off_pack);
+    C.pack_o = p->fold ? (double *)(sv + H.off_pack_o) : nullptr;
     C.partial = (double *)(sv + H.off_partial);
     C.tplanes = (uint16_t *)(ws + H.off_tplanes);
     C.ttplanes = (uint16_t *)(ws + H.off_ttplanes);
     C.ppacks = (uint16_t *)(sv + H.off_ppacks);
+    C.ppacks_o = p->fold ? (uint16_t *)(sv + H.off_ppacks_o) : nullptr;
     C.pscale = (double *)(sv + H.off_pscale);
     C.nrows = (int)H.rows.size();
     C.nblocks = H.nblocks;
@@ -837,7 +945,11 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     if (e == hipSuccess) e = upload(ws, H.off_span0, H.span0.data(), sizeof(int32_t) * H.span0.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_lidx, H.lidx.data(), sizeof(int32_t) * H.lidx.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_bands, H.bands.data(), sizeof(int32_t) * H.bands.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_pairs, H.pairs.data(), sizeof(int32_t) * H.pairs.size(), s);
   }
+  if (e == hipSuccess) e = upload(ws, p->off_pos_m, p->pos_m.data(), sizeof(int32_t) * p->pos_m.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_perm_m, p->perm_m.data(), sizeof(int32_t) * p->perm_m.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_perm_e, p->perm_e.data(), sizeof(int32_t) * p->perm_e.size(), s);
   if (e == hipSuccess) e = upload(ws, p->off_litems, p->litems.data(), sizeof(int32_t) * p->litems.size(), s);
   if (e == hipSuccess) e = upload(ws, p->off_lbase, p->lbase.data(), sizeof(int32_t) * p->lbase.size(), s);
   if (e == hipSuccess) e = upload(ws, p->off_lchunks, p->lchunks.data(), sizeof(int32_t) * p->lchunks.size(), s);
@@ -863,6 +975,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     if (e == hipSuccess) e = upload(ws, p->off_scls, p->scls.data(), sizeof(SepClass) * p->scls.size(), s);
   }
   if (e == hipSuccess) e = launch_tables(D, p->cdev.data(), p->rule, !p->sep, s);
+  if (e == hipSuccess && !p->sep) e = launch_pair_tables(D, p->cdev.data(), s);
   if (e == hipSuccess && p->sep) e = launch_sep_tables(D, p->sdev, s);
   if (e == hipSuccess && p->sep_bf16) e = launch_sep_split_tables(D, p->sdev, s);
   if (e == hipSuccess && p->nplanes) e = launch_split_tables(D, p->cdev.data(), p->precision, s);
@@ -906,7 +1019,7 @@ hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, int scan_
   if (e == hipSuccess) e = timed(MPOLE_PHASE_MOMENT, [&] { return launch_moment(B, k, wgs[PH_MOMENT], s); });
   if (e == hipSuccess) e = timed(MPOLE_PHASE_REDUCE, [&] { return launch_reduce(B, wgs[PH_REDUCE], s); });
   if (e == hipSuccess) e = timed(MPOLE_PHASE_SCAN, [&] { return launch_scan(B, wgs[PH_SCAN], scan_modes, s); });
-  if (e == hipSuccess && phi && k != 0)
+  if (e == hipSuccess && phi && wgs[PH_COEF] > 0)
     e = timed(MPOLE_PHASE_SPLIT, [&] { return launch_split_coef(B, k, wgs[PH_COEF], s); });
   if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] {
     hipError_t r = launch_expand(B, k, wgs[PH_EXPAND], s);
@@ -1163,7 +1276,7 @@ void batch_layout(mpole_batch_t *b, const mpole_tuning *tunings) {
   for (int f = 0; f < nf; ++f) {
     const mpole_plan_t *p = b->plans[f];
     double w = 0.0;
-    for (const auto &C : p->cls) w += (double)C.rows.size() * C.nblocks_pad * p->namp;
+    for (const auto &C : p->cls) w += (double)C.rows.size() * C.npair_pad * p->namp_m;
     work[f] = w;
     total += w;
   }

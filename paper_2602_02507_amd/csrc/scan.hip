@@ -34,17 +34,21 @@ __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
   if (n >= P.namp) return;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   const int row = ld_const(P.shell_row + i);
-  const size_t off = (size_t)row * P.namp + n;
-  const size_t stride = (size_t)C.nrows * P.namp;
+  // the partials hold moment mode columns: natural mode n sits in column
+  // pos_m[n] (padding modes past nam have none and sum to 0)
+  const int col = P.pos_m ? gmem(P.pos_m)[n] : n;
+  const size_t off = (size_t)row * P.namp_m + max(col, 0);
+  const size_t stride = (size_t)C.nrows * P.namp_m;
   double s = 0.0;
-  if (P.nplanes == 0) {
+  if (col < 0) {
+  } else if (P.nplanes == 0) {
     const auto src = gmem(C.partial) + off;   // FP64 partials
 #pragma unroll 8
     for (int q = 0; q < C.splits; ++q) s += src[q * stride];
   } else if (n == 0) {
     // split precisions: the monopole moment, summed in FP64 by the packing
     // workgroups of this shell, in workgroup order
-    const int nparts = (C.nblocks + kPackSpan - 1) / kPackSpan;
+    const int nparts = (C.npair + kPackSpan - 1) / kPackSpan;
     for (int q = 0; q < nparts; ++q) s += gmem(P.mono_part)[(size_t)i * P.mono_stride + q];
   } else {
     const auto src = gmem(reinterpret_cast<const float *>(C.partial)) + off;   // FP32 partials

@@ -4,21 +4,31 @@
 // transposed moment operand [b/16][n][plane][b%16]; the expansion
 // coefficients are split per solve with one power-of-two scale per shell
 // (the packed source is split by the packing kernel).
+#include <algorithm>
+
 #include "device_util.h"
 #include "split_util.h"
 
 namespace mpole {
 namespace {
 
+// The split operands over pairs: expansion rows = pairs, k = expansion mode
+// column; moment rows = moment mode column, k = pairs (pair_kernel gives the
+// pair's kernel of a natural mode, 0 for padding).
 template <int KIND>
-__global__ __launch_bounds__(256) void k_split_tables(ClassDev C, int namp) {
+__global__ __launch_bounds__(256) void k_split_tables(PlanDev P, ClassDev C) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long n_el = (long)C.nblocks_pad * namp;
-  if (t >= n_el) return;
-  const int b = (int)(t / namp), n = (int)(t % namp);
-  const double x = C.table[t];
-  split_store<KIND>(x, C.tplanes + slab_index<KIND>(b, n, C.nblocks_pad), 16);   // expansion: rows b, k = n
-  split_store<KIND>(x, C.ttplanes + slab_index<KIND>(n, b, namp), 16);           // moment: rows n, k = b
+  const long ne = (long)C.npair_pad * P.namp_e, nm = (long)C.npair_pad * P.namp_m;
+  if (t < ne) {
+    const int q = (int)(t / P.namp_e), col = (int)(t % P.namp_e);
+    const int n = P.perm_e ? P.perm_e[col] : col;
+    split_store<KIND>(pair_kernel(P, C, q, n), C.tplanes + slab_index<KIND>(q, col, C.npair_pad), 16);
+  }
+  if (t < nm) {
+    const int q = (int)(t / P.namp_m), col = (int)(t % P.namp_m);
+    const int n = P.perm_m ? P.perm_m[col] : col;
+    split_store<KIND>(pair_kernel(P, C, q, n), C.ttplanes + slab_index<KIND>(col, q, P.namp_m), 16);
+  }
 }
 
 // One workgroup per shell: scale and split the expansion coefficients.
@@ -33,10 +43,25 @@ __global__ __launch_bounds__(256) void k_split_coef(BatchDev B) {
   for (int n = threadIdx.x + 1; n < P.nam; n += 256) mx = fmax(mx, fabs(c[n]));
   const double scale = row_scale(block_max(mx, red));
   const double inv = 1.0 / scale;
-  // the l = 0 term is added in FP64 by the expansion epilogue
-  for (int n = threadIdx.x; n < P.namp; n += 256)
-    split_store<KIND>((n > 0 && n < P.nam) ? c[n] * inv : 0.0, P.cplanes + slab_index<KIND>(i, n, P.nr), 16);
+  // expansion mode columns; the l = 0 term is added in FP64 by the expansion
+  // epilogue
+  for (int col = threadIdx.x; col < P.namp_e; col += 256) {
+    const int n = P.perm_e ? P.perm_e[col] : col;
+    split_store<KIND>((n > 0 && n < P.nam) ? c[n] * inv : 0.0, P.cplanes + slab_index<KIND>(i, col, P.nr), 16);
+  }
   if (threadIdx.x == 0) P.cscale[i] = scale;
+}
+
+// Folded FP64: the coefficients of one shell in expansion mode columns.
+__global__ __launch_bounds__(256) void k_perm_coef(BatchDev B) {
+  const Job J = job_of(B, PH_COEF, blockIdx.x);
+  const PlanDev &P = J.P;
+  const int i = J.local;
+  const double *__restrict__ c = P.coef + (size_t)i * P.namp;
+  for (int col = threadIdx.x; col < P.namp_e; col += 256) {
+    const int n = P.perm_e[col];
+    P.coef_e[(size_t)i * P.namp_e + col] = (n >= 0 && n < P.nam) ? c[n] : 0.0;
+  }
 }
 
 }  // namespace
@@ -44,12 +69,12 @@ __global__ __launch_bounds__(256) void k_split_coef(BatchDev B) {
 hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, int kind, hipStream_t s) {
   for (int c = 0; c < P.nclasses; ++c) {
     const ClassDev &C = host_classes[c];
-    const long n = (long)C.nblocks_pad * P.namp;
+    const long n = (long)C.npair_pad * std::max(P.namp_m, P.namp_e);
     const dim3 g((unsigned)((n + 255) / 256));
     if (kind == kSplitBf16x3)
-      hipLaunchKernelGGL(k_split_tables<kSplitBf16x3>, g, dim3(256), 0, s, C, P.namp);
+      hipLaunchKernelGGL(k_split_tables<kSplitBf16x3>, g, dim3(256), 0, s, P, C);
     else
-      hipLaunchKernelGGL(k_split_tables<kSplitFp16x2>, g, dim3(256), 0, s, C, P.namp);
+      hipLaunchKernelGGL(k_split_tables<kSplitFp16x2>, g, dim3(256), 0, s, P, C);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -57,8 +82,10 @@ hipError_t launch_split_tables(const PlanDev &P, const ClassDev *host_classes, i
 }
 
 hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStream_t s) {
-  if (wgs <= 0 || precision == 0) return hipSuccess;
-  if (precision == kSplitBf16x3)
+  if (wgs <= 0) return hipSuccess;
+  if (precision == 0)
+    hipLaunchKernelGGL(k_perm_coef, dim3(wgs), dim3(256), 0, s, B);
+  else if (precision == kSplitBf16x3)
     hipLaunchKernelGGL(k_split_coef<kSplitBf16x3>, dim3(wgs), dim3(256), 0, s, B);
   else
     hipLaunchKernelGGL(k_split_coef<kSplitFp16x2>, dim3(wgs), dim3(256), 0, s, B);

@@ -118,7 +118,23 @@ __global__ void k_block_table(PlanDev P, ClassDev C) {
     v = num / den;
   }
   C.table[t] = v;
-  if (n == 0) C.tcol0[b] = v;
+}
+
+// Per pair q: tcol0[q] (l = 0 kernel) and, folded FP64, tm[q][column] and
+// te[q][column] over the moment and expansion mode columns.
+__global__ void k_pair_tables(PlanDev P, ClassDev C) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nm = (long)C.npair_pad * P.namp_m, ne = (long)C.npair_pad * P.namp_e;
+  if (t < C.npair_pad) C.tcol0[t] = pair_kernel(P, C, (int)t, 0);
+  if (!P.fold || P.nplanes != 0) return;
+  if (t < nm) {
+    const int q = (int)(t / P.namp_m), col = (int)(t % P.namp_m);
+    C.tm[t] = pair_kernel(P, C, q, P.perm_m[col]);
+  }
+  if (t < ne) {
+    const int q = (int)(t / P.namp_e), col = (int)(t % P.namp_e);
+    C.te[t] = pair_kernel(P, C, q, P.perm_e[col]);
+  }
 }
 
 // 4 pi G dOmega of each block: the cell weights of its members, in CSR order.
@@ -233,6 +249,17 @@ hipError_t launch_tables(const PlanDev &P, const ClassDev *host_classes, const G
       hipLaunchKernelGGL(k_tsum_final, dim3(grid_for(P.namp, 256)), dim3(256), 0, s, P, C);
     }
     e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_pair_tables(const PlanDev &P, const ClassDev *host_classes, hipStream_t s) {
+  for (int c = 0; c < P.nclasses; ++c) {
+    const ClassDev &C = host_classes[c];
+    const long n = (long)C.npair_pad * std::max(std::max(P.namp_m, P.namp_e), 1);
+    hipLaunchKernelGGL(k_pair_tables, dim3(grid_for(n, 256)), dim3(256), 0, s, P, C);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

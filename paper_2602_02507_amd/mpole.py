@@ -22,7 +22,7 @@ STATUS = {0: "MPOLE_OK", 1: "MPOLE_ERR_INVALID", 2: "MPOLE_ERR_RANGE", 3: "MPOLE
 
 # every entry point include/mpole.h declares
 EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_plan_workspace_bytes",
-           "mpole_plan_nmodes", "mpole_plan_bind", "mpole_solve", "mpole_solve_static", "mpole_plan_copy_table",
+           "mpole_plan_nmodes", "mpole_plan_folded", "mpole_plan_bind", "mpole_solve", "mpole_solve_static", "mpole_plan_copy_table",
            "mpole_plan_set_timing", "mpole_plan_phase_ms", "mpole_plan_work", "mpole_gradient", "mpole_gravity_sources", "mpole_coarsen",
            "mpole_genasis_shape", "mpole_genasis_build", "mpole_plan_tune",
            "mpole_plan_get_tuning", "mpole_plan_configure", "mpole_plan_moment_wgs", "mpole_plan_destroy",
@@ -98,6 +98,7 @@ def lib():
         L.mpole_plan_workspace_bytes.argtypes = [vp]
         L.mpole_plan_workspace_bytes.restype = sz
         L.mpole_plan_nmodes.argtypes = [vp]
+        L.mpole_plan_folded.argtypes = [vp]
         L.mpole_plan_bind.argtypes = [vp, vp, sz, vp]
         L.mpole_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.mpole_solve_static.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -198,6 +199,7 @@ class HostPlan:
         _check(lib().mpole_plan_create(ctypes.byref(m), ctypes.byref(h)))
         self.handle = h
         self.nmodes = lib().mpole_plan_nmodes(h)
+        self.folded = bool(lib().mpole_plan_folded(h))
         if moment_wgs:
             _check(lib().mpole_plan_configure(h, int(moment_wgs)))
         if tuning is not None:

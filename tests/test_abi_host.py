@@ -116,16 +116,49 @@ def test_tuning_knobs_validated_and_reported():
     assert q.tuning()["moment_wgs"] == 2048
 
 
-def test_split_chunk_cap_bounds_accumulation_chains():
+def test_split_chunk_cap_bounds_accumulation_chains(monkeypatch):
     # one workgroup requested: the split precisions still split K into chunks of
-    # at most 2048 blocks (FP32 accumulators), FP64 does not
+    # at most 2048 pairs (FP32 accumulators), FP64 does not
     m = wl.production_mesh(16)
     outer_blocks = 128 * 256 - 16 * 256 + 16 * 256 // 4   # outer class: 8 polar rows per pole merged 1x4 in phi
+    ru = lambda x, k: -(-x // k) * k
+    # folded (the production mesh is mirror-symmetric): pairs of blocks, and
+    # moment columns = even modes padded to the tile width + odd modes
     b = mpole.HostPlan.from_mesh(m, precision="bf16x3", tuning={"moment_wgs": 1})
     f = mpole.HostPlan.from_mesh(m, precision="fp64", tuning={"moment_wgs": 1})
+    assert b.folded and f.folded
+    n_even, n_odd = 153, 136                                # l + m even / odd for lmax 16
+    n_tiles = -(-(ru(n_even, 128) + ru(n_odd, 16)) // 128)
+    assert b.moment_wgs >= 4 * n_tiles * -(-(outer_blocks // 2) // 2048)
+    n_tiles64 = -(-(ru(n_even, 64) + ru(n_odd, 16)) // 64)
+    assert f.moment_wgs == -(-480 // 64) * n_tiles64 + 1 * n_tiles64   # FP64: one split per 64 x 64 tile
+    # unfolded: blocks and natural mode order
+    monkeypatch.setenv("MPOLE_FOLD", "0")
+    b = mpole.HostPlan.from_mesh(m, precision="bf16x3", tuning={"moment_wgs": 1})
+    f = mpole.HostPlan.from_mesh(m, precision="fp64", tuning={"moment_wgs": 1})
+    assert not b.folded and not f.folded
     n_tiles = (289 + 127) // 128
     assert b.moment_wgs >= 4 * n_tiles * -(-outer_blocks // 2048)
-    assert f.moment_wgs == -(-480 // 64) * 5 + 1 * 5   # FP64: one split per 64 x 64 tile
+    assert f.moment_wgs == -(-480 // 64) * 5 + 1 * 5
+
+
+def test_fold_detection():
+    """The mirror fold needs theta edges symmetric about the equator and a
+    block map that maps onto itself under theta -> pi - theta (blocks that
+    straddle the equator are their own mirrors); dense precisions only."""
+    prod = wl.production_mesh(8, nr=40, ntheta=36, nphi=72)   # 4 x 4 blocks straddle the equator (rows 16-19)
+    prod.shell_class, prod.class_block = wl.production_merge(40, 36, 72, inner_shells=8, polar_rows=4)
+    assert mpole.HostPlan.from_mesh(prod, precision="bf16x3").folded
+    odd = wl.production_mesh(6, nr=12, ntheta=33, nphi=16, merged=False)   # equator row is its own mirror
+    assert mpole.HostPlan.from_mesh(odd).folded
+    assert not mpole.HostPlan.from_mesh(odd, precision="fp64sep").folded
+    assert not mpole.HostPlan.from_mesh(wl.random_mesh(3, 12, 8, 16, 4)).folded   # jittered theta edges
+    asym = wl.production_mesh(6, nr=12, ntheta=8, nphi=16, merged=False)
+    cb = np.arange(8 * 16, dtype=np.int32)
+    cb[16:18] = 16                  # a 1 x 2 block in row 1 whose mirror row (6) stays single cells
+    cb = np.unique(cb, return_inverse=True)[1].astype(np.int32)
+    asym.shell_class, asym.class_block = np.zeros(12, np.int32), cb[None, :]
+    assert not mpole.HostPlan.from_mesh(asym).folded
 
 
 def test_workload_library_exports_its_header():
