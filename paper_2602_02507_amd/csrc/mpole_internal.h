@@ -42,7 +42,8 @@ struct ClassDev {
   const int32_t *moff;   // [nblocks+1] CSR offsets of block members
   const int32_t *mem;    // [ncell] member fine-cell index j*nphi+k, ascending per block
   const int4 *rect;      // [nblocks] (j0, k0, nj, nk) when every block is a theta-phi rectangle, else null
-  const int32_t *span0;  // [ceil(npair / kPackSpan)] first rep cell of a packing span of pairs whose rep blocks
+  const int32_t *span0;  // [ceil(nblocks / kPackSpan)] first cell of a span of consecutive single-cell blocks, else -1
+  const int32_t *pspan0; // [ceil(npair / kPackSpan)] first rep cell of a packing span of pairs whose rep blocks
                          // are single cells at consecutive cells (their mirrors then are the mirror cells), else -1
   const int32_t *lidx;   // [nblocks] index of a large block in the class's large-block list, else -1; null if none
   // theta bands when every block is an nj x nk rectangle at a phi column
@@ -59,6 +60,10 @@ struct ClassDev {
   // (b, b).  Pairs are ordered by their first block.
   const int2 *pairs;     // [npair] (rep, mir) block ids
   int32_t npair, npair_pad;
+  // packing: band tasks (j0, nj, nk, q0), one workgroup each (null: spans of
+  // kPackSpan pairs), and the packing workgroups per shell of this class
+  const int4 *ptasks;
+  int32_t npack;
   double *table;         // [nblocks_pad][namp] FP64 block-mean kernels, natural mode order, zero padded
   double *tm, *te;       // FP64 contraction operands over pairs: [npair_pad][namp_m] (moment) and
                          // [npair_pad][namp_e] (expansion); both the table itself when unfolded
@@ -89,7 +94,9 @@ struct PlanDev {
   ClassDev *classes;           // [nclasses] (device copy)
   double *pavg;      // [ntheta][nplm] theta-cell averages of P~_l^m
   double *trig;      // [nphi][2*(lmax+1)] (<cos m ph>, <sin m ph>)
-  double *weight;    // [ncell] 4 pi G dOmega
+  double *weight;    // [ncell] 4 pi G dOmega = wrow[j] * dphi[k]
+  double *wrow;      // [ntheta] 4 pi G (cos th_j - cos th_j+1)
+  double *dphi;      // [nphi] phi_k+1 - phi_k
   double *dom;       // [ncell] dOmega, the solid angle of each angular cell
   double *jr, *ji;   // [nr][lmax+1] exact shell integrals of r^(2+l), r^(1-l)
   double *rr, *ri;   // [nr][lmax+1] volume-averaged r^l, r^-(l+1)

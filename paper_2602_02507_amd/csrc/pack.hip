@@ -56,6 +56,136 @@ __device__ __forceinline__ void block_sw(const PlanDev &P, const ClassDev &C, in
   wt = gmem(C.wsum)[b];
 }
 
+// One pair's packed values: the even and odd sources less the shift times
+// the even and odd weights; the FP64 monopole (sum of even sources times the
+// pair's l = 0 kernel) and the row maximum (FP16 x2) accumulate.
+template <int MODE>
+__device__ __forceinline__ void pack_vals(const ClassDev &C, bool fold, int q, double se, double so, double we,
+                                          double wo, double shift, double &de, double &dod, double &mono,
+                                          double &mx) {
+  de = MODE != 0 ? se - shift * we : se;
+  dod = MODE != 0 ? so - shift * wo : so;
+  if (MODE != 0) {
+    mono += se * gmem(C.tcol0)[q];
+    mx = fmax(mx, fmax(fabs(de), fold ? fabs(dod) : 0.0));
+  }
+}
+
+// Stores of one pair's packed values: the FP64 rows (FP64, FP16 x2) or the
+// split planes (BF16 x3, 2-byte stores).
+template <int MODE>
+__device__ __forceinline__ void pack_store(const ClassDev &C, bool fold, int row, int q, double de, double dod) {
+  if (MODE == kSplitBf16x3) {
+    split_store<kSplitBf16x3>(de, C.ppacks + slab_index<kSplitBf16x3>(row, q, C.nrows), 16);
+    if (fold) split_store<kSplitBf16x3>(dod, C.ppacks_o + slab_index<kSplitBf16x3>(row, q, C.nrows), 16);
+  } else {
+    gmem(C.pack)[(size_t)row * C.npair_pad + q] = de;
+    if (fold) gmem(C.pack_o)[(size_t)row * C.npair_pad + q] = dod;
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void pack_emit(const ClassDev &C, bool fold, int row, int q, double se, double so,
+                                          double we, double wo, double shift, double &mono, double &mx) {
+  double de, dod;
+  pack_vals<MODE>(C, fold, q, se, so, we, wo, shift, de, dod, mono, mx);
+  pack_store<MODE>(C, fold, row, q, de, dod);
+}
+
+// Band task tx of a class (the block map is theta bands): lanes take phi
+// columns k; a task of single-cell rows (nk = 1) packs pair q0 + r nphi + k
+// from cell (j0 + r, k) and its mirror cell (ntheta-1-j0-r, k); a task of
+// nj x nk merged blocks sums each column down the band's rows (and the
+// mirror band's), combines the nk lanes of a block by xor butterflies
+// (blocks are aligned and nk <= 64 divides the wavefront), and packs pair
+// q0 + k / nk.  Coalesced loads, all issued before they are used; a cell's
+// weight is its row factor times its column width (bitwise the weight
+// table).  BF16 x3 rows of single cells whose pairs start at multiples of 8
+// go through LDS and leave as 16-byte stores of 8 pairs of one plane.
+constexpr int STAGE_PAIRS = kBandCopyRows * PACK_THREADS;
+template <int MODE>
+__device__ __forceinline__ void pack_band(const PlanDev &P, const ClassDev &C, int row, int tx, const double *src,
+                                          double shift, double &mono, double &mx, uint16_t *st) {
+  const int4 tk = ld_const(C.ptasks + tx);
+  const int j0 = tk.x, nj = tk.y, nk = tk.z, q0 = tk.w;
+  const bool fold = P.fold != 0;
+  const bool self = !fold || j0 + nj - 1 == P.ntheta - 1 - j0;   // the band is its own mirror
+  const auto srcg = gmem(src);
+  const auto dphi = gmem(static_cast<const double *>(P.dphi));
+  const int mrow0 = P.ntheta - 1 - j0;   // mirror of row j0 (mirror of j0 + r is mrow0 - r)
+  const bool staged = MODE == kSplitBf16x3 && nk == 1 && ((q0 | P.nphi) & 7) == 0;
+  for (int k0 = 0; k0 < P.nphi; k0 += PACK_THREADS) {
+    const int k = k0 + threadIdx.x;
+    const bool kin = k < P.nphi;
+    const int kc = kin ? k : 0;
+    const double dp = kin ? dphi[kc] : 0.0;
+    if (nk == 1) {
+      double xr[kBandCopyRows], xm[kBandCopyRows];
+#pragma unroll
+      for (int r = 0; r < kBandCopyRows; ++r) {
+        const int rr = min(r, nj - 1);
+        xr[r] = srcg[(j0 + rr) * P.nphi + kc];
+        xm[r] = self ? 0.0 : srcg[(mrow0 - rr) * P.nphi + kc];
+      }
+#pragma unroll
+      for (int r = 0; r < kBandCopyRows; ++r) {
+        if (r >= nj) break;
+        const double wr = ld_const(P.wrow + j0 + r) * dp;
+        const double wm = self ? 0.0 : ld_const(P.wrow + mrow0 - r) * dp;
+        const double sr = wr * xr[r], sm = wm * xm[r];
+        const int q = q0 + r * P.nphi + k;
+        if (!staged) {
+          if (kin) pack_emit<MODE>(C, fold, row, q, sr + sm, sr - sm, wr + wm, wr - wm, shift, mono, mx);
+        } else if (kin) {
+          double de, dod;
+          pack_vals<MODE>(C, fold, q, sr + sm, sr - sm, wr + wm, wr - wm, shift, de, dod, mono, mx);
+          // planes of row r, parity 0/1: st[((r * 2 + par) * 3 + plane) * 256 + lane]
+          split_store<kSplitBf16x3>(de, st + (r * 2 + 0) * 3 * PACK_THREADS + threadIdx.x, PACK_THREADS);
+          if (fold) split_store<kSplitBf16x3>(dod, st + (r * 2 + 1) * 3 * PACK_THREADS + threadIdx.x, PACK_THREADS);
+        }
+      }
+      if (staged) {
+        __syncthreads();
+        // 16-byte pieces: (row r, parity, plane, 8 pairs) of the chunk's runs
+        const int nrun = min(PACK_THREADS, P.nphi - k0), nh = nrun / 8, npar = fold ? 2 : 1;
+        const int items = nj * npar * 3 * nh;
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        for (int it = threadIdx.x; it < items; it += PACK_THREADS) {
+          const int h = it % nh, rest = it / nh;
+          const int plane = rest % 3, rp = rest / 3;
+          const int par = rp % npar, r = rp / npar;
+          const u4 v = *reinterpret_cast<const u4 *>(st + ((r * 2 + par) * 3 + plane) * PACK_THREADS + 8 * h);
+          const int q = q0 + r * P.nphi + k0 + 8 * h;   // a multiple of 8
+          uint16_t *dst = (par ? C.ppacks_o : C.ppacks) + slab_index<kSplitBf16x3>(row, q, C.nrows) + 16 * plane;
+          *gmem(reinterpret_cast<u4 *>(dst)) = v;
+        }
+        __syncthreads();
+      }
+    } else {
+      double a = 0.0, w = 0.0, am = 0.0, wn = 0.0;
+#pragma unroll 4
+      for (int r = 0; r < nj; ++r) {
+        const double wc = ld_const(P.wrow + j0 + r) * dp, xc = srcg[(j0 + r) * P.nphi + kc];
+        const double wcm = self ? 0.0 : ld_const(P.wrow + mrow0 - r) * dp;
+        const double xcm = self ? 0.0 : srcg[(mrow0 - r) * P.nphi + kc];
+        a += wc * xc;
+        w += wc;
+        am += wcm * xcm;
+        wn += wcm;
+      }
+      if (!kin) a = w = am = wn = 0.0;
+      for (int d = 1; d < nk; d <<= 1) {
+        a += __shfl_xor(a, d, 64);
+        w += __shfl_xor(w, d, 64);
+        am += __shfl_xor(am, d, 64);
+        wn += __shfl_xor(wn, d, 64);
+      }
+      if (kin && (k & (nk - 1)) == 0)
+        pack_emit<MODE>(C, fold, row, q0 + k / nk, a + am, a - am, w + wn, w - wn, shift, mono, mx);
+    }
+  }
+}
+
 template <int MODE>   // 0 = FP64, kSplitBf16x3, kSplitFp16x2
 __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   __shared__ double red[PACK_THREADS / 64];
@@ -67,7 +197,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   const double *__restrict__ rho = J.io.rho;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   const int q0 = bx * PACK_SPAN + threadIdx.x;   // this thread's first pair
-  if (bx * PACK_SPAN >= C.npair) return;   // whole workgroup idle for this class
+  if (bx >= C.npack) return;   // whole workgroup idle for this class
   const int row = ld_const(P.shell_row + i);
   const double *__restrict__ src = rho + (size_t)i * P.ncell;
   const double *__restrict__ w = P.weight;
@@ -96,10 +226,18 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     }
     shift = wsm > 0.0 ? a / wsm : 0.0;   // stored at the end: no store ahead of the loads
   }
+  double mono = 0.0, mx = 0.0;
+  if (C.ptasks != nullptr) {
+    __shared__ __align__(16) uint16_t band_stage[MODE == kSplitBf16x3 ? 2 * 3 * STAGE_PAIRS : 8];
+    pack_band<MODE>(P, C, row, bx, src, shift, mono, mx, band_stage);
+    // the padding pairs past the last one are zero
+    const int q = C.npair + threadIdx.x;
+    if (bx == 0 && q < C.npair_pad) pack_emit<MODE>(C, fold, row, q, 0.0, 0.0, 0.0, 0.0, 0.0, mono, mx);
+  } else {
   // per pair (rep, mir): the even and odd combinations of the two blocks'
   // sources and weights (the mirror's part left out when mir == rep)
   double se[PACK_UNROLL], so[PACK_UNROLL], we[PACK_UNROLL], wo[PACK_UNROLL];
-  const int run0 = ld_const(C.span0 + bx);
+  const int run0 = ld_const(C.pspan0 + bx);
   if (run0 >= 0) {
     // the span's rep blocks are single cells at consecutive cells and their
     // mirrors the mirror cells: coalesced loads, no block descriptors
@@ -141,7 +279,6 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     de[u] = MODE != 0 ? se[u] - shift * we[u] : se[u];
     dod[u] = MODE != 0 ? so[u] - shift * wo[u] : so[u];
   }
-  double mono = 0.0, mx = 0.0;
   if (MODE == kSplitBf16x3) {
     // split into LDS copies of this workgroup's 64 k-slab groups of 16 pairs,
     // [group][plane][16], then write each group's 96 contiguous bytes
@@ -182,6 +319,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
       mx = fmax(mx, fmax(fabs(de[u]), fold ? fabs(dod[u]) : 0.0));
     }
   }
+  }   // span path
   if (MODE != 0) {
     if (bx == 0 && threadIdx.x == 0) {
       gmem(P.shift)[i] = shift;
@@ -204,9 +342,8 @@ __global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
   const int i = J.local;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   const int row = ld_const(P.shell_row + i);
-  const int nparts = (C.npair + PACK_SPAN - 1) / PACK_SPAN;
   double mx = 0.0;
-  for (int q = 0; q < nparts; ++q) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);
+  for (int q = 0; q < C.npack; ++q) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);
   const double scale = row_scale(mx);
   const double inv = 1.0 / scale;   // exact: a power of two
   for (int par = 0; par < (P.fold ? 2 : 1); ++par) {

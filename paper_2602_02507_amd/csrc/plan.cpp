@@ -91,17 +91,20 @@ GaussRule make_gauss_rule() {
 struct ClassHost {
   std::vector<int32_t> rows, moff, mem;
   std::vector<int32_t> rect;  // 4 per block when every block is a rectangle in (j, k)
-  std::vector<int32_t> span0; // per packing span: first cell when the span is a run of single cells, else -1
+  std::vector<int32_t> span0;  // per block span: first cell when the span is a run of single cells, else -1
+  std::vector<int32_t> pspan0; // the same per packing span of pairs (rep cells)
   std::vector<int32_t> sep_src, sep_avg;   // separable path: blocks on merged rows, blocks with > 1 member
   std::vector<int32_t> large, lidx;        // blocks of more than kLargeBlock cells; index in `large` per block
   std::vector<int32_t> bands;              // theta bands (j0, nj, nk, kind), or empty
   std::vector<int32_t> mirb;               // mirror block of each block (theta -> pi - theta), or empty
   std::vector<int32_t> pairs;              // (rep, mir) per pair
-  int npair = 0, npair_pad = 0;
+  std::vector<int32_t> ptasks;             // band packing tasks (j0, nj, nk, q0), or empty
+  int npair = 0, npair_pad = 0, npack = 0;
+  size_t off_ptasks = 0;
   size_t off_pairs = 0, off_tm = 0, off_te = 0, off_pack_o = 0, off_ppacks_o = 0;
   size_t off_lidx = 0, off_bands = 0;
   size_t off_sep_src = 0, off_sep_avg = 0;
-  size_t off_span0 = 0;
+  size_t off_span0 = 0, off_pspan0 = 0;
   size_t off_rect = 0;
   int nblocks = 0, nblocks_pad = 0, splits = 1, kchunk = 0;
   int m_tiles_mom = 0, m_tiles_exp = 0, n_tiles_mom = 0, n_tiles_exp = 0, wg_mom_begin = 0, wg_exp_begin = 0;
@@ -124,6 +127,7 @@ struct mpole_plan_t {
   std::vector<ClassHost> cls;
   size_t ws_bytes = 0;
   size_t off_r = 0, off_th = 0, off_ph = 0, off_shell_class = 0, off_shell_row = 0, off_classes = 0;
+  size_t off_wrow = 0, off_dphi = 0;
   size_t off_pavg = 0, off_trig = 0, off_weight = 0, off_jr = 0, off_ji = 0, off_rr = 0, off_ri = 0;
   size_t off_ang = 0, off_coef = 0, off_edge_r = 0, off_edge_i = 0, off_cplanes = 0, off_cscale = 0, off_mono = 0, off_max = 0;
   int mono_stride = 1;
@@ -212,6 +216,54 @@ void choose_splits(mpole_plan_t &p, int target) {
 
 void layout_plan(mpole_plan_t *p, int target);
 int default_target(const mpole_plan_t *p);
+
+// Band packing tasks of a class whose blocks form theta bands of merged
+// blocks (at most kLargeBlock cells) and single-cell rows: one task per
+// merged band that is its own rep (north of its mirror, or its own mirror),
+// and per run of up to kBandCopyRows single-cell rows that are all north of
+// their mirror rows or one row that is its own mirror (unfolded: every band,
+// rows as they come).  Each task's pairs must be consecutive: q0 + k / nk for
+// a merged band, q0 + (j - j0) nphi + k for single-cell rows; any other map
+// keeps the span path (empty list).
+void build_pack_tasks(const mpole_plan_t *p, ClassHost &C) {
+  C.ptasks.clear();
+  if (C.bands.empty()) return;
+  std::vector<int32_t> id(p->ncell), qb(C.nblocks, -1);
+  for (int b = 0; b < C.nblocks; ++b)
+    for (int e = C.moff[b]; e < C.moff[b + 1]; ++e) id[C.mem[e]] = b;
+  for (int q = 0; q < C.npair; ++q) qb[C.pairs[2 * q]] = q;
+  const int nt = p->nt, np = p->np;
+  std::vector<int32_t> t;
+  auto pair_at = [&](int j, int k) { return qb[id[(size_t)j * np + k]]; };
+  for (size_t x = 0; x + 3 < C.bands.size(); x += 4) {
+    const int j0 = C.bands[x], nj = C.bands[x + 1], nk = C.bands[x + 2], kind = C.bands[x + 3];
+    if (kind == 2) return;
+    if (kind == 1) {
+      const int mj0 = nt - j0 - nj;   // first row of the mirror band
+      if (p->fold && mj0 < j0) continue;
+      const int q0 = pair_at(j0, 0);
+      for (int k = 0; k < np; ++k)
+        if (q0 < 0 || pair_at(j0, k) != q0 + k / nk) return;
+      t.insert(t.end(), {j0, nj, nk, q0});
+      continue;
+    }
+    // single-cell rows: runs of rows that are reps of pairs (or their own mirror)
+    for (int j = j0; j < j0 + nj;) {
+      const int mj = nt - 1 - j;
+      if (p->fold && mj < j) { ++j; continue; }
+      int n = 1;
+      if (!p->fold || mj > j)
+        while (j + n < j0 + nj && n < kBandCopyRows && (!p->fold || nt - 1 - (j + n) > j + n)) ++n;
+      const int q0 = pair_at(j, 0);
+      for (int r = 0; r < n; ++r)
+        for (int k = 0; k < np; ++k)
+          if (q0 < 0 || pair_at(j + r, k) != q0 + r * np + k) return;
+      t.insert(t.end(), {j, n, 1, q0});
+      j += n;
+    }
+  }
+  C.ptasks = t;
+}
 
 int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
   if (!m) return fail(MPOLE_ERR_INVALID, "mesh is null");
@@ -390,11 +442,23 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
     }
     C.npair = (int)(C.pairs.size() / 2);
     C.npair_pad = round_up(C.npair, p->kpad);
+    // spans of kPackSpan blocks that are single cells at consecutive cell
+    // indices (coarsening): span0[s] = cell of the span's first block, else -1
+    const int nbspan = (C.nblocks + kPackSpan - 1) / kPackSpan;
+    C.span0.assign(nbspan, -1);
+    for (int sp = 0; sp < nbspan; ++sp) {
+      const int bb = sp * kPackSpan, be = std::min(C.nblocks, bb + kPackSpan);
+      const int first = C.mem[C.moff[bb]];
+      bool affine = true;
+      for (int b = bb; b < be && affine; ++b)
+        affine = C.moff[b + 1] - C.moff[b] == 1 && C.mem[C.moff[b]] == first + (b - bb);
+      if (affine) C.span0[sp] = first;
+    }
     // packing spans of pairs whose rep blocks are single cells at consecutive
-    // cell indices: span0[s] = cell of the span's first rep, else -1 (their
+    // cell indices: pspan0[s] = cell of the span's first rep, else -1 (their
     // mirror blocks are then the single mirror cells)
     const int nspan = (C.npair + kPackSpan - 1) / kPackSpan;
-    C.span0.assign(nspan, -1);
+    C.pspan0.assign(nspan, -1);
     for (int sp = 0; sp < nspan; ++sp) {
       const int qb = sp * kPackSpan, qe = std::min(C.npair, qb + kPackSpan);
       const int first = C.mem[C.moff[C.pairs[2 * qb]]];
@@ -404,8 +468,10 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
         affine = C.moff[b + 1] - C.moff[b] == 1 && C.mem[C.moff[b]] == first + (q - qb) &&
                  C.moff[mb + 1] - C.moff[mb] == 1;
       }
-      if (affine) C.span0[sp] = first;
+      if (affine) C.pspan0[sp] = first;
     }
+    build_pack_tasks(p, C);
+    C.npack = C.ptasks.empty() ? nspan : (int)(C.ptasks.size() / 4);
   }
   // mode columns: folded, even parity (l + m) first, then odd
   p->pos_m.clear();
@@ -579,6 +645,8 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->off_pavg = take(sizeof(double) * (size_t)p->nt * nplm);
   p->off_trig = take(sizeof(double) * (size_t)p->np * 2 * (p->L + 1));
   p->off_weight = take(sizeof(double) * (size_t)p->ncell);
+  p->off_wrow = take(sizeof(double) * (size_t)p->nt);
+  p->off_dphi = take(sizeof(double) * (size_t)p->np);
   p->off_dom = take(sizeof(double) * (size_t)p->ncell);
   p->off_jr = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
   p->off_ji = take(sizeof(double) * (size_t)p->nr * (p->L + 1));
@@ -597,8 +665,8 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->off_cscale = stake(sizeof(double) * (size_t)p->nr);
   {
     int maxb = 0;
-    for (auto &C : p->cls) maxb = std::max(maxb, C.npair);
-    p->mono_stride = (maxb + kPackSpan - 1) / kPackSpan;
+    for (auto &C : p->cls) maxb = std::max(maxb, C.npack);
+    p->mono_stride = std::max(maxb, 1);
   }
   p->off_mono = stake(sizeof(double) * (size_t)p->nr * p->mono_stride);
   p->off_max = stake(sizeof(double) * (size_t)p->nr * p->mono_stride);
@@ -616,11 +684,13 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_mem = take(sizeof(int32_t) * p->ncell);
     C.off_rect = take(sizeof(int32_t) * C.rect.size());
     C.off_span0 = take(sizeof(int32_t) * C.span0.size());
+    C.off_pspan0 = take(sizeof(int32_t) * C.pspan0.size());
     C.off_lidx = take(sizeof(int32_t) * C.lidx.size());
     C.off_bands = take(sizeof(int32_t) * C.bands.size());
     const size_t dense = p->sep ? 0 : 1;   // the separable path has no block x mode tables
     C.off_table = take(dense * sizeof(double) * (size_t)C.nblocks_pad * p->namp);
     C.off_pairs = take(sizeof(int32_t) * C.pairs.size());
+    C.off_ptasks = take(sizeof(int32_t) * C.ptasks.size());
     // FP64 folded operands over pairs (unfolded: the table itself)
     const size_t f64fold = (dense && p->fold && p->nplanes == 0) ? 1 : 0;
     C.off_tm = take(f64fold * sizeof(double) * (size_t)C.npair_pad * p->namp_m);
@@ -777,6 +847,8 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
   D.pavg = (double *)(ws + p->off_pavg);
   D.trig = (double *)(ws + p->off_trig);
   D.weight = (double *)(ws + p->off_weight);
+  D.wrow = (double *)(ws + p->off_wrow);
+  D.dphi = (double *)(ws + p->off_dphi);
   D.dom = (double *)(ws + p->off_dom);
   D.jr = (double *)(ws + p->off_jr);
   D.ji = (double *)(ws + p->off_ji);
@@ -818,12 +890,15 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
     C.mem = (const int32_t *)(ws + H.off_mem);
     C.rect = H.rect.empty() ? nullptr : (const int4 *)(ws + H.off_rect);
     C.span0 = (const int32_t *)(ws + H.off_span0);
+    C.pspan0 = (const int32_t *)(ws + H.off_pspan0);
     C.lidx = H.lidx.empty() ? nullptr : (const int32_t *)(ws + H.off_lidx);
     C.bands = H.bands.empty() ? nullptr : (const int4 *)(ws + H.off_bands);
     C.nbands = (int32_t)(H.bands.size() / 4);
     D.max_bands = std::max(D.max_bands, C.nbands);
     C.table = (double *)(ws + H.off_table);
     C.pairs = (const int2 *)(ws + H.off_pairs);
+    C.ptasks = H.ptasks.empty() ? nullptr : (const int4 *)(ws + H.off_ptasks);
+    C.npack = H.npack;
     C.npair = H.npair;
     C.npair_pad = H.npair_pad;
     const bool f64fold = p->fold && p->nplanes == 0;
@@ -943,9 +1018,11 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     if (e == hipSuccess) e = upload(ws, H.off_mem, H.mem.data(), sizeof(int32_t) * H.mem.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_rect, H.rect.data(), sizeof(int32_t) * H.rect.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_span0, H.span0.data(), sizeof(int32_t) * H.span0.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_pspan0, H.pspan0.data(), sizeof(int32_t) * H.pspan0.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_lidx, H.lidx.data(), sizeof(int32_t) * H.lidx.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_bands, H.bands.data(), sizeof(int32_t) * H.bands.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_pairs, H.pairs.data(), sizeof(int32_t) * H.pairs.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_ptasks, H.ptasks.data(), sizeof(int32_t) * H.ptasks.size(), s);
   }
   if (e == hipSuccess) e = upload(ws, p->off_pos_m, p->pos_m.data(), sizeof(int32_t) * p->pos_m.size(), s);
   if (e == hipSuccess) e = upload(ws, p->off_perm_m, p->perm_m.data(), sizeof(int32_t) * p->perm_m.size(), s);

@@ -48,8 +48,7 @@ __global__ __launch_bounds__(256) void k_reduce(BatchDev B) {
   } else if (n == 0) {
     // split precisions: the monopole moment, summed in FP64 by the packing
     // workgroups of this shell, in workgroup order
-    const int nparts = (C.npair + kPackSpan - 1) / kPackSpan;
-    for (int q = 0; q < nparts; ++q) s += gmem(P.mono_part)[(size_t)i * P.mono_stride + q];
+    for (int q = 0; q < C.npack; ++q) s += gmem(P.mono_part)[(size_t)i * P.mono_stride + q];
   } else {
     const auto src = gmem(reinterpret_cast<const float *>(C.partial)) + off;   // FP32 partials
 #pragma unroll 8

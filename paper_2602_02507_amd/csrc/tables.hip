@@ -83,13 +83,21 @@ __global__ void k_trig(PlanDev P) {
   P.trig[(size_t)k * 2 * L1 + 2 * m + 1] = s;
 }
 
+// dOmega and the source weight 4 pi G dOmega of each cell; the weight is the
+// product of a row factor 4 pi G (cos th_j - cos th_j+1) and the column
+// width dph_k, both kept, so that kernels can form it from the two factors
+// bitwise equal to the table.
 __global__ void k_weight(PlanDev P) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.ncell) return;
   const int j = q / P.nphi, k = q % P.nphi;
-  const double dom = cos_diff(P.theta_edges[j], P.theta_edges[j + 1]) * (P.phi_edges[k + 1] - P.phi_edges[k]);
-  P.dom[q] = dom;
-  P.weight[q] = 4.0 * kPi * P.G * dom;
+  const double dc = cos_diff(P.theta_edges[j], P.theta_edges[j + 1]);
+  const double dp = P.phi_edges[k + 1] - P.phi_edges[k];
+  const double wr = 4.0 * kPi * P.G * dc;
+  P.dom[q] = dc * dp;
+  P.weight[q] = wr * dp;
+  if (k == 0) P.wrow[j] = wr;
+  if (j == 0) P.dphi[k] = dp;
 }
 
 __global__ void k_block_table(PlanDev P, ClassDev C) {
