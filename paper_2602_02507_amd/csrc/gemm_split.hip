@@ -65,7 +65,9 @@ struct Split<kSplitFp16x2> {
   }
 };
 
-// Operand source: element (row, k, plane) at base + ((k/16) rows + row) 16 NP + 16 plane + k%16.
+// Operand source: element (row, k, plane) at base + ((k/16) rows + row) 16 NP + 16 plane + k%16
+// (k-slab major), except the moment contraction's packed source, which is
+// row-major: base + (row npair_pad/16 + k/16) 16 NP + 16 plane + k%16.
 struct Operand {
   const uint16_t *base;
   int rows;
@@ -140,9 +142,11 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
     lx_slot[u] = cx * TMV + (rx & ~7) + ((rx + S::sig[cx]) & 7);
     x_ok[u] = x_loader && (m0 + rx) < M;
     const int xr = EXPAND ? (x_ok[u] ? gmem(C.rows)[m0 + rx] : 0) : (x_ok[u] ? m0 + rx : 0);
-    x_off[u] = (size_t)xr * (16 * NP) + 8 * cx;
+    // expansion: k-slab major coefficients; moment: the row-major packed
+    // source [row][k/16][plane][k%16], rows npair_pad long
+    x_off[u] = (size_t)xr * (EXPAND ? 16 * NP : (size_t)C.npair_pad * NP) + 8 * cx;
   }
-  const size_t x_slab = (size_t)X.rows * 16 * NP, y_slab = (size_t)Y.rows * 16 * NP;
+  const size_t x_slab = EXPAND ? (size_t)X.rows * 16 * NP : (size_t)16 * NP, y_slab = (size_t)Y.rows * 16 * NP;
 
   // accumulators: every stage goes to acc; a folded expansion parks its even
   // mode sums in acco at the parity boundary and sums the odd ones in acc

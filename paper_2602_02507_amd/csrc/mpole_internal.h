@@ -73,7 +73,8 @@ struct ClassDev {
   // packed sources over pairs: even = S(rep) + S(mir), odd = S(rep) - S(mir)
   // (the mirror's own source is left out of a pair (b, b)); odd only folded
   double *pack, *pack_o;        // [nrows][npair_pad] FP64 (FP64 and FP16 x2 paths)
-  uint16_t *ppacks, *ppacks_o;  // [nplanes] split planes, rows = class rows, k = pairs
+  uint16_t *ppacks, *ppacks_o;  // [nplanes] split planes, rows = class rows, k = pairs, row-major
+                                //   [row][k/16][plane][k%16] (each shell's row contiguous)
   double *pscale;        // [nrows] power-of-two row scales of the packed source
   double *partial;       // [splits][nrows][namp_m] split-K partial moments (moment mode columns)
   double *wsum;          // [nblocks_pad] 4 pi G dOmega of each block (sum over its cells)

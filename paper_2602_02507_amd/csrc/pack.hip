@@ -57,16 +57,16 @@ __device__ __forceinline__ void block_sw(const PlanDev &P, const ClassDev &C, in
 }
 
 // One pair's packed values: the even and odd sources less the shift times
-// the even and odd weights; the FP64 monopole (sum of even sources times the
-// pair's l = 0 kernel) and the row maximum (FP16 x2) accumulate.
+// the even and odd weights; the sum of the even sources (the monopole
+// moment over sqrt(4 pi): the l = 0 kernel is the constant P~_0^0 =
+// 1/sqrt(4 pi) on every block) and the row maximum (FP16 x2) accumulate.
 template <int MODE>
-__device__ __forceinline__ void pack_vals(const ClassDev &C, bool fold, int q, double se, double so, double we,
-                                          double wo, double shift, double &de, double &dod, double &mono,
-                                          double &mx) {
+__device__ __forceinline__ void pack_vals(bool fold, double se, double so, double we, double wo, double shift,
+                                          double &de, double &dod, double &mono, double &mx) {
   de = MODE != 0 ? se - shift * we : se;
   dod = MODE != 0 ? so - shift * wo : so;
   if (MODE != 0) {
-    mono += se * gmem(C.tcol0)[q];
+    mono += se;
     mx = fmax(mx, fmax(fabs(de), fold ? fabs(dod) : 0.0));
   }
 }
@@ -76,8 +76,8 @@ __device__ __forceinline__ void pack_vals(const ClassDev &C, bool fold, int q, d
 template <int MODE>
 __device__ __forceinline__ void pack_store(const ClassDev &C, bool fold, int row, int q, double de, double dod) {
   if (MODE == kSplitBf16x3) {
-    split_store<kSplitBf16x3>(de, C.ppacks + slab_index<kSplitBf16x3>(row, q, C.nrows), 16);
-    if (fold) split_store<kSplitBf16x3>(dod, C.ppacks_o + slab_index<kSplitBf16x3>(row, q, C.nrows), 16);
+    split_store<kSplitBf16x3>(de, C.ppacks + row_index<kSplitBf16x3>(row, q, C.npair_pad), 16);
+    if (fold) split_store<kSplitBf16x3>(dod, C.ppacks_o + row_index<kSplitBf16x3>(row, q, C.npair_pad), 16);
   } else {
     gmem(C.pack)[(size_t)row * C.npair_pad + q] = de;
     if (fold) gmem(C.pack_o)[(size_t)row * C.npair_pad + q] = dod;
@@ -88,7 +88,7 @@ template <int MODE>
 __device__ __forceinline__ void pack_emit(const ClassDev &C, bool fold, int row, int q, double se, double so,
                                           double we, double wo, double shift, double &mono, double &mx) {
   double de, dod;
-  pack_vals<MODE>(C, fold, q, se, so, we, wo, shift, de, dod, mono, mx);
+  pack_vals<MODE>(fold, se, so, we, wo, shift, de, dod, mono, mx);
   pack_store<MODE>(C, fold, row, q, de, dod);
 }
 
@@ -103,6 +103,26 @@ __device__ __forceinline__ void pack_emit(const ClassDev &C, bool fold, int row,
 // table).  BF16 x3 rows of single cells whose pairs start at multiples of 8
 // go through LDS and leave as 16-byte stores of 8 pairs of one plane.
 constexpr int STAGE_PAIRS = kBandCopyRows * PACK_THREADS;
+
+// Writes the split planes staged in LDS as 16-byte pieces (8 pairs of one
+// plane): runs r < nrun_rows of len pairs (a multiple of 8) starting at pair
+// q_first + r * q_step (a multiple of 8), parity par at st + ((r * 2 + par)
+// * 3 + plane) * PACK_THREADS.  Called by the whole workgroup.
+__device__ __forceinline__ void stage_out(const ClassDev &C, bool fold, int row, const uint16_t *st, int nrun_rows,
+                                          int len, int q_first, int q_step) {
+  const int nh = len / 8, npar = fold ? 2 : 1;
+  const int items = nrun_rows * npar * 3 * nh;
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  for (int it = threadIdx.x; it < items; it += PACK_THREADS) {
+    const int h = it % nh, rest = it / nh;
+    const int plane = rest % 3, rp = rest / 3;
+    const int par = rp % npar, r = rp / npar;
+    const u4 v = *reinterpret_cast<const u4 *>(st + ((r * 2 + par) * 3 + plane) * PACK_THREADS + 8 * h);
+    const int q = q_first + r * q_step + 8 * h;
+    uint16_t *dst = (par ? C.ppacks_o : C.ppacks) + row_index<kSplitBf16x3>(row, q, C.npair_pad) + 16 * plane;
+    *gmem(reinterpret_cast<u4 *>(dst)) = v;
+  }
+}
 template <int MODE>
 __device__ __forceinline__ void pack_band(const PlanDev &P, const ClassDev &C, int row, int tx, const double *src,
                                           double shift, double &mono, double &mx, uint16_t *st) {
@@ -138,7 +158,7 @@ __device__ __forceinline__ void pack_band(const PlanDev &P, const ClassDev &C, i
           if (kin) pack_emit<MODE>(C, fold, row, q, sr + sm, sr - sm, wr + wm, wr - wm, shift, mono, mx);
         } else if (kin) {
           double de, dod;
-          pack_vals<MODE>(C, fold, q, sr + sm, sr - sm, wr + wm, wr - wm, shift, de, dod, mono, mx);
+          pack_vals<MODE>(fold, sr + sm, sr - sm, wr + wm, wr - wm, shift, de, dod, mono, mx);
           // planes of row r, parity 0/1: st[((r * 2 + par) * 3 + plane) * 256 + lane]
           split_store<kSplitBf16x3>(de, st + (r * 2 + 0) * 3 * PACK_THREADS + threadIdx.x, PACK_THREADS);
           if (fold) split_store<kSplitBf16x3>(dod, st + (r * 2 + 1) * 3 * PACK_THREADS + threadIdx.x, PACK_THREADS);
@@ -146,19 +166,8 @@ __device__ __forceinline__ void pack_band(const PlanDev &P, const ClassDev &C, i
       }
       if (staged) {
         __syncthreads();
-        // 16-byte pieces: (row r, parity, plane, 8 pairs) of the chunk's runs
-        const int nrun = min(PACK_THREADS, P.nphi - k0), nh = nrun / 8, npar = fold ? 2 : 1;
-        const int items = nj * npar * 3 * nh;
-        typedef unsigned u4 __attribute__((ext_vector_type(4)));
-        for (int it = threadIdx.x; it < items; it += PACK_THREADS) {
-          const int h = it % nh, rest = it / nh;
-          const int plane = rest % 3, rp = rest / 3;
-          const int par = rp % npar, r = rp / npar;
-          const u4 v = *reinterpret_cast<const u4 *>(st + ((r * 2 + par) * 3 + plane) * PACK_THREADS + 8 * h);
-          const int q = q0 + r * P.nphi + k0 + 8 * h;   // a multiple of 8
-          uint16_t *dst = (par ? C.ppacks_o : C.ppacks) + slab_index<kSplitBf16x3>(row, q, C.nrows) + 16 * plane;
-          *gmem(reinterpret_cast<u4 *>(dst)) = v;
-        }
+        // the chunk's runs of each row: pairs q0 + r nphi + k0 ..
+        stage_out(C, fold, row, st, nj, min(PACK_THREADS, P.nphi - k0), q0 + k0, P.nphi);
         __syncthreads();
       }
     } else {
@@ -180,8 +189,26 @@ __device__ __forceinline__ void pack_band(const PlanDev &P, const ClassDev &C, i
         am += __shfl_xor(am, d, 64);
         wn += __shfl_xor(wn, d, 64);
       }
-      if (kin && (k & (nk - 1)) == 0)
-        pack_emit<MODE>(C, fold, row, q0 + k / nk, a + am, a - am, w + wn, w - wn, shift, mono, mx);
+      // BF16 x3: the chunk's pairs q0 + k0/nk .. staged when they start at a
+      // multiple of 8 and come in multiples of 8
+      const int npc = min(PACK_THREADS, P.nphi - k0) / nk;
+      const bool mstaged = MODE == kSplitBf16x3 && (((q0 + k0 / nk) | npc) & 7) == 0;
+      if (kin && (k & (nk - 1)) == 0) {
+        if (!mstaged) {
+          pack_emit<MODE>(C, fold, row, q0 + k / nk, a + am, a - am, w + wn, w - wn, shift, mono, mx);
+        } else {
+          double de, dod;
+          pack_vals<MODE>(fold, a + am, a - am, w + wn, w - wn, shift, de, dod, mono, mx);
+          const int t = threadIdx.x / nk;
+          split_store<kSplitBf16x3>(de, st + 0 * 3 * PACK_THREADS + t, PACK_THREADS);
+          if (fold) split_store<kSplitBf16x3>(dod, st + 1 * 3 * PACK_THREADS + t, PACK_THREADS);
+        }
+      }
+      if (mstaged) {
+        __syncthreads();
+        stage_out(C, fold, row, st, 1, npc, q0 + k0 / nk, 0);
+        __syncthreads();
+      }
     }
   }
 }
@@ -299,7 +326,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
       uint16_t *dst0 = par ? C.ppacks_o : C.ppacks;
       for (int v = threadIdx.x; v < ngroups * 6; v += PACK_THREADS) {   // 6 x 16 B per group
         const int g = v / 6, part = v % 6;
-        const auto dst = gmem(reinterpret_cast<u4 *>(dst0 + ((size_t)(g0 + g) * C.nrows + row) * 48));
+        const auto dst = gmem(reinterpret_cast<u4 *>(dst0 + row_index<kSplitBf16x3>(row, 16 * (g0 + g), C.npair_pad)));
         dst[part] = st[g * 6 + part];
       }
     }
@@ -315,7 +342,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
     }
     if (q >= C.npair) continue;
     if (MODE != 0) {
-      mono += se[u] * gmem(C.tcol0)[q];
+      mono += se[u];
       mx = fmax(mx, fmax(fabs(de[u]), fold ? fabs(dod[u]) : 0.0));
     }
   }
@@ -325,7 +352,7 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
       gmem(P.shift)[i] = shift;
       if (MODE == kSplitBf16x3) gmem(C.pscale)[row] = 1.0;   // BF16 x3 rows are not scaled
     }
-    mono = block_sum(mono, red);
+    mono = block_sum(mono, red) * (1.0 / sqrt(4.0 * kPi));
     if (MODE == kSplitFp16x2) mx = block_max(mx, red);
     if (threadIdx.x == 0) {
       P.mono_part[(size_t)i * P.mono_stride + bx] = mono;
@@ -350,7 +377,7 @@ __global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
     const double *__restrict__ prow = (par ? C.pack_o : C.pack) + (size_t)row * C.npair_pad;
     uint16_t *dst = par ? C.ppacks_o : C.ppacks;
     for (int q = threadIdx.x; q < C.npair_pad; q += 256)   // the row's zero padding included
-      split_store<kSplitFp16x2>(prow[q] * inv, dst + slab_index<kSplitFp16x2>(row, q, C.nrows), 16);
+      split_store<kSplitFp16x2>(prow[q] * inv, dst + row_index<kSplitFp16x2>(row, q, C.npair_pad), 16);
   }
   if (threadIdx.x == 0) C.pscale[row] = scale;
 }

@@ -44,6 +44,14 @@ __device__ inline size_t slab_index(int row, int k, int rows) {
   return ((size_t)(k >> 4) * rows + row) * (split_planes<KIND>() * 16) + (k & 15);
 }
 
+// element (row, k) of a row-major split operand (the packed source of the
+// moment contraction): [row][k/16][plane][k%16], npad = padded row length;
+// one shell's row is a contiguous run, and so is each 16-wide K step of it
+template <int KIND>
+__device__ inline size_t row_index(int row, int k, int npad) {
+  return (size_t)row * npad * split_planes<KIND>() + (size_t)(k >> 4) * (split_planes<KIND>() * 16) + (k & 15);
+}
+
 // planes of x; stride = distance between planes in elements
 template <int KIND>
 __device__ inline void split_store(double x, uint16_t *dst, size_t stride) {
