@@ -593,8 +593,10 @@ def bench_large(args, precision):
 
 
 def bench_batch(args, precision):
-    """64 seeded fields of uneven size and lmax solved as one batch (one launch
-    per phase, all fields), captured once in a HIP graph and replayed."""
+    """64 seeded fields of uneven size and lmax solved as one batch, captured
+    once in a HIP graph and replayed: the persistent launch (one launch over
+    per-XCD work queues) is the measured line; the per-phase launch of the
+    same batch is timed beside it and must agree bitwise."""
     import torch
     from paper_2602_02507_amd import mpole
     from paper_2602_02507_amd import workloads as wl
@@ -616,8 +618,8 @@ def bench_batch(args, precision):
                                                                  tune_info[prec]["field_shapes_tuned"]),
                   file=sys.stderr, flush=True)
 
-    def timed_batch(prec):
-        batch = mpole.Batch(meshes, precision=prec, rho=rho, device=dev, tunings=tunings.get(prec))
+    def timed_batch(prec, launch="persistent"):
+        batch = mpole.Batch(meshes, precision=prec, rho=rho, device=dev, tunings=tunings.get(prec), launch=launch)
         for _ in range(args.warmup):
             batch.solve()
         torch.cuda.synchronize()
@@ -632,6 +634,7 @@ def bench_batch(args, precision):
             g.replay()
         b.record(stream)
         torch.cuda.synchronize()
+        batch.check()
         return batch, a.elapsed_time(b) / args.steps
 
     fp64_ms = None
@@ -641,16 +644,28 @@ def bench_batch(args, precision):
         del b64
         torch.cuda.empty_cache()
         print("bench: fp64 batch %.3f ms" % fp64_ms, file=sys.stderr, flush=True)
+    phased, phases_ms = timed_batch(precision, "phases")
+    field_ph = np.array(phased.field_ms())
+    print("bench: %s batch, one launch per phase: %.3f ms; field completion p50 %.3f p99 %.3f ms" % (
+        precision, phases_ms, np.percentile(field_ph, 50), np.percentile(field_ph, 99)), file=sys.stderr, flush=True)
     batch, ms = timed_batch(precision)
     field = np.array(batch.field_ms())
-    print("bench: %s batch %.3f ms; field completion p50 %.3f p99 %.3f ms" % (
-        precision, ms, np.percentile(field, 50), np.percentile(field, 99)), file=sys.stderr, flush=True)
+    print("bench: %s batch, %s launch: %.3f ms; field completion p50 %.3f p99 %.3f ms%s" % (
+        precision, batch.launch, ms, np.percentile(field, 50), np.percentile(field, 99),
+        "" if batch.launch == "persistent" else " (" + batch.launch_note + ")"), file=sys.stderr, flush=True)
+    launches_equal = all(bool(torch.equal(p, q)) for p, q in zip(batch.phi, phased.phi))
+    del phased
+    torch.cuda.empty_cache()
     result = {"metric": METRIC, "value": cell_modes / (ms * 1e-3), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "dtype": DTYPE[precision], "data": "synthetic",
               "config": {"workload": args.workload, "fields": len(meshes), "cells": int(sum(m.ncells for m in meshes)),
                          "cell_modes": cell_modes, "precision": precision, "hip_graph": True},
+              "launch": batch.launch,
               "field_ms_p50": float(np.percentile(field, 50)), "field_ms_p99": float(np.percentile(field, 99)),
+              "phases_launch": {"ms_per_step": phases_ms, "field_ms_p50": float(np.percentile(field_ph, 50)),
+                                "field_ms_p99": float(np.percentile(field_ph, 99)),
+                                "bitwise_equal_to_persistent": launches_equal},
               "autotuned": not args.no_tune,
               "tuning_summary": _tuning_summary(tunings.get(precision)),
               "tune_s": {k: v["seconds"] for k, v in tune_info.items()}}

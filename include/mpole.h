@@ -379,13 +379,34 @@ int mpole_plan_destroy(mpole_plan plan);
 
 /*
  * Batched solve of many independent fields with uneven meshes and lmax (one
- * plan per field, all with the same precision).  Every phase of the solve is
- * ONE kernel launch covering all fields (workgroups are assigned to fields by
- * prefix sums), so a batch solve is a fixed sequence of a few launches with
- * no host synchronisation, allocation or memset: it can be captured in a HIP
- * graph and replayed.  Separable fields (MPOLE_FP64_SEPARABLE, MPOLE_BF16X3_SEPARABLE) are solved
- * one after another, each field's launches filling the device on their own,
- * equally without host synchronisation, allocation or memset.
+ * plan per field, all with the same precision).  A batch solve enqueues no
+ * host synchronisation, allocation or memset, so it can be captured in a HIP
+ * graph and replayed.  It runs in one of two ways:
+ *
+ * MPOLE_LAUNCH_PERSISTENT (the default where it applies): ONE launch of a
+ *   persistent kernel (plus a small reset kernel) does every phase of every
+ *   field.  At bind the library reads which XCD (accelerator die, with its
+ *   own L2 cache) each workgroup runs on, and lays out one work queue per
+ *   XCD: whole fields, spread over the queues by their estimated work and
+ *   ordered shortest first within a queue, each field as its phases in solve
+ *   order, each phase as items (one or a group of workgroups of the phase's
+ *   own kernel).  A workgroup takes the next item of its own XCD's queue,
+ *   waits until the field's previous phase is complete, and runs the item
+ *   with the same device code as the per-phase kernels, so results are
+ *   bitwise those of MPOLE_LAUNCH_PHASES.  Small fields complete early (see
+ *   mpole_batch_field_ms).  Every dependency wait is bounded: after
+ *   wait_polls polls it sets an error word, skips its item and the launch
+ *   ends normally; mpole_batch_check reports it.  A batch launches per phase
+ *   instead when its fields are separable, when a field has coarsened blocks
+ *   of more than 64 cells, when the XCD ids do not follow the round-robin
+ *   dispatch of workgroups, or when the fields cannot be spread over the
+ *   queues within 1.25 times the mean estimated queue work
+ *   (mpole_batch_launch_note says which).
+ * MPOLE_LAUNCH_PHASES: every phase of the solve is ONE kernel launch
+ *   covering all fields (workgroups are assigned to fields by prefix sums), a
+ *   fixed sequence of a few launches.  Separable fields
+ *   (MPOLE_FP64_SEPARABLE, MPOLE_BF16X3_SEPARABLE) are solved one after
+ *   another, each field's launches filling the device on their own.
  *
  * mpole_batch_create: nfields in [1, 4096] meshes (host descriptors, copied);
  *   MPOLE_ERR_INVALID if their precisions differ.
@@ -414,6 +435,33 @@ int mpole_batch_bind(mpole_batch batch, void *dev_workspace, size_t bytes, const
 int mpole_batch_solve(mpole_batch batch, void *hip_stream);
 int mpole_batch_field_ms(mpole_batch batch, double *ms);
 int mpole_batch_destroy(mpole_batch batch);
+
+#define MPOLE_LAUNCH_PHASES 0
+#define MPOLE_LAUNCH_PERSISTENT 1
+#define MPOLE_LAUNCH_PERSISTENT_FORCED 2   /* persistent also when the queues are unbalanced */
+/*
+ * mpole_batch_set_launch: the launch later solves use (MPOLE_LAUNCH_PHASES,
+ *   MPOLE_LAUNCH_PERSISTENT where the batch allows it, see above, or
+ *   MPOLE_LAUNCH_PERSISTENT_FORCED, which skips only the balance condition:
+ *   a batch of fewer fields than XCDs then leaves XCDs idle) and the
+ *   wait budget of the persistent launch in polls (0: the default, 2^22
+ *   polls, seconds of waiting).  Any time; a captured graph
+ *   keeps the launch it captured.  MPOLE_ERR_INVALID for a null batch or an
+ *   unknown launch.
+ * mpole_batch_launch: for a bound batch, the launch the next solve runs; -1
+ *   for a null or unbound batch.
+ * mpole_batch_launch_note: why a bound batch does not run the persistent
+ *   launch under MPOLE_LAUNCH_PERSISTENT ("" when it does, and for a null or
+ *   unbound batch); the string belongs to the batch.
+ * mpole_batch_check: synchronises hip_stream and, if the last solve ran the
+ *   persistent launch and one of its dependency waits gave up (its
+ *   potentials are then undefined), returns MPOLE_ERR_DEVICE; MPOLE_OK
+ *   otherwise.  MPOLE_ERR_WORKSPACE for an unbound batch.
+ */
+int mpole_batch_set_launch(mpole_batch batch, int32_t launch, uint32_t wait_polls);
+int mpole_batch_launch(mpole_batch batch);
+const char *mpole_batch_launch_note(mpole_batch batch);
+int mpole_batch_check(mpole_batch batch, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libmpole.so")
 SOURCES = ["plan.cpp", "tables.hip", "pack.hip", "gemm_f64.hip", "scan.hip", "split.hip", "gemm_split.hip",
-           "gradient.hip", "separable.hip", "sep_bf16.hip", "coarsen.hip", "blocks.hip", "genasis.cpp"]
+           "gradient.hip", "separable.hip", "sep_bf16.hip", "coarsen.hip", "blocks.hip", "genasis.cpp",
+           "persistent.hip"]
 WL_LIB = os.path.join(LIBDIR, "libmpole_workload.so")
 WL_SOURCES = ["rotated_density.hip"]
 ARCH = "gfx950"

@@ -7,6 +7,23 @@ namespace mpole {
 // int pair as a plain vector type (loads through global address-space pointers)
 typedef int i2v __attribute__((ext_vector_type(2)));
 
+// Thread index within the workgroup, as the per-phase device code (the work
+// items) reads it.  A translation unit that runs items in a loop (the
+// persistent batched kernel) defines MPOLE_ITEM_LOOP: the index then passes
+// through an empty asm statement on every read, so that the index arithmetic
+// of an item cannot be hoisted out of the loop, where it would stay live in
+// vector registers across every item.
+#ifdef MPOLE_ITEM_LOOP
+static __device__ __forceinline__ int item_tid() {
+  int t = (int)threadIdx.x;
+  __asm__ volatile("" : "+v"(t));
+  __builtin_assume(t >= 0 && t < 1024);
+  return t;
+}
+#else
+static __device__ __forceinline__ int item_tid() { return (int)threadIdx.x; }
+#endif
+
 // Linear workgroup id -> logical tile id such that XCD x (which receives the
 // hardware ids w = x mod 8 of a launch) owns the contiguous logical ids
 // [x*q + min(x, r), ...): tiles that share operand panels then share an L2.
@@ -101,7 +118,7 @@ __device__ inline Job job_of(const BatchDev &B, int h, int wg) {
 __device__ inline void stamp_done(const BatchDev &B, int f) {
   if (B.stamps == nullptr) return;
   __syncthreads();
-  if (threadIdx.x == 0) atomicMax(&B.stamps[f], (unsigned long long)wall_clock64());
+  if (item_tid() == 0) atomicMax(&B.stamps[f], (unsigned long long)wall_clock64());
 }
 
 // dOmega_b S_b of block b of one shell: the sum over the block's member
@@ -178,8 +195,8 @@ __device__ inline double large_source(const PlanDev &P, const ClassDev &C, int i
 // wavefront totals in order); red holds blockDim.x/64 doubles.
 __device__ inline double block_sum(double v, double *red) {
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+  const int w = item_tid() >> 6, nw = blockDim.x >> 6;
+  if ((item_tid() & 63) == 0) red[w] = v;
   __syncthreads();
   double s = 0.0;
   for (int q = 0; q < nw; ++q) s += red[q];
@@ -190,8 +207,8 @@ __device__ inline double block_sum(double v, double *red) {
 __device__ inline double block_max(double v, double *red) {
   v = fabs(v);
   for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
-  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+  const int w = item_tid() >> 6, nw = blockDim.x >> 6;
+  if ((item_tid() & 63) == 0) red[w] = v;
   __syncthreads();
   double m = 0.0;
   for (int q = 0; q < nw; ++q) m = fmax(m, red[q]);

@@ -161,6 +161,25 @@ struct BatchDev {
   unsigned long long *stamps;  // [nf+1]: per field, wall clock when its potential is done; [nf] batch start; or null
 };
 
+// Work queues of the persistent batched solve (device copies in the batch
+// workspace): one queue per XCD, a run of segments (field, phase, first
+// item, items) with ascending first items.  Phase h of field f has
+// sub[f][h] per-phase workgroups (sub-items), run grp[f][h] at a time as one
+// item.  Dispensers per queue, completion counters and items per (field,
+// phase), the error word.
+struct PersistDev {
+  const int4 *segs;      // all queues' segments, queue after queue
+  const int32_t *qseg;   // [nq + 1] segment range of each queue
+  const int32_t *xcc_q;  // [16] queue of each XCD id, -1 for none
+  const int32_t *sub;    // [nf][PH_COUNT] sub-items of each phase
+  const int32_t *grp;    // [nf][PH_COUNT] sub-items per item
+  int32_t nq;
+  uint32_t *next;        // [nq] next item of each queue
+  uint32_t *done;        // [nf][PH_COUNT] completed items
+  const int32_t *tot;    // [nf][PH_COUNT] items of each phase
+  uint32_t *err;         // 1: a dependency wait ran out of polls
+};
+
 // Separable FP64 path: bind-time transform tables and per-solve intermediates
 // (trig modes t = 0, 2m-1 (cos), 2m (sin), padded to tpad; t-major per shell).
 struct SepClass;
@@ -266,6 +285,16 @@ hipError_t launch_sep_phi_anal_bf16(const PlanDev &P, const SepDev &S, const dou
 hipError_t launch_sep_phi_syn_bf16(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s);
 // the block means of the potential after a phi synthesis (merged blocks, bands, large blocks)
 hipError_t launch_sep_block_means(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s);
+
+// persistent batched solve: XCD probe (ids[w] = XCD id of workgroup w),
+// resident workgroups per CU of the persistent kernel of a precision (0 if
+// unknown), scan modes per item, and the launch (reset + the persistent kernel)
+hipError_t launch_xcc_probe(int32_t *ids, int wgs, hipStream_t s);
+int persistent_blocks_per_cu(int precision);
+int persistent_scan_modes();
+// (Q: host copy of the descriptor, for the reset; Qdev: its device copy)
+hipError_t launch_persistent(const BatchDev &B, const PersistDev &Q, const PersistDev *Qdev, uint32_t spin_limit,
+                             int precision, int grid, hipStream_t s);
 
 hipError_t launch_moment_f64(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_expand_f64(const BatchDev &B, int wgs, hipStream_t s);

@@ -1327,16 +1327,38 @@ int mpole_plan_work(mpole_plan p, double *moment_flops, double *expand_flops, do
 
 }  // extern "C"
 
+namespace {
+constexpr int kProbeWgs = 1024;                 // workgroups of the XCD probe
+constexpr int kMaxXcc = 16;                     // XCD ids 0..15
+constexpr int kItemsPerPhase = 128;             // light phases: sub-items grouped to about this many items
+constexpr int kMaxGroup = 64;                   // ... at most this many sub-items per item
+constexpr uint32_t kWaitPolls = 1u << 22;       // default wait budget (seconds of polling)
+constexpr double kMaxQueueImbalance = 1.25;     // longest queue over the mean, else launch per phase
+}  // namespace
+
 struct mpole_batch_t {
   std::vector<mpole_plan_t *> plans;
   std::vector<size_t> off;      // workspace offset of each field's plan
   size_t off_plans = 0, off_io = 0, off_prefix = 0, off_stamps = 0, ws_bytes = 0;
+  // persistent launch: descriptor, segments, queue ranges, XCD -> queue,
+  // sub-items and groups per phase, dispensers, completion counters, items,
+  // error word, probe ids
+  size_t off_pq = 0, off_segs = 0, off_qseg = 0, off_xccq = 0, off_sub = 0, off_grp = 0, off_next = 0, off_done = 0,
+         off_tot = 0, off_err = 0, off_probe = 0;
   int precision = 0;
   std::vector<int32_t> prefix;  // [PH_COUNT][nf+1]
   std::vector<SolveIO> io;
   bool bound = false;
   char *ws = nullptr;
   double clock_khz = 0.0;
+  int launch = MPOLE_LAUNCH_PERSISTENT;   // requested launch
+  uint32_t wait_polls = kWaitPolls;
+  bool pq_ok = false;                     // work queues built at bind
+  bool pq_balanced = false;               // ... and within kMaxQueueImbalance
+  bool last_persistent = false;           // the last solve ran the persistent launch
+  int pq_grid = 0, pq_nq = 0;
+  PersistDev pq{};                        // host copy of the descriptor (device pointers)
+  std::string pq_note;                    // why the batch launches per phase, if it does
   ~mpole_batch_t() {
     for (auto *p : plans) delete p;
   }
@@ -1376,11 +1398,188 @@ void batch_layout(mpole_batch_t *b, const mpole_tuning *tunings) {
   b->off_io = take(sizeof(SolveIO) * nf);
   b->off_prefix = take(sizeof(int32_t) * PH_COUNT * (nf + 1));
   b->off_stamps = take(sizeof(unsigned long long) * (nf + 1));
+  b->off_pq = take(sizeof(PersistDev));
+  b->off_segs = take(sizeof(int4) * PH_COUNT * nf);
+  b->off_qseg = take(sizeof(int32_t) * (kMaxXcc + 1));
+  b->off_xccq = take(sizeof(int32_t) * kMaxXcc);
+  b->off_sub = take(sizeof(int32_t) * PH_COUNT * nf);
+  b->off_grp = take(sizeof(int32_t) * PH_COUNT * nf);
+  b->off_next = take(sizeof(uint32_t) * kMaxXcc);
+  b->off_done = take(sizeof(uint32_t) * PH_COUNT * nf);
+  b->off_tot = take(sizeof(int32_t) * PH_COUNT * nf);
+  b->off_err = take(sizeof(uint32_t));
+  b->off_probe = take(sizeof(int32_t) * kProbeWgs);
   b->ws_bytes = off;
   b->prefix.assign(PH_COUNT * (nf + 1), 0);
   for (int h = 0; h < PH_COUNT; ++h)
     for (int f = 0; f < nf; ++f)
       b->prefix[h * (nf + 1) + f + 1] = b->prefix[h * (nf + 1) + f] + phase_wgs_host(b->plans[f], h);
+}
+
+// Estimated time of one field's solve (seconds on the whole device, for the
+// order in which lanes claim fields and for the balance test): streaming of
+// the density, planes and potential, the two contractions at a sustained
+// MFMA rate of the precision, and the radial part per (shell, mode).
+double field_estimate(const mpole_plan_t *P) {
+  double macs = 0.0;
+  for (const auto &C : P->cls)
+    macs += (double)round_up((int)C.rows.size(), 64) * C.npair_pad * (double)(P->namp_m + P->namp_e);
+  const double mac_rate = P->precision == MPOLE_FP64 ? 1.6e13 : P->precision == MPOLE_FP16X2 ? 2e14 : 1e14;
+  return 4e-12 * (double)P->nr * P->ncell + macs / mac_rate + 8.4e-11 * (double)P->nr * P->namp;
+}
+
+// Sub-items per item of phase h with `sub` sub-items: the light phases
+// (packing, row split, split-K sum, coefficient step) are grouped to about
+// kItemsPerPhase items, the contractions and the scan are one workgroup per
+// item.
+int phase_group(int h, int sub) {
+  if (h == PH_MOMENT || h == PH_EXPAND || h == PH_SCAN || sub <= kItemsPerPhase) return 1;
+  return std::min(kMaxGroup, (sub + kItemsPerPhase - 1) / kItemsPerPhase);
+}
+
+// Work queues of the persistent launch (on the bound workspace, enqueued on
+// s and synchronised): eligibility, the XCD ids of the device, items per
+// (field, phase), fields spread over one queue per XCD (longest estimate
+// first onto the least loaded queue), shortest first within a queue, and
+// the balance test.  Leaves pq_ok false, with the reason in pq_note, when the
+// batch is to launch per phase.
+hipError_t build_queues(mpole_batch_t *b, hipStream_t s) {
+  b->pq_ok = false;
+  b->pq_balanced = false;
+  b->pq_note.clear();
+  const int nf = (int)b->plans.size();
+  const int smodes = persistent_scan_modes();
+  if (b->precision == MPOLE_FP64_SEPARABLE || b->precision == MPOLE_BF16X3_SEPARABLE) {
+    b->pq_note = "separable precisions launch per phase";
+    return hipSuccess;
+  }
+  for (int f = 0; f < nf; ++f) {
+    if (b->plans[f]->dev.n_litems > 0) {
+      b->pq_note = "a field has blocks of more than " + std::to_string(kLargeBlock) + " cells";
+      return hipSuccess;
+    }
+    if (b->plans[f]->namp % smodes != 0) {
+      b->pq_note = "padded mode count not a multiple of the scan item";
+      return hipSuccess;
+    }
+  }
+  const int per_cu = persistent_blocks_per_cu(b->precision);
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (per_cu <= 0 || ncu <= 0) {
+    b->pq_note = "no occupancy figure for the persistent kernel";
+    return hipSuccess;
+  }
+  // XCD ids of a run of probe workgroups: they must repeat with the period of
+  // the distinct ids (the round-robin dispatch of workgroups over XCDs),
+  // which is what lets a queue be bound to the XCD that runs its workgroups
+  std::vector<int32_t> ids(kProbeWgs, -1);
+  int32_t *ids_d = (int32_t *)(b->ws + b->off_probe);
+  e = launch_xcc_probe(ids_d, kProbeWgs, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ids.data(), ids_d, sizeof(int32_t) * kProbeWgs, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::vector<int32_t> xq(kMaxXcc, -1);
+  int period = 0;
+  for (int w = 0; w < kProbeWgs; ++w) {
+    if (ids[w] < 0 || ids[w] >= kMaxXcc) {
+      b->pq_note = "XCD id out of range";
+      return hipSuccess;
+    }
+    if (period == w && xq[ids[w]] < 0) {
+      xq[ids[w]] = 0;
+      ++period;
+    }
+  }
+  for (int w = 0; w < kProbeWgs; ++w)
+    if (ids[w] != ids[w % period]) {
+      b->pq_note = "workgroups are not dispatched round-robin over XCDs";
+      return hipSuccess;
+    }
+  int nq = 0;
+  for (int x = 0; x < kMaxXcc; ++x)
+    if (xq[x] == 0) xq[x] = nq++;
+  // items per (field, phase) and each field's estimate
+  std::vector<int32_t> tot(PH_COUNT * nf, 0), sub(PH_COUNT * nf, 0), grp(PH_COUNT * nf, 1);
+  std::vector<double> est(nf, 0.0);
+  double total = 0.0;
+  for (int f = 0; f < nf; ++f) {
+    const mpole_plan_t *P = b->plans[f];
+    for (int h = 0; h < PH_COUNT; ++h) {
+      const int n = h == PH_SCAN ? P->namp / smodes : phase_wgs_host(P, h);
+      const int g = phase_group(h, n);
+      sub[f * PH_COUNT + h] = n;
+      grp[f * PH_COUNT + h] = g;
+      tot[f * PH_COUNT + h] = (n + g - 1) / g;
+    }
+    est[f] = field_estimate(P);
+    total += est[f];
+  }
+  std::vector<int> order(nf);
+  for (int f = 0; f < nf; ++f) order[f] = f;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return est[a] > est[c]; });
+  std::vector<double> load(nq, 0.0);
+  std::vector<std::vector<int>> fq(nq);
+  for (int f : order) {
+    const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    fq[q].push_back(f);
+    load[q] += est[f];
+  }
+  const double longest = *std::max_element(load.begin(), load.end());
+  b->pq_balanced = longest <= kMaxQueueImbalance * total / nq;
+  if (!b->pq_balanced) {
+    char msg[128];
+    std::snprintf(msg, sizeof msg, "fields do not spread over %d XCD queues (longest queue %.2f x the mean)", nq,
+                  longest * nq / total);
+    b->pq_note = msg;
+  }
+  std::vector<int4> segs;
+  std::vector<int32_t> qseg(kMaxXcc + 1, 0);
+  for (int q = 0; q < nq; ++q) {
+    std::reverse(fq[q].begin(), fq[q].end());   // shortest first
+    qseg[q] = (int32_t)segs.size();
+    int first = 0;
+    for (int f : fq[q])
+      for (int h = 0; h < PH_COUNT; ++h) {
+        const int n = tot[f * PH_COUNT + h];
+        if (n == 0) continue;
+        segs.push_back(int4{f, h, first, n});
+        first += n;
+      }
+  }
+  qseg[nq] = (int32_t)segs.size();
+  char *ws = b->ws;
+  PersistDev Q{};
+  Q.segs = (const int4 *)(ws + b->off_segs);
+  Q.qseg = (const int32_t *)(ws + b->off_qseg);
+  Q.xcc_q = (const int32_t *)(ws + b->off_xccq);
+  Q.sub = (const int32_t *)(ws + b->off_sub);
+  Q.grp = (const int32_t *)(ws + b->off_grp);
+  Q.nq = nq;
+  Q.next = (uint32_t *)(ws + b->off_next);
+  Q.done = (uint32_t *)(ws + b->off_done);
+  Q.tot = (const int32_t *)(ws + b->off_tot);
+  Q.err = (uint32_t *)(ws + b->off_err);
+  e = upload(ws, b->off_segs, segs.data(), sizeof(int4) * segs.size(), s);
+  if (e == hipSuccess) e = upload(ws, b->off_qseg, qseg.data(), sizeof(int32_t) * qseg.size(), s);
+  if (e == hipSuccess) e = upload(ws, b->off_xccq, xq.data(), sizeof(int32_t) * kMaxXcc, s);
+  if (e == hipSuccess) e = upload(ws, b->off_sub, sub.data(), sizeof(int32_t) * sub.size(), s);
+  if (e == hipSuccess) e = upload(ws, b->off_grp, grp.data(), sizeof(int32_t) * grp.size(), s);
+  if (e == hipSuccess) e = upload(ws, b->off_tot, tot.data(), sizeof(int32_t) * tot.size(), s);
+  if (e == hipSuccess) e = upload(ws, b->off_pq, &Q, sizeof(PersistDev), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host arrays above are temporaries
+  if (e != hipSuccess) return e;
+  b->pq = Q;
+  b->pq_nq = nq;
+  b->pq_grid = per_cu * ncu;
+  b->pq_ok = true;
+  return hipSuccess;
+}
+
+bool runs_persistent(const mpole_batch_t *b) {
+  return b->pq_ok && (b->launch == MPOLE_LAUNCH_PERSISTENT_FORCED || (b->launch == MPOLE_LAUNCH_PERSISTENT && b->pq_balanced));
 }
 
 }  // namespace
@@ -1486,12 +1685,16 @@ int mpole_batch_bind(mpole_batch b, void *dev_ws, size_t bytes, const double *co
   if (e == hipSuccess) e = upload(ws, b->off_io, b->io.data(), sizeof(SolveIO) * nf, s);
   if (e == hipSuccess) e = upload(ws, b->off_prefix, b->prefix.data(), sizeof(int32_t) * b->prefix.size(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host arrays above are temporaries
+  b->ws = ws;
+  if (e == hipSuccess) e = build_queues(b, s);
   int dev = 0, khz = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch bind: %s", hipGetErrorString(e));
+  if (e != hipSuccess) {
+    b->pq_ok = false;
+    return fail(MPOLE_ERR_DEVICE, "batch bind: %s", hipGetErrorString(e));
+  }
   b->clock_khz = khz;
-  b->ws = ws;
   b->bound = true;
   return ok();
 }
@@ -1521,6 +1724,9 @@ int mpole_batch_solve(mpole_batch b, void *stream) {
                   [](int, auto &&launch) { return launch(); });
       if (e == hipSuccess) e = launch_stamp(B.stamps, f, s);
     }
+  } else if (runs_persistent(b)) {
+    e = launch_persistent(B, b->pq, (const PersistDev *)(b->ws + b->off_pq), b->wait_polls, b->precision, b->pq_grid,
+                          (hipStream_t)stream);
   } else {
     std::vector<LargeJob> large;
     for (int f = 0; f < nf; ++f)
@@ -1529,6 +1735,43 @@ int mpole_batch_solve(mpole_batch b, void *stream) {
                   [](int, auto &&launch) { return launch(); });
   }
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch solve: %s", hipGetErrorString(e));
+  b->last_persistent = runs_persistent(b);
+  return ok();
+}
+
+int mpole_batch_set_launch(mpole_batch b, int32_t launch, uint32_t wait_polls) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (launch != MPOLE_LAUNCH_PHASES && launch != MPOLE_LAUNCH_PERSISTENT && launch != MPOLE_LAUNCH_PERSISTENT_FORCED)
+    return fail(MPOLE_ERR_INVALID, "unknown launch %d", launch);
+  b->launch = launch;
+  b->wait_polls = wait_polls ? wait_polls : kWaitPolls;
+  return ok();
+}
+
+int mpole_batch_launch(mpole_batch b) {
+  if (!b || !b->bound) return -1;
+  return runs_persistent(b) ? MPOLE_LAUNCH_PERSISTENT : MPOLE_LAUNCH_PHASES;
+}
+
+const char *mpole_batch_launch_note(mpole_batch b) {
+  if (!b || !b->bound) return "";
+  return b->pq_note.c_str();
+}
+
+int mpole_batch_check(mpole_batch b, void *stream) {
+  if (!b) return fail(MPOLE_ERR_INVALID, "batch is null");
+  if (!b->bound) return fail(MPOLE_ERR_WORKSPACE, "batch has no bound workspace");
+  if (!b->last_persistent) return ok();
+  uint32_t err = 0;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(&err, b->pq.err, sizeof err, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "batch check: %s", hipGetErrorString(e));
+  if (err != 0)
+    return fail(MPOLE_ERR_DEVICE,
+                "batch solve: a dependency wait of the persistent launch gave up after %u polls; the potentials of "
+                "that solve are undefined",
+                b->wait_polls);
   return ok();
 }
 

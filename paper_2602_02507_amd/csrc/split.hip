@@ -8,6 +8,7 @@
 
 #include "device_util.h"
 #include "split_util.h"
+#include "coef_impl.h"
 
 namespace mpole {
 namespace {
@@ -31,38 +32,13 @@ __global__ __launch_bounds__(256) void k_split_tables(PlanDev P, ClassDev C) {
   }
 }
 
-// One workgroup per shell: scale and split the expansion coefficients.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_split_coef(BatchDev B) {
   __shared__ double red[256 / 64];
-  const Job J = job_of(B, PH_COEF, blockIdx.x);
-  const PlanDev &P = J.P;
-  const int i = J.local;
-  const double *__restrict__ c = P.coef + (size_t)i * P.namp;
-  double mx = 0.0;
-  for (int n = threadIdx.x + 1; n < P.nam; n += 256) mx = fmax(mx, fabs(c[n]));
-  const double scale = row_scale(block_max(mx, red));
-  const double inv = 1.0 / scale;
-  // expansion mode columns; the l = 0 term is added in FP64 by the expansion
-  // epilogue
-  for (int col = threadIdx.x; col < P.namp_e; col += 256) {
-    const int n = P.perm_e ? P.perm_e[col] : col;
-    split_store<KIND>((n > 0 && n < P.nam) ? c[n] * inv : 0.0, P.cplanes + slab_index<KIND>(i, col, P.nr), 16);
-  }
-  if (threadIdx.x == 0) P.cscale[i] = scale;
+  split_coef_item<KIND>(job_of(B, PH_COEF, blockIdx.x), red);
 }
 
-// Folded FP64: the coefficients of one shell in expansion mode columns.
-__global__ __launch_bounds__(256) void k_perm_coef(BatchDev B) {
-  const Job J = job_of(B, PH_COEF, blockIdx.x);
-  const PlanDev &P = J.P;
-  const int i = J.local;
-  const double *__restrict__ c = P.coef + (size_t)i * P.namp;
-  for (int col = threadIdx.x; col < P.namp_e; col += 256) {
-    const int n = P.perm_e[col];
-    P.coef_e[(size_t)i * P.namp_e + col] = (n >= 0 && n < P.nam) ? c[n] : 0.0;
-  }
-}
+__global__ __launch_bounds__(256) void k_perm_coef(BatchDev B) { perm_coef_item(job_of(B, PH_COEF, blockIdx.x)); }
 
 }  // namespace
 

@@ -29,7 +29,9 @@ EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_
            "mpole_batch_create", "mpole_batch_tune", "mpole_batch_configure", "mpole_batch_get_tuning",
            "mpole_batch_workspace_bytes",
            "mpole_batch_bind",
-           "mpole_batch_solve", "mpole_batch_field_ms", "mpole_batch_destroy")
+           "mpole_batch_solve", "mpole_batch_field_ms", "mpole_batch_destroy", "mpole_batch_set_launch",
+           "mpole_batch_launch", "mpole_batch_launch_note", "mpole_batch_check")
+LAUNCH_PHASES, LAUNCH_PERSISTENT, LAUNCH_PERSISTENT_FORCED = 0, 1, 2
 PHASES = ("pack", "moment", "reduce", "scan", "split", "expand")
 
 
@@ -128,6 +130,11 @@ def lib():
         L.mpole_batch_solve.argtypes = [vp, vp]
         L.mpole_batch_field_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.mpole_batch_destroy.argtypes = [vp]
+        L.mpole_batch_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32]
+        L.mpole_batch_launch.argtypes = [vp]
+        L.mpole_batch_launch_note.argtypes = [vp]
+        L.mpole_batch_launch_note.restype = ctypes.c_char_p
+        L.mpole_batch_check.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -364,14 +371,20 @@ class Plan(HostPlan):
 
 
 class Batch:
-    """Many fields (uneven meshes, same precision) solved by one launch per phase.
+    """Many fields (uneven meshes, same precision) solved together: one
+    persistent launch over per-XCD work queues where the batch allows it,
+    else one launch per phase (`launch`: "persistent", "phases", or "forced" for
+    persistent also on unbalanced queues).
 
     `meshes` are workloads.Mesh-like objects; rho/phi are per-field float64
     device tensors (phi allocated here when not given).  `solve()` enqueues one
     batch solve on the current stream (graph-capturable); `field_ms()` gives
-    each field's completion time within the last solve after a sync."""
+    each field's completion time within the last solve after a sync;
+    `check()` synchronises and raises if a dependency wait of the persistent
+    launch gave up."""
 
-    def __init__(self, meshes, precision="bf16x3", rho=None, device="cuda", moment_wgs=None, tunings=None):
+    def __init__(self, meshes, precision="bf16x3", rho=None, device="cuda", moment_wgs=None, tunings=None,
+                 launch="persistent", wait_polls=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("mpole needs a ROCm GPU; none is visible to torch")
@@ -394,6 +407,7 @@ class Batch:
                 raise ValueError("one tuning per field")
             arr = (Tuning * self.n)(*[Tuning.of(t) for t in tunings])
             _check(lib().mpole_batch_tune(h, arr))
+        self.set_launch(launch, wait_polls)
         dev = torch.device(device)
         if dev.index is None:
             dev = torch.device(dev.type, torch.cuda.current_device())
@@ -416,6 +430,28 @@ class Batch:
         import torch
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         _check(lib().mpole_batch_solve(self.handle, ctypes.c_void_p(s)))
+
+    def set_launch(self, launch="persistent", wait_polls=0):
+        """Launch of later solves ("persistent", "phases" or "forced": persistent
+        also on unbalanced queues) and the dependency-wait budget of the
+        persistent launch in polls (0: the library default)."""
+        mode = {"phases": LAUNCH_PHASES, "persistent": LAUNCH_PERSISTENT, "forced": LAUNCH_PERSISTENT_FORCED}[launch]
+        _check(lib().mpole_batch_set_launch(self.handle, mode, int(wait_polls)))
+
+    @property
+    def launch(self):
+        """The launch the next solve runs: "persistent" or "phases"."""
+        return "persistent" if lib().mpole_batch_launch(self.handle) == LAUNCH_PERSISTENT else "phases"
+
+    @property
+    def launch_note(self):
+        """Why the batch does not launch persistent when asked to ("" if it does)."""
+        return lib().mpole_batch_launch_note(self.handle).decode()
+
+    def check(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().mpole_batch_check(self.handle, ctypes.c_void_p(s)))
 
     def tunings(self):
         """Per-field launch tunings in use, as dicts."""

@@ -211,7 +211,8 @@ def test_bf16x3_separable_plan_host_side():
 def test_workspace_errors_before_any_device_work():
     """Every MPOLE_ERR_WORKSPACE path is decided on the host before a HIP call:
     a null, misaligned or undersized workspace at bind (plan and batch), and
-    solves, table copies and field times of an unbound plan or batch.  The
+    solves, table copies, field times and launch checks of an unbound plan or
+    batch; an unknown batch launch is MPOLE_ERR_INVALID.  The
     fake device addresses below are never dereferenced."""
     import ctypes
     L = mpole.lib()
@@ -247,6 +248,18 @@ def test_workspace_errors_before_any_device_work():
     assert L.mpole_batch_solve(h, None) == 3
     ms = (ctypes.c_double * 2)()
     assert L.mpole_batch_field_ms(h, ms) == 3
+    # launch selection: decided on the host; an unbound batch has no launch yet
+    assert L.mpole_batch_set_launch(h, 3, 0) == 1
+    assert b"unknown launch" in L.mpole_last_error()
+    assert L.mpole_batch_set_launch(h, mpole.LAUNCH_PERSISTENT_FORCED, 5) == 0
+    assert L.mpole_batch_set_launch(h, mpole.LAUNCH_PHASES, 0) == 0
+    assert L.mpole_batch_launch(h) == -1
+    assert L.mpole_batch_launch_note(h) == b""
+    assert L.mpole_batch_check(h, None) == 3
+    assert L.mpole_batch_set_launch(None, 1, 0) == 1
+    assert L.mpole_batch_launch(None) == -1
+    assert L.mpole_batch_launch_note(None) == b""
+    assert L.mpole_batch_check(None, None) == 1
     assert L.mpole_batch_destroy(h) == 0
 
 
