@@ -1330,6 +1330,7 @@ int mpole_plan_work(mpole_plan p, double *moment_flops, double *expand_flops, do
 namespace {
 constexpr int kProbeWgs = 1024;                 // workgroups of the XCD probe
 constexpr int kMaxXcc = 16;                     // XCD ids 0..15
+constexpr int kPairFields = 2;                  // fields whose phases interleave in a queue
 constexpr int kItemsPerPhase = 128;             // light phases: sub-items grouped to about this many items
 constexpr int kMaxGroup = 64;                   // ... at most this many sub-items per item
 constexpr uint32_t kWaitPolls = 1u << 22;       // default wait budget (seconds of polling)
@@ -1535,19 +1536,27 @@ hipError_t build_queues(mpole_batch_t *b, hipStream_t s) {
                   longest * nq / total);
     b->pq_note = msg;
   }
+  // Within a queue, fields shortest first, taken in pairs whose phases are
+  // interleaved (A pack, B pack, A moment, B moment, ...): while the last
+  // round of one field's phase drains, the other field's items fill the
+  // XCD, and a memory-bound phase of one runs beside a contraction of the
+  // other.  Every item still follows the items it depends on.
   std::vector<int4> segs;
   std::vector<int32_t> qseg(kMaxXcc + 1, 0);
   for (int q = 0; q < nq; ++q) {
     std::reverse(fq[q].begin(), fq[q].end());   // shortest first
     qseg[q] = (int32_t)segs.size();
     int first = 0;
-    for (int f : fq[q])
-      for (int h = 0; h < PH_COUNT; ++h) {
-        const int n = tot[f * PH_COUNT + h];
-        if (n == 0) continue;
-        segs.push_back(int4{f, h, first, n});
-        first += n;
-      }
+    for (size_t k = 0; k < fq[q].size(); k += kPairFields) {
+      const size_t kend = std::min(fq[q].size(), k + kPairFields);
+      for (int h = 0; h < PH_COUNT; ++h)
+        for (size_t j = k; j < kend; ++j) {
+          const int f = fq[q][j], n = tot[f * PH_COUNT + h];
+          if (n == 0) continue;
+          segs.push_back(int4{f, h, first, n});
+          first += n;
+        }
+    }
   }
   qseg[nq] = (int32_t)segs.size();
   char *ws = b->ws;
