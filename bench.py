@@ -82,6 +82,20 @@ def kernel_name(precision, phase):
     return "k_gemm_split<%s, %s>" % (precision, phase)
 
 
+def sources_sha256_16(sources):
+    """First 16 hex digits of the sha256 of the named files, concatenated in
+    order (None if one is missing): the kernel sources a counter entry holds
+    for."""
+    import hashlib
+    h = hashlib.sha256()
+    for s in sources:
+        path = os.path.join(ROOT, s)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload, phase):
     """HBM bytes per launch from the committed counter runs, or None when there
     is none for this kernel or its source changed since they were taken."""
@@ -94,8 +108,7 @@ def measured_traffic(workload, phase):
     for e in data["entries"]:
         if e["workload"] != workload or e["phase"] != phase:
             continue
-        src = os.path.join(ROOT, e["source"])
-        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != e["sha256_16"]:
+        if sources_sha256_16(e["sources"]) != e["sha256_16"]:
             return None
         return 1024.0 * (cal["fetch_factor"] * e["fetch_kib"] + cal["write_factor"] * e["write_kib"])
     return None
