@@ -28,7 +28,12 @@ constexpr int kScanModesWide = 16, kScanModesNarrow = 8, kScanWideMinWgs = 256;
 // BF16 x3 separable: one-row blocks of up to this many phi cells are averaged
 // inside the phi transforms (a power of two, at most 8)
 constexpr int kSepFuseNk = 8;
-constexpr int kBandCopyRows = 8;
+// single-cell rows merged into one theta band (at most), and single-cell
+// rows (with their mirror rows) per packing workgroup of a banded class
+constexpr int kBandRows = 8;
+constexpr int kBandCopyRows = 4;
+// FP16 x2: pairs of one shell's row split into planes per workgroup
+constexpr int kSplitRowChunk = 1024;
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.
 struct GaussRule {
@@ -48,7 +53,7 @@ struct ClassDev {
   const int32_t *lidx;   // [nblocks] index of a large block in the class's large-block list, else -1; null if none
   // theta bands when every block is an nj x nk rectangle at a phi column
   // that is a multiple of nk, uniform within the band: (j0, nj, nk, kind),
-  // kind 0 = single cells (up to kBandCopyRows rows), 1 = blocks of at most
+  // kind 0 = single cells (up to kBandRows rows), 1 = blocks of at most
   // kLargeBlock cells with nk a power of two <= 64, 2 = larger blocks; null
   // for other block maps
   const int4 *bands;
@@ -121,6 +126,7 @@ struct PlanDev {
   double *max_part;  // [nr][mono_stride] partial row maxima of the packed source (FP16 x2)
   int32_t mono_stride;
   int32_t pack_parts;       // packing workgroups per shell
+  int32_t split_chunks;     // FP16 x2: row-split workgroups per shell (kSplitRowChunk pairs each), else 0
   int32_t wg_mom, wg_exp;   // workgroups of the two contraction launches
   int32_t tm_mom, tm_exp;   // output tile heights of the two contractions
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer

@@ -366,24 +366,41 @@ __device__ __forceinline__ void pack_item(const BatchDev &B, const Job &J, char 
   }
 }
 
-// FP16 x2: per shell, the row's power-of-two scale from the partial maxima,
-// then the scaled split planes of the FP64 row.
+// FP16 x2: chunk c of shell i's row (kSplitRowChunk pairs of both parities):
+// the row's power-of-two scale from the shell's partial maxima (every
+// workgroup of the shell combines them in the same order), then the scaled
+// split planes of the chunk's pairs, all loads issued before the stores.
 __device__ __forceinline__ void split_rows_item(const BatchDev &B, const Job &J) {
+  constexpr int U = kSplitRowChunk / 256;
   const PlanDev &P = J.P;
-  const int i = J.local;
+  const int i = J.local / P.split_chunks, q0 = (J.local % P.split_chunks) * kSplitRowChunk;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
+  if (q0 >= C.npair_pad) return;   // past this class's row (workgroup-uniform)
   const int row = ld_const(P.shell_row + i);
   double mx = 0.0;
   for (int q = 0; q < C.npack; ++q) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);
   const double scale = row_scale(mx);
   const double inv = 1.0 / scale;   // exact: a power of two
-  for (int par = 0; par < (P.fold ? 2 : 1); ++par) {
-    const double *__restrict__ prow = (par ? C.pack_o : C.pack) + (size_t)row * C.npair_pad;
-    uint16_t *dst = par ? C.ppacks_o : C.ppacks;
-    for (int q = item_tid(); q < C.npair_pad; q += 256)   // the row's zero padding included
-      split_store<kSplitFp16x2>(prow[q] * inv, dst + row_index<kSplitFp16x2>(row, q, C.npair_pad), 16);
-  }
-  if (item_tid() == 0) C.pscale[row] = scale;
+  const int npar = P.fold ? 2 : 1;
+  double v[2][U];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * 256 + item_tid();
+      const double *__restrict__ prow = (par ? C.pack_o : C.pack) + (size_t)row * C.npair_pad;
+      v[par][u] = par < npar && q < C.npair_pad ? prow[q] : 0.0;   // the row's zero padding included
+    }
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * 256 + item_tid();
+      if (par < npar && q < C.npair_pad)
+        split_store<kSplitFp16x2>(v[par][u] * inv,
+                                  (par ? C.ppacks_o : C.ppacks) + row_index<kSplitFp16x2>(row, q, C.npair_pad), 16);
+    }
+  if (q0 == 0 && item_tid() == 0) C.pscale[row] = scale;
 }
 
 }  // namespace

@@ -396,7 +396,7 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
         if (kind == 1 && (nk > 64 || (nk & (nk - 1)) != 0)) ok = false;
         if (!ok) break;
         const size_t nb4 = C.bands.size();
-        if (kind == 0 && nb4 > 0 && C.bands[nb4 - 1] == 0 && C.bands[nb4 - 3] < kBandCopyRows &&
+        if (kind == 0 && nb4 > 0 && C.bands[nb4 - 1] == 0 && C.bands[nb4 - 3] < kBandRows &&
             C.bands[nb4 - 4] + C.bands[nb4 - 3] == j) {
           ++C.bands[nb4 - 3];
         } else {
@@ -804,10 +804,18 @@ int mpole_plan_folded(mpole_plan p) { return p && p->fold ? 1 : 0; }
 
 namespace {
 
+// FP16 x2 row-split workgroups per shell: chunks of kSplitRowChunk pairs of
+// the longest padded row of any class.
+int split_chunks(const mpole_plan_t *p) {
+  int n = 0;
+  for (const auto &C : p->cls) n = std::max(n, C.npair_pad);
+  return (n + kSplitRowChunk - 1) / kSplitRowChunk;
+}
+
 int phase_wgs_host(const mpole_plan_t *p, int h) {
   switch (h) {
     case PH_PACK: return p->mono_stride * p->nr;
-    case PH_SPLITROWS: return p->precision == MPOLE_FP16X2 ? p->nr : 0;
+    case PH_SPLITROWS: return p->precision == MPOLE_FP16X2 ? p->nr * split_chunks(p) : 0;
     case PH_MOMENT: return p->wg_mom;
     case PH_REDUCE: return (p->namp + 255) / 256 * p->nr;
     case PH_SCAN: return p->namp / p->scan_modes;
@@ -824,6 +832,7 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
                 std::vector<ClassDev> &cd, SepDev &S) {
   D = PlanDev{};
   D.pack_parts = p->mono_stride;
+  D.split_chunks = p->precision == MPOLE_FP16X2 ? split_chunks(p) : 0;
   D.wg_mom = p->wg_mom;
   D.tm_mom = p->tm_mom;
   D.tm_exp = p->tm_exp;
