@@ -12,7 +12,10 @@ __global__ __launch_bounds__(PACK_THREADS) void k_pack(BatchDev B) {
   pack_item<MODE>(B, job_of(B, PH_PACK, blockIdx.x), lds, blockIdx.x == 0);
 }
 
-__global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) { split_rows_item(B, job_of(B, PH_SPLITROWS, blockIdx.x)); }
+__global__ __launch_bounds__(256) void k_split_rows_fp16(BatchDev B) {
+  __shared__ double red[4];
+  split_rows_item(B, job_of(B, PH_SPLITROWS, blockIdx.x), red);
+}
 
 }  // namespace
 

@@ -367,20 +367,18 @@ __device__ __forceinline__ void pack_item(const BatchDev &B, const Job &J, char 
 }
 
 // FP16 x2: chunk c of shell i's row (kSplitRowChunk pairs of both parities):
-// the row's power-of-two scale from the shell's partial maxima (every
-// workgroup of the shell combines them in the same order), then the scaled
-// split planes of the chunk's pairs, all loads issued before the stores.
-__device__ __forceinline__ void split_rows_item(const BatchDev &B, const Job &J) {
+// the row's power-of-two scale from the maximum of the shell's partial
+// maxima (reduced across the workgroup: a maximum is exact in any order, so
+// every workgroup of the shell gets the same scale), then the scaled split
+// planes of the chunk's pairs.  The row loads are issued before the scale
+// is known; red holds 4 doubles of LDS.
+__device__ __forceinline__ void split_rows_item(const BatchDev &B, const Job &J, double *red) {
   constexpr int U = kSplitRowChunk / 256;
   const PlanDev &P = J.P;
   const int i = J.local / P.split_chunks, q0 = (J.local % P.split_chunks) * kSplitRowChunk;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   if (q0 >= C.npair_pad) return;   // past this class's row (workgroup-uniform)
   const int row = ld_const(P.shell_row + i);
-  double mx = 0.0;
-  for (int q = 0; q < C.npack; ++q) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);
-  const double scale = row_scale(mx);
-  const double inv = 1.0 / scale;   // exact: a power of two
   const int npar = P.fold ? 2 : 1;
   double v[2][U];
 #pragma unroll
@@ -391,6 +389,11 @@ __device__ __forceinline__ void split_rows_item(const BatchDev &B, const Job &J)
       const double *__restrict__ prow = (par ? C.pack_o : C.pack) + (size_t)row * C.npair_pad;
       v[par][u] = par < npar && q < C.npair_pad ? prow[q] : 0.0;   // the row's zero padding included
     }
+  double mx = 0.0;
+  for (int q = item_tid(); q < C.npack; q += 256) mx = fmax(mx, P.max_part[(size_t)i * P.mono_stride + q]);
+  mx = block_max(mx, red);
+  const double scale = row_scale(mx);
+  const double inv = 1.0 / scale;   // exact: a power of two
 #pragma unroll
   for (int par = 0; par < 2; ++par)
 #pragma unroll

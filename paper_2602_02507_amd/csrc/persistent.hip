@@ -139,7 +139,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) __attribute__((amdgpu_waves_per_eu
         J.local = s;
         switch (h) {
           case PH_PACK: pack_item<KIND>(B, J, lds, false); break;
-          case PH_SPLITROWS: split_rows_item(B, J); break;
+          case PH_SPLITROWS: split_rows_item(B, J, reinterpret_cast<double *>(lds)); break;
           case PH_MOMENT:
             if constexpr (KIND == 0) moment_f64_item(B, J, reinterpret_cast<double *>(lds));
             else split_item<KIND, false>(B, J, reinterpret_cast<u4 *>(lds));
