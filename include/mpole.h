@@ -219,7 +219,8 @@ int mpole_plan_copy_table(mpole_plan plan, int32_t cls, double *host_out, int64_
  * phase, and clears the record.  Phases: MPOLE_PHASE_PACK (density
  * streaming), _MOMENT (moment contraction), _REDUCE (split-K sum), _SCAN
  * (radial sums and coefficients), _SPLIT (coefficient split, split
- * precisions only), _EXPAND (expansion contraction and potential streaming).
+ * precisions only), _EXPAND (expansion contraction and potential streaming,
+ * including the broadcast of merged blocks' values to their cells).
  */
 enum {
   MPOLE_PHASE_PACK = 0, MPOLE_PHASE_MOMENT = 1, MPOLE_PHASE_REDUCE = 2, MPOLE_PHASE_SCAN = 3,

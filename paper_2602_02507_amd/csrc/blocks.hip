@@ -14,6 +14,7 @@
 // nj x nk rectangle at a phi column divisible by nk, the layout of
 // power-of-two coarsening) take the band kernel for block means instead of
 // one thread per block: coalesced column sums and lane butterflies.
+#include "bcast_impl.h"
 #include "device_util.h"
 
 namespace mpole {
@@ -141,7 +142,15 @@ __global__ __launch_bounds__(LB_THREADS) void k_band(PlanDev P, const double *in
   }
 }
 
+__global__ __launch_bounds__(256) void k_bcast(BatchDev B) { bcast_item(B, job_of(B, PH_BCAST, blockIdx.x)); }
+
 }  // namespace
+
+hipError_t launch_bcast(const BatchDev &B, int wgs, hipStream_t s) {
+  if (wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bcast, dim3(wgs), dim3(256), 0, s, B);
+  return hipGetLastError();
+}
 
 hipError_t launch_bands(const PlanDev &P, int mode, const double *in, double *out, hipStream_t s, int skip_nk) {
   if (P.max_bands == 0 || P.nr == 0) return hipSuccess;

@@ -227,7 +227,9 @@ __device__ __forceinline__ void expand_f64_item(const BatchDev &B, const Job &J,
         bcell[u][h] = rect[4 * b] * P.nphi + rect[4 * b + 1];
         bnj[u][h] = rect[4 * b + 2];
         bnk[u][h] = rect[4 * b + 3];
-        if (bnj[u][h] * bnk[u][h] > kLargeBlock) bnj[u][h] = bnk[u][h] = 1;   // first cell; launch_large broadcasts
+        // first cell only: launch_large (past kLargeBlock cells) or the
+        // broadcast phase (merged blocks of a banded class) writes the rest
+        if (bnj[u][h] * bnk[u][h] > kLargeBlock || C.bands != nullptr) bnj[u][h] = bnk[u][h] = 1;
       } else {
         bcell[u][h] = gmem(C.moff)[b];
         bnj[u][h] = gmem(C.moff)[b + 1];

@@ -248,22 +248,34 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
 #undef LSTORE
   if (kt < nk) compute(0, kt);   // odd stage count: the last stage sits in LDS 0
 
-  // epilogue: undo the row scale in FP64
+  // epilogue: undo the row scale in FP64.  The tile's per-row values (the
+  // shell, its coefficient scale and l = 0 coefficient; the moment rows'
+  // source scales) are first staged in LDS, one row per thread: read per row
+  // inside the store loop, each row's dependent loads would wait behind the
+  // previous row's stores, a memory round trip per row.
   const auto rows = gmem(C.rows);
-  const auto rect = gmem(reinterpret_cast<const int *>(C.rect));   // (j0, k0, nj, nk) per block
   const auto moff = gmem(C.moff), mem = gmem(C.mem);
   const auto tcol0 = gmem(C.tcol0);
   const auto cscale = gmem(P.cscale), coef = gmem(P.coef);
   const auto pscale = gmem(C.pscale);
   const auto part = gmem(reinterpret_cast<float *>(C.partial));
-  // this lane's two expansion pairs, read once for all its rows: l = 0
+  double *e_sc = reinterpret_cast<double *>(lds);   // [TMV] row scale
+  double *e_c0 = e_sc + TMV;                        // [TMV] l = 0 coefficient (expansion)
+  int *e_shell = reinterpret_cast<int *>(e_c0 + TMV);   // [TMV] shell (expansion)
+  __syncthreads();   // the last stage's LDS reads are done
+  // This lane's two expansion pairs, read once for all its rows: l = 0
   // kernel and the member cells of both blocks, [0] the rep and [1] the
-  // mirror (rect: first cell and extent; CSR: member range in bcell .. bnj;
-  // a block of more than kLargeBlock cells only gets its first cell here,
-  // launch_large copies it to the rest)
+  // mirror (rect: first cell and extent; CSR: member range in bcell .. bnj).
+  // The loads go in two rounds: the pairs, their l = 0 kernels and the tile
+  // rows' shells; then the blocks' rectangles or member ranges and the
+  // shells' scales and l = 0 coefficients (staged in LDS).
+  typedef int i4v __attribute__((ext_vector_type(4)));
   bool bok[2] = {false, false}, bmir[2] = {false, false};
   double bt0[2] = {0.0, 0.0};
   int bcell[2][2] = {}, bnj[2][2] = {}, bnk[2][2] = {};
+  i2v pr[2] = {};
+  int shell_t = 0;
+  const bool stager = tid < TMV && m0 + tid < M;
   if (EXPAND) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -271,16 +283,29 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
       bok[b] = q < N;
       if (!bok[b]) continue;
       bt0[b] = tcol0[q];
-      const i2v pr = gmem(reinterpret_cast<const i2v *>(C.pairs))[q];
-      bmir[b] = pr.y != pr.x;
+      pr[b] = gmem(reinterpret_cast<const i2v *>(C.pairs))[q];
+    }
+    if (stager) shell_t = rows[m0 + tid];
+  } else if (stager) {
+    e_sc[tid] = pscale[m0 + tid];
+  }
+  if (EXPAND) {
+    const auto rect4 = gmem(reinterpret_cast<const i4v *>(C.rect));
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (!bok[b]) continue;
+      bmir[b] = pr[b].y != pr[b].x;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int blk = h ? pr.y : pr.x;
+        const int blk = h ? pr[b].y : pr[b].x;
         if (C.rect != nullptr) {
-          bcell[b][h] = rect[4 * blk] * P.nphi + rect[4 * blk + 1];
-          bnj[b][h] = rect[4 * blk + 2];
-          bnk[b][h] = rect[4 * blk + 3];
-          if (bnj[b][h] * bnk[b][h] > kLargeBlock) bnj[b][h] = bnk[b][h] = 1;   // first cell; launch_large broadcasts
+          const i4v rc = rect4[blk];   // (j0, k0, nj, nk)
+          bcell[b][h] = rc.x * P.nphi + rc.y;
+          bnj[b][h] = rc.z;
+          bnk[b][h] = rc.w;
+          // first cell only: launch_large (past kLargeBlock cells) or the
+          // broadcast phase (merged blocks of a banded class) writes the rest
+          if (bnj[b][h] * bnk[b][h] > kLargeBlock || C.bands != nullptr) bnj[b][h] = bnk[b][h] = 1;
         } else {
           bcell[b][h] = moff[blk];
           bnj[b][h] = moff[blk + 1];
@@ -288,17 +313,23 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
         }
       }
     }
+    if (stager) {
+      e_shell[tid] = shell_t;
+      e_sc[tid] = cscale[shell_t];
+      e_c0[tid] = coef[(size_t)shell_t * P.namp];
+    }
   }
+  __syncthreads();
 #pragma unroll
   for (int a = 0; a < AT; ++a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = m0 + wm * (TMV / 2) + a * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+      const int lr = wm * (TMV / 2) + a * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5), row = m0 + lr;
       if (row >= M) continue;
       if (EXPAND) {
-        const int shell = rows[row];
-        const double sc = cscale[shell];
-        const double c0 = coef[(size_t)shell * P.namp];   // l = 0 coefficient, FP64
+        const int shell = e_shell[lr];
+        const double sc = e_sc[lr];
+        const double c0 = e_c0[lr];   // l = 0 coefficient, FP64
         const auto dst = gmem(phi + (size_t)shell * P.ncell);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -325,7 +356,7 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
         }
       } else {
         // FP32 partial sums (the accumulator type; the row scale is a power of two)
-        const float sc = (float)pscale[row];
+        const float sc = (float)e_sc[lr];
         const auto out = part + ((size_t)split * M + row) * P.namp_m;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {

@@ -34,6 +34,8 @@ constexpr int kBandRows = 8;
 constexpr int kBandCopyRows = 4;
 // FP16 x2: pairs of one shell's row split into planes per workgroup
 constexpr int kSplitRowChunk = 1024;
+// bands of merged blocks per broadcast workgroup
+constexpr int kBcastBands = 4;
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.
 struct GaussRule {
@@ -58,6 +60,10 @@ struct ClassDev {
   // for other block maps
   const int4 *bands;
   int32_t nbands;
+  // indices of the bands of merged blocks (kind 1): the expansion writes the
+  // first cell of each such block, the broadcast phase the rest
+  const int32_t *bcast;
+  int32_t nbcast;
   // The contractions run over block pairs.  With the mirror fold (PlanDev::
   // fold) a pair is a block and its mirror image about the equator (theta ->
   // pi - theta), whose kernels differ only by the sign (-1)^(l+m); a block
@@ -127,6 +133,7 @@ struct PlanDev {
   int32_t mono_stride;
   int32_t pack_parts;       // packing workgroups per shell
   int32_t split_chunks;     // FP16 x2: row-split workgroups per shell (kSplitRowChunk pairs each), else 0
+  int32_t bcast_chunks;     // broadcast workgroups per shell (kBcastBands bands each), 0: none
   int32_t wg_mom, wg_exp;   // workgroups of the two contraction launches
   int32_t tm_mom, tm_exp;   // output tile heights of the two contractions
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
@@ -149,7 +156,7 @@ struct PlanDev {
 
 // Phases of one solve; a launch of phase h covers the workgroups
 // [prefix[h][f], prefix[h][f+1]) of every field f of a batch.
-enum Phase { PH_PACK = 0, PH_SPLITROWS, PH_MOMENT, PH_REDUCE, PH_SCAN, PH_COEF, PH_EXPAND, PH_COUNT };
+enum Phase { PH_PACK = 0, PH_SPLITROWS, PH_MOMENT, PH_REDUCE, PH_SCAN, PH_COEF, PH_EXPAND, PH_BCAST, PH_COUNT };
 
 // Per-field device pointers of one solve.
 struct SolveIO {
@@ -249,6 +256,8 @@ hipError_t launch_stamp_reset(const BatchDev &B, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *stamps, int idx, hipStream_t s);   // stamps[idx] = wall clock
 hipError_t launch_pack(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_split_rows(const BatchDev &B, int wgs, hipStream_t s);   // FP16 x2 only
+// every cell of the merged blocks of banded classes from the block's first cell
+hipError_t launch_bcast(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_moment(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_reduce(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_scan(const BatchDev &B, int wgs, int modes, hipStream_t s);

@@ -3,10 +3,11 @@
 //
 // A field's work is its phases in solve order (packing, FP16 row split,
 // moment contraction, split-K sum, radial scan, coefficient step, expansion
-// contraction); phase h is a run of items, each item a group of consecutive
-// workgroups of the phase's own kernel (several for the light phases, so
-// that the cost of taking an item is spread over enough work), run with the
-// same device code, so results are bitwise those of the per-phase launches.
+// contraction, broadcast of merged blocks); phase h is a run of items, each
+// item a group of consecutive workgroups of the phase's own kernel (several
+// for the light phases, so that the cost of taking an item is spread over
+// enough work), run with the same device code, so results are bitwise those
+// of the per-phase launches.
 //
 // The host lays the items out as one queue per XCD (an accelerator complex
 // die, with its own L2): whole fields, spread over the queues by their
@@ -25,6 +26,7 @@
 // it (so later waits end too) and the launch ends normally; the host reports
 // the error after synchronising.
 #define MPOLE_ITEM_LOOP 1
+#include "bcast_impl.h"
 #include "coef_impl.h"
 #include "gemm_f64_impl.h"
 #include "gemm_split_impl.h"
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) __attribute__((amdgpu_waves_per_eu
             if constexpr (KIND == 0) expand_f64_item(B, J, reinterpret_cast<double *>(lds));
             else split_item<KIND, true>(B, J, reinterpret_cast<u4 *>(lds));
             break;
+          case PH_BCAST: bcast_item(B, J); break;
           default: break;
         }
       }

@@ -96,13 +96,14 @@ struct ClassHost {
   std::vector<int32_t> sep_src, sep_avg;   // separable path: blocks on merged rows, blocks with > 1 member
   std::vector<int32_t> large, lidx;        // blocks of more than kLargeBlock cells; index in `large` per block
   std::vector<int32_t> bands;              // theta bands (j0, nj, nk, kind), or empty
+  std::vector<int32_t> bcast;              // indices of the bands of merged blocks (kind 1)
   std::vector<int32_t> mirb;               // mirror block of each block (theta -> pi - theta), or empty
   std::vector<int32_t> pairs;              // (rep, mir) per pair
   std::vector<int32_t> ptasks;             // band packing tasks (j0, nj, nk, q0), or empty
   int npair = 0, npair_pad = 0, npack = 0;
   size_t off_ptasks = 0;
   size_t off_pairs = 0, off_tm = 0, off_te = 0, off_pack_o = 0, off_ppacks_o = 0;
-  size_t off_lidx = 0, off_bands = 0;
+  size_t off_lidx = 0, off_bands = 0, off_bcast = 0;
   size_t off_sep_src = 0, off_sep_avg = 0;
   size_t off_span0 = 0, off_pspan0 = 0;
   size_t off_rect = 0;
@@ -406,6 +407,9 @@ int build_plan(const mpole_mesh *m, mpole_plan_t *p) {
       }
       if (!ok) C.bands.clear();
     }
+    C.bcast.clear();
+    for (size_t x = 0; x + 3 < C.bands.size(); x += 4)
+      if (C.bands[x + 3] == 1) C.bcast.push_back((int32_t)(x / 4));
     // mirror image of every block about the equator (row j -> ntheta-1-j),
     // when the map is symmetric: the mirror cells of a block's members are
     // exactly the members of one block
@@ -687,6 +691,7 @@ void layout_plan(mpole_plan_t *p, int target) {
     C.off_pspan0 = take(sizeof(int32_t) * C.pspan0.size());
     C.off_lidx = take(sizeof(int32_t) * C.lidx.size());
     C.off_bands = take(sizeof(int32_t) * C.bands.size());
+    C.off_bcast = take(sizeof(int32_t) * C.bcast.size());
     const size_t dense = p->sep ? 0 : 1;   // the separable path has no block x mode tables
     C.off_table = take(dense * sizeof(double) * (size_t)C.nblocks_pad * p->namp);
     C.off_pairs = take(sizeof(int32_t) * C.pairs.size());
@@ -804,6 +809,15 @@ int mpole_plan_folded(mpole_plan p) { return p && p->fold ? 1 : 0; }
 
 namespace {
 
+// Broadcast workgroups per shell (dense paths): kBcastBands bands of merged
+// blocks each, for the class with the most such bands.
+int bcast_chunks(const mpole_plan_t *p) {
+  if (p->sep) return 0;
+  size_t n = 0;
+  for (const auto &C : p->cls) n = std::max(n, C.bcast.size());
+  return (int)((n + kBcastBands - 1) / kBcastBands);
+}
+
 // FP16 x2 row-split workgroups per shell: chunks of kSplitRowChunk pairs of
 // the longest padded row of any class.
 int split_chunks(const mpole_plan_t *p) {
@@ -821,6 +835,7 @@ int phase_wgs_host(const mpole_plan_t *p, int h) {
     case PH_SCAN: return p->namp / p->scan_modes;
     case PH_COEF: return (p->nplanes || (p->fold && !p->sep)) ? p->nr : 0;
     case PH_EXPAND: return p->wg_exp;
+    case PH_BCAST: return p->nr * bcast_chunks(p);
   }
   return 0;
 }
@@ -833,6 +848,7 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
   D = PlanDev{};
   D.pack_parts = p->mono_stride;
   D.split_chunks = p->precision == MPOLE_FP16X2 ? split_chunks(p) : 0;
+  D.bcast_chunks = bcast_chunks(p);
   D.wg_mom = p->wg_mom;
   D.tm_mom = p->tm_mom;
   D.tm_exp = p->tm_exp;
@@ -903,6 +919,8 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
     C.lidx = H.lidx.empty() ? nullptr : (const int32_t *)(ws + H.off_lidx);
     C.bands = H.bands.empty() ? nullptr : (const int4 *)(ws + H.off_bands);
     C.nbands = (int32_t)(H.bands.size() / 4);
+    C.bcast = H.bcast.empty() ? nullptr : (const int32_t *)(ws + H.off_bcast);
+    C.nbcast = (int32_t)H.bcast.size();
     D.max_bands = std::max(D.max_bands, C.nbands);
     C.table = (double *)(ws + H.off_table);
     C.pairs = (const int2 *)(ws + H.off_pairs);
@@ -1030,6 +1048,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
     if (e == hipSuccess) e = upload(ws, H.off_pspan0, H.pspan0.data(), sizeof(int32_t) * H.pspan0.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_lidx, H.lidx.data(), sizeof(int32_t) * H.lidx.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_bands, H.bands.data(), sizeof(int32_t) * H.bands.size(), s);
+    if (e == hipSuccess) e = upload(ws, H.off_bcast, H.bcast.data(), sizeof(int32_t) * H.bcast.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_pairs, H.pairs.data(), sizeof(int32_t) * H.pairs.size(), s);
     if (e == hipSuccess) e = upload(ws, H.off_ptasks, H.ptasks.data(), sizeof(int32_t) * H.ptasks.size(), s);
   }
@@ -1110,6 +1129,7 @@ hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, int scan_
   if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] {
     hipError_t r = launch_expand(B, k, wgs[PH_EXPAND], s);
     for (int q = 0; q < nlarge && r == hipSuccess; ++q) r = launch_large(*large[q].P, kLargeBcast, nullptr, large[q].phi, s);
+    if (r == hipSuccess) r = launch_bcast(B, wgs[PH_BCAST], s);
     return r;
   });
   return e;
