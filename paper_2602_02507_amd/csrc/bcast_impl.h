@@ -13,22 +13,29 @@
 namespace mpole {
 namespace {
 
-// Bands [kBcastBands c, kBcastBands (c + 1)) of the merged-block bands of
-// shell i, item J.local = i * bcast_chunks + c.
+// Item J.local: bands [kBcastBands c, kBcastBands (c + 1)) of the
+// merged-block bands of shell i, where bcast_pre[i] <= J.local <
+// bcast_pre[i + 1] and c = J.local - bcast_pre[i] (every item has bands).
 __device__ __forceinline__ void bcast_item(const BatchDev &B, const Job &J) {
   const PlanDev &P = J.P;
-  const int i = J.local / P.bcast_chunks, c = J.local % P.bcast_chunks;
+  int lo = 0, hi = P.nr - 1;   // the shell: last i with bcast_pre[i] <= J.local
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ld_const(P.bcast_pre + mid) <= J.local) lo = mid; else hi = mid - 1;
+  }
+  const int i = lo, t0 = (J.local - ld_const(P.bcast_pre + i)) * kBcastBands;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
+  const int nb = min(kBcastBands, C.nbcast - t0);
   const auto phi = gmem(J.io.phi + (size_t)i * P.ncell);
-  const int t0 = c * kBcastBands, nb = min(kBcastBands, C.nbcast - t0);
-  // up to kBcastBands bands of up to kBcastCells cells per thread: all loads
-  // are issued before the stores
+  // up to kBcastCells cells per thread and band with all loads issued before
+  // the stores, then what is left of taller bands a cell at a time
   constexpr int kBcastCells = 4;
   double v[kBcastBands][kBcastCells];
   int dst[kBcastBands][kBcastCells];
   int4 bd[kBcastBands];
 #pragma unroll
-  for (int t = 0; t < kBcastBands; ++t) bd[t] = t < nb ? ld_const(C.bands + ld_const(C.bcast + t0 + t)) : int4{0, 0, 1, 1};
+  for (int t = 0; t < kBcastBands; ++t)
+    bd[t] = t < nb ? ld_const(C.bands + ld_const(C.bcast + t0 + t)) : int4{0, 0, 1, 1};
 #pragma unroll
   for (int t = 0; t < kBcastBands; ++t)
 #pragma unroll
@@ -44,7 +51,6 @@ __device__ __forceinline__ void bcast_item(const BatchDev &B, const Job &J) {
 #pragma unroll
     for (int u = 0; u < kBcastCells; ++u)
       if (dst[t][u] >= 0) phi[dst[t][u]] = v[t][u];
-  // bands of more than kBcastCells x 256 cells: the rest, a cell at a time
   for (int t = 0; t < nb; ++t) {
     const int4 bt = ld_const(C.bands + ld_const(C.bcast + t0 + t));
     for (int q = item_tid() + kBcastCells * 256; q < bt.y * P.nphi; q += 256) {

@@ -34,7 +34,7 @@ constexpr int kBandRows = 8;
 constexpr int kBandCopyRows = 4;
 // FP16 x2: pairs of one shell's row split into planes per workgroup
 constexpr int kSplitRowChunk = 1024;
-// bands of merged blocks per broadcast workgroup
+// bands of merged blocks copied per group of loads in the broadcast phase
 constexpr int kBcastBands = 4;
 
 // Gauss-Legendre rule on [-1, 1], computed on the host.
@@ -133,7 +133,7 @@ struct PlanDev {
   int32_t mono_stride;
   int32_t pack_parts;       // packing workgroups per shell
   int32_t split_chunks;     // FP16 x2: row-split workgroups per shell (kSplitRowChunk pairs each), else 0
-  int32_t bcast_chunks;     // broadcast workgroups per shell (kBcastBands bands each), 0: none
+  const int32_t *bcast_pre; // [nr + 1] first broadcast workgroup of each shell (kBcastBands bands each)
   int32_t wg_mom, wg_exp;   // workgroups of the two contraction launches
   int32_t tm_mom, tm_exp;   // output tile heights of the two contractions
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer
