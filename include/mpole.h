@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define MPOLE_ABI_VERSION 1
+#define MPOLE_ABI_VERSION 2
 #define MPOLE_LMAX_MAX 64
 
 typedef enum {
@@ -219,12 +219,13 @@ int mpole_plan_copy_table(mpole_plan plan, int32_t cls, double *host_out, int64_
  * phase, and clears the record.  Phases: MPOLE_PHASE_PACK (density
  * streaming), _MOMENT (moment contraction), _REDUCE (split-K sum), _SCAN
  * (radial sums and coefficients), _SPLIT (coefficient split, split
- * precisions only), _EXPAND (expansion contraction and potential streaming,
- * including the broadcast of merged blocks' values to their cells).
+ * precisions only), _EXPAND (expansion contraction and potential streaming),
+ * _BCAST (the potential of merged blocks of banded coarsening classes copied
+ * from each block's first cell to its other cells).
  */
 enum {
   MPOLE_PHASE_PACK = 0, MPOLE_PHASE_MOMENT = 1, MPOLE_PHASE_REDUCE = 2, MPOLE_PHASE_SCAN = 3,
-  MPOLE_PHASE_SPLIT = 4, MPOLE_PHASE_EXPAND = 5, MPOLE_NPHASES = 6
+  MPOLE_PHASE_SPLIT = 4, MPOLE_PHASE_EXPAND = 5, MPOLE_PHASE_BCAST = 6, MPOLE_NPHASES = 7
 };
 int mpole_plan_set_timing(mpole_plan plan, int enable);
 int mpole_plan_phase_ms(mpole_plan plan, double *total_ms, int64_t *launches);

@@ -13,17 +13,12 @@
 namespace mpole {
 namespace {
 
-// Item J.local: bands [kBcastBands c, kBcastBands (c + 1)) of the
-// merged-block bands of shell i, where bcast_pre[i] <= J.local <
-// bcast_pre[i + 1] and c = J.local - bcast_pre[i] (every item has bands).
+// Item J.local = (shell i, first band t0): bands [t0, t0 + kBcastBands) of
+// the shell's merged-block bands (every item has bands).
 __device__ __forceinline__ void bcast_item(const BatchDev &B, const Job &J) {
   const PlanDev &P = J.P;
-  int lo = 0, hi = P.nr - 1;   // the shell: last i with bcast_pre[i] <= J.local
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ld_const(P.bcast_pre + mid) <= J.local) lo = mid; else hi = mid - 1;
-  }
-  const int i = lo, t0 = (J.local - ld_const(P.bcast_pre + i)) * kBcastBands;
+  const int2 it = ld_const(P.bcast_items + J.local);
+  const int i = it.x, t0 = it.y;
   const ClassDev C = ld_const(P.classes + ld_const(P.shell_class + i));
   const int nb = min(kBcastBands, C.nbcast - t0);
   const auto phi = gmem(J.io.phi + (size_t)i * P.ncell);

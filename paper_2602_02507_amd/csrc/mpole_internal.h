@@ -133,7 +133,7 @@ struct PlanDev {
   int32_t mono_stride;
   int32_t pack_parts;       // packing workgroups per shell
   int32_t split_chunks;     // FP16 x2: row-split workgroups per shell (kSplitRowChunk pairs each), else 0
-  const int32_t *bcast_pre; // [nr + 1] first broadcast workgroup of each shell (kBcastBands bands each)
+  const int2 *bcast_items;  // broadcast workgroups: (shell, first band), kBcastBands bands each
   int32_t wg_mom, wg_exp;   // workgroups of the two contraction launches
   int32_t tm_mom, tm_exp;   // output tile heights of the two contractions
   double *edge_r, *edge_i;  // [nr+1][namp] edge moments when the caller passes no buffer

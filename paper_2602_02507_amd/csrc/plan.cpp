@@ -156,7 +156,7 @@ struct mpole_plan_t {
   std::vector<int32_t> pos_m, perm_m, perm_e;
   size_t off_pos_m = 0, off_perm_m = 0, off_perm_e = 0, off_coef_e = 0;
   int scan_modes = kScanModesWide;   // modes per radial-scan workgroup
-  size_t off_plandev = 0, off_prefix = 0, off_bcast_pre = 0;
+  size_t off_plandev = 0, off_prefix = 0, off_bcast_items = 0;
   size_t solve_off = 0, solve_bytes = 0;        // per-solve region: start in the workspace, size
   size_t off_plandev_s = 0, off_classes_s = 0;  // device views of the static-scratch solve
   int wg_mom = 0, wg_exp = 0;
@@ -179,7 +179,7 @@ struct mpole_plan_t {
   std::vector<ClassDev> cdev_s;
   SepDev sdev_s{};
   std::vector<int32_t> prefix;   // [PH_COUNT][2] single-plan phase prefix sums
-  std::vector<int32_t> bcast_pre; // [nr + 1] first broadcast workgroup of each shell
+  std::vector<int32_t> bcast_items; // broadcast workgroups: (shell, first band) pairs
 };
 
 namespace {
@@ -743,7 +743,7 @@ void layout_plan(mpole_plan_t *p, int target) {
   p->off_plandev = take(sizeof(PlanDev));
   p->off_prefix = take(sizeof(int32_t) * PH_COUNT * 2);
   bcast_layout(p);
-  p->off_bcast_pre = take(sizeof(int32_t) * (p->nr + 1));
+  p->off_bcast_items = take(sizeof(int32_t) * p->bcast_items.size());
   p->off_plandev_s = take(sizeof(PlanDev));
   p->off_classes_s = take(sizeof(ClassDev) * p->ncls);
   p->solve_off = off;
@@ -814,12 +814,13 @@ int mpole_plan_folded(mpole_plan p) { return p && p->fold ? 1 : 0; }
 namespace {
 
 // Broadcast workgroups of a dense plan: kBcastBands merged-block bands of a
-// shell each; bcast_pre[i] = the first workgroup of shell i.
+// shell each, as (shell, first band) pairs.
 void bcast_layout(mpole_plan_t *p) {
-  p->bcast_pre.assign(p->nr + 1, 0);
+  p->bcast_items.clear();
+  if (p->sep) return;
   for (int i = 0; i < p->nr; ++i) {
-    const int n = p->sep ? 0 : (int)p->cls[p->shell_class[i]].bcast.size();
-    p->bcast_pre[i + 1] = p->bcast_pre[i] + (n + kBcastBands - 1) / kBcastBands;
+    const int n = (int)p->cls[p->shell_class[i]].bcast.size();
+    for (int t = 0; t < n; t += kBcastBands) p->bcast_items.insert(p->bcast_items.end(), {i, t});
   }
 }
 
@@ -840,7 +841,7 @@ int phase_wgs_host(const mpole_plan_t *p, int h) {
     case PH_SCAN: return p->namp / p->scan_modes;
     case PH_COEF: return (p->nplanes || (p->fold && !p->sep)) ? p->nr : 0;
     case PH_EXPAND: return p->wg_exp;
-    case PH_BCAST: return p->bcast_pre.empty() ? 0 : p->bcast_pre[p->nr];
+    case PH_BCAST: return (int)(p->bcast_items.size() / 2);
   }
   return 0;
 }
@@ -853,7 +854,7 @@ void make_views(const mpole_plan_t *p, char *ws, char *sv, ClassDev *classes_dev
   D = PlanDev{};
   D.pack_parts = p->mono_stride;
   D.split_chunks = p->precision == MPOLE_FP16X2 ? split_chunks(p) : 0;
-  D.bcast_pre = (const int32_t *)(ws + p->off_bcast_pre);
+  D.bcast_items = (const int2 *)(ws + p->off_bcast_items);
   D.wg_mom = p->wg_mom;
   D.tm_mom = p->tm_mom;
   D.tm_exp = p->tm_exp;
@@ -1068,7 +1069,7 @@ int bind_plan(mpole_plan_t *p, void *dev_ws, size_t bytes, void *stream) {
   for (int h = 0; h < PH_COUNT; ++h) p->prefix[2 * h + 1] = phase_wgs_host(p, h);
   if (e == hipSuccess) e = upload(ws, p->off_plandev, &p->dev, sizeof(PlanDev), s);
   if (e == hipSuccess) e = upload(ws, p->off_prefix, p->prefix.data(), sizeof(int32_t) * p->prefix.size(), s);
-  if (e == hipSuccess) e = upload(ws, p->off_bcast_pre, p->bcast_pre.data(), sizeof(int32_t) * p->bcast_pre.size(), s);
+  if (e == hipSuccess) e = upload(ws, p->off_bcast_items, p->bcast_items.data(), sizeof(int32_t) * p->bcast_items.size(), s);
   if (e == hipSuccess && p->static_ok) {
     e = upload(ws, p->off_plandev_s, &p->dev_s, sizeof(PlanDev), s);
     if (e == hipSuccess) e = upload(ws, p->off_classes_s, p->cdev_s.data(), sizeof(ClassDev) * p->ncls, s);
@@ -1135,9 +1136,10 @@ hipError_t run_solve(const BatchDev &B, int precision, const int *wgs, int scan_
   if (e == hipSuccess && phi) e = timed(MPOLE_PHASE_EXPAND, [&] {
     hipError_t r = launch_expand(B, k, wgs[PH_EXPAND], s);
     for (int q = 0; q < nlarge && r == hipSuccess; ++q) r = launch_large(*large[q].P, kLargeBcast, nullptr, large[q].phi, s);
-    if (r == hipSuccess) r = launch_bcast(B, wgs[PH_BCAST], s);
     return r;
   });
+  if (e == hipSuccess && phi && wgs[PH_BCAST] > 0)
+    e = timed(MPOLE_PHASE_BCAST, [&] { return launch_bcast(B, wgs[PH_BCAST], s); });
   return e;
 }
 

@@ -32,7 +32,7 @@ EXPORTS = ("mpole_abi_version", "mpole_last_error", "mpole_plan_create", "mpole_
            "mpole_batch_solve", "mpole_batch_field_ms", "mpole_batch_destroy", "mpole_batch_set_launch",
            "mpole_batch_launch", "mpole_batch_launch_note", "mpole_batch_check")
 LAUNCH_PHASES, LAUNCH_PERSISTENT, LAUNCH_PERSISTENT_FORCED = 0, 1, 2
-PHASES = ("pack", "moment", "reduce", "scan", "split", "expand")
+PHASES = ("pack", "moment", "reduce", "scan", "split", "expand", "bcast")
 
 
 class Tuning(ctypes.Structure):
@@ -237,10 +237,10 @@ class HostPlan:
 
     def phase_ms(self):
         """{phase: (total ms, launches)} since timing was enabled or last read."""
-        ms = (ctypes.c_double * 6)()
-        n = (ctypes.c_int64 * 6)()
+        ms = (ctypes.c_double * len(PHASES))()
+        n = (ctypes.c_int64 * len(PHASES))()
         _check(lib().mpole_plan_phase_ms(self.handle, ms, n))
-        return {PHASES[k]: (ms[k], n[k]) for k in range(6)}
+        return {PHASES[k]: (ms[k], n[k]) for k in range(len(PHASES))}
 
     def __del__(self):
         h = getattr(self, "handle", None)

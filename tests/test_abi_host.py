@@ -25,7 +25,7 @@ def test_library_exports_every_declared_function():
     L = mpole.lib()
     for n in names:
         assert hasattr(L, n), n
-    assert L.mpole_abi_version() == 1
+    assert L.mpole_abi_version() == 2
 
 
 def test_plan_sizes():

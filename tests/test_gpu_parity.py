@@ -175,3 +175,36 @@ def test_optional_outputs_and_determinism():
         assert torch.equal(a[k], b[k]), k
     assert torch.equal(only_phi["phi"], a["phi"])
     assert torch.equal(only_ang["ang"], a["ang"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_phase_timing_and_merged_block_broadcast(precision):
+    """Per-phase timing reports every phase of a dense solve; on a coarsened
+    mesh (merged blocks in theta bands) the broadcast phase runs and every
+    member cell of a merged block carries its block's value; without merged
+    blocks the broadcast phase has no launch."""
+    torch = _torch()
+    from paper_2602_02507_amd import mpole
+    for merged in (True, False):
+        mesh = wl.production_mesh(6, nr=40, ntheta=32, nphi=64, merged=merged)
+        rho = torch.from_numpy(wl.production_density(mesh, seed=11)).cuda()
+        plan = mpole.Plan.from_mesh(mesh, precision=precision)
+        plan.set_timing(True)
+        plan.phase_ms()
+        phi = plan.solve(rho)["phi"]
+        ph = plan.phase_ms()
+        plan.set_timing(False)
+        assert set(ph) == set(mpole.PHASES)
+        for k in ("pack", "moment", "reduce", "scan", "expand"):
+            assert ph[k][1] == 1 and ph[k][0] > 0, (k, ph[k])
+        assert ph["bcast"][1] == (1 if merged else 0), ph["bcast"]
+        if merged:
+            got = phi.cpu().numpy()
+            blocks = np.asarray(mesh.class_block)
+            cls = np.asarray(mesh.shell_class)
+            for i in (0, 5, 39):
+                ids = blocks[cls[i]].reshape(mesh.ntheta, mesh.nphi)
+                row = got[i]
+                for b in np.unique(ids)[:200]:
+                    v = row[ids == b]
+                    assert np.all(v == v[0]), (i, b)
