@@ -422,6 +422,293 @@ __global__ __launch_bounds__(256) void k_sep_phi_syn_bf16(PlanDev P, SepDev S, d
   }
 }
 
+// ---- whole-tile forms --------------------------------------------------------
+//
+// Vector memory counters retire in issue order, loads and stores alike, so a
+// wait for a load also waits for every load and store issued before it, and
+// at a join of branches the compiler waits for the longest count any path
+// needs.  The two forms below (the host picks them when the mesh has whole K
+// steps and tiles) keep every load a wait is for ahead of the stores and
+// other loads that need not finish, and their steady state has no branch
+// around a memory access, so each wait covers exactly the loads it needs.
+
+// Analysis on whole K steps (nphi a multiple of 32, at most kAnalFullPhi;
+// 16-byte aligned rows): the density and trig-fragment loads of step ks + 1
+// are issued before step ks is computed, into the other of two register sets
+// (no copies between them); dphi, the same for every row, comes from an LDS
+// copy of the row (dynamic LDS, nphi doubles).  Every wavefront runs the same
+// step sequence (a row tile past the mesh computes on row 0 of the shell and
+// stores nothing).  Same arithmetic, in the same order, as
+// k_sep_phi_anal_bf16.
+constexpr int kAnalFullPhi = 1024;
+template <int MT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT >= 5 ? 3 : 4))) void k_sep_phi_anal_bf16_full(
+    PlanDev P, SepDev S, const double *rho) {
+  constexpr int NF = MT > 0 ? MT * 3 * 64 : 64;   // fragment entries (16 bytes) per K step
+  constexpr int CP = (NF + 255) / 256;             // copied per thread
+  __shared__ u4 As[2][NF];
+  extern __shared__ double Ds[];                   // TW row 0: dphi_k
+  const int lane = threadIdx.x & 63, quad = lane >> 4;
+  const int i = blockIdx.y;
+  const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const bool tile_in = j0 < P.ntheta;   // wavefront-uniform
+  const int j = j0 + (lane & 15);
+  const bool jin = j < P.ntheta;
+  const int jr = jin ? j : (tile_in ? j0 : 0);
+  const long o = (long)i * P.ncell + (long)jr * P.nphi;
+  const int code = S.rowalt != nullptr ? S.rowalt[(long)i * P.ntheta + jr] : 0;
+  const int fnk = code >= 2 ? 1 << (code - 1) : 1;
+  const double *row = (code == 1 ? S.shat : rho) + o + 8 * quad;   // this lane's cells of step 0
+  const int nks = S.ks_a;                                    // >= 1
+  for (int k = threadIdx.x; k < P.nphi; k += 256) Ds[k] = S.tw[k];   // made visible by the first barrier
+
+  f4 acc[MT > 0 ? MT : 1];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = f4{};
+  double rs = 0.0;
+
+  auto load = [&](double (&v)[8], int ks) __attribute__((always_inline)) { load8(row + 32 * ks, v); };
+  u4 fr[CP];
+  auto fetch = [&](int ks) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      const int e = min((int)threadIdx.x + 256 * c, NF - 1);
+      if (MT > 0) fr[c] = frag(S.twf, (long)ks * (NF / 64) + e / 64, e % 64);
+    }
+  };
+  auto put = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      if (MT > 0 && e < NF) As[buf][e] = fr[c];
+    }
+  };
+  auto step = [&](double (&v)[8], int ks) __attribute__((always_inline)) {
+    double d[8];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      const double2 w = *reinterpret_cast<const double2 *>(Ds + 32 * ks + 8 * quad + e);
+      d[e] = w.x;
+      d[e + 1] = w.y;
+    }
+    if (fnk > 1) {   // dphi-weighted means of the lane's aligned groups of fnk cells
+      double g[8], dw[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        g[e] = d[e] * v[e];
+        dw[e] = d[e];
+      }
+#pragma unroll
+      for (int m = 1; m < 8; m <<= 1)
+        if (m < fnk) {
+          double tg[8], tw[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            tg[e] = g[e] + g[e ^ m];
+            tw[e] = dw[e] + dw[e ^ m];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            g[e] = tg[e];
+            dw[e] = tw[e];
+          }
+        }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = dw[e] > 0.0 ? g[e] / dw[e] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rs += d[e] * v[e];
+    if constexpr (MT > 0) {
+      u4 b[3];
+      split8(v, b);
+      const u4 *st = As[ks & 1];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        u4 a[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a[q] = st[(m * 3 + q) * 64 + lane];
+        acc[m] = mma6(a, b, acc[m]);
+      }
+    }
+  };
+  double va[8], vb[8];
+  fetch(0);
+  load(va, 0);
+  put(0);
+  // drain the vector memory counter once: with nothing in flight on entry,
+  // the loop head needs no wait for registers the prologue loaded
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // gfx9 encoding: vmcnt(0), expcnt and lgkmcnt left free
+  __syncthreads();
+  // step ks reads buffer ks & 1; the fragments of step ks + 1 go to the other
+  // buffer, last read in step ks - 1 (past the barrier).  The last step
+  // fetches its own data again into the unused buffer and registers.
+  for (int ks = 0;; ks += 2) {
+    const int k1 = min(ks + 1, nks - 1);
+    fetch(k1);
+    load(vb, k1);
+    step(va, ks);
+    put((ks + 1) & 1);
+    __syncthreads();
+    if (ks + 1 >= nks) break;
+    const int k2 = min(ks + 2, nks - 1);
+    fetch(k2);
+    load(va, k2);
+    step(vb, ks + 1);
+    put(ks & 1);
+    __syncthreads();
+    if (ks + 2 >= nks) break;
+  }
+  if (!tile_in) return;
+  rs += __shfl_xor(rs, 16, 64);
+  rs += __shfl_xor(rs, 32, 64);
+  const auto F = gmem(S.f) + (long)i * S.tpad * P.ntheta;
+  if (!jin) return;
+  if (quad == 0) F[j] = rs;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = 1 + 16 * m + 4 * quad + r;
+      if (t <= 2 * P.lmax) F[(long)t * P.ntheta + j] = (double)acc[m][r];
+    }
+}
+
+// Synthesis on whole tiles (nphi a multiple of 32, ntheta a multiple of 64,
+// an even number of phi tiles per wavefront): a workgroup's four wavefronts
+// (64 rows of one shell) share each tile pair's trig fragments and the TT row
+// 0 and dphi values of its 32 cells through LDS, two buffers deep.  The
+// loads of pair p + 1 are issued before pair p is computed and stored, and
+// written to LDS after the stores without waiting for them; the G loads of the
+// prologue are unconditional.  Same arithmetic, in the same order, as
+// k_sep_phi_syn_bf16.
+template <int NKS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NKS >= 3 ? 3 : 4))) void k_sep_phi_syn_bf16_full(PlanDev P, SepDev S, double *phi, int ntw) {
+  constexpr int NE = 2 * (NKS > 0 ? NKS : 1) * 3 * 64;   // fragment entries (16 bytes) of a tile pair
+  constexpr int CP = (NE + 255) / 256;                    // staged per thread
+  __shared__ u4 Bs[2][NE];
+  __shared__ double Cs[2][64];   // per pair: TT row 0 of its 32 cells, then their dphi
+  const int lane = threadIdx.x & 63, quad = lane >> 4;
+  const int i = blockIdx.y;
+  const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int nt0 = blockIdx.z * ntw, npairs = (min(nt0 + ntw, S.nt_s) - nt0) / 2;
+  const int ja = j0 + (lane & 15);   // this lane's G row (every row is in the mesh)
+  const int np = P.nphi;
+  const double *G = S.g + (long)i * S.tpad * P.ntheta;
+  const int tmax = 2 * P.lmax;
+
+  u4 a[NKS > 0 ? NKS : 1][3];
+  {
+    double v[NKS > 0 ? NKS : 1][8];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int t = 1 + 32 * ks + 8 * quad + e;
+        const double x = *gmem(G + (long)min(t, tmax) * P.ntheta + ja);
+        v[ks][e] = t <= tmax ? x : 0.0;
+      }
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) split8(v[ks], a[ks]);
+  }
+  double g0[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) g0[r] = *gmem(G + j0 + 4 * quad + r);
+  int fnk[4];
+  bool any_fused = false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int code = S.rowalt != nullptr ? S.rowalt[(long)i * P.ntheta + j0 + 4 * quad + r] : 0;
+    fnk[r] = code >= 2 ? 1 << (code - 1) : 1;
+    any_fused = any_fused || fnk[r] > 1;
+  }
+  any_fused = __any(any_fused);   // wavefront-uniform
+  const auto out = gmem(phi) + (long)i * P.ncell + (long)j0 * np;
+
+  // staging: entry e = ((ks * 2 + tile) * 3 + plane) * 64 + lane of the pair
+  u4 sb[CP];
+  double sc;
+  const int cx = threadIdx.x & 63;
+  const double *cbase = cx < 32 ? S.tw + (long)S.tpad * np + cx : S.tw + (cx - 32);   // TT row 0 / TW row 0
+  auto stage_load = [&](int nt) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      const int e = min((int)threadIdx.x + 256 * c, NE - 1);
+      const int ln = e % 64, q = (e / 64) % 3, tt = (e / 192) % 2, ks = e / 384;
+      sb[c] = frag(S.ttf, ((long)ks * S.nt_s + nt + tt) * 3 + q, ln);
+    }
+    sc = *gmem(cbase + 16 * nt);
+  };
+  auto stage_put = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      const int e = threadIdx.x + 256 * c;
+      if (e < NE) Bs[buf][e] = sb[c];
+    }
+    if (threadIdx.x < 64) Cs[buf][threadIdx.x] = sc;
+  };
+  auto store = [&](f4 acc, int nt, int tt, int buf) __attribute__((always_inline)) {
+    const int k = 16 * nt + (lane & 15);
+    const double c0 = Cs[buf][16 * tt + (lane & 15)];
+    double y[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[r] = g0[r] * c0 + (double)acc[r];
+    if (any_fused) {
+      const double w = Cs[buf][32 + 16 * tt + (lane & 15)];   // dphi_k
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double num = w * y[r], den = w;
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+          const double pn = __shfl_xor(num, m, 64), pd = __shfl_xor(den, m, 64);
+          if (m < fnk[r]) {
+            num += pn;
+            den += pd;
+          }
+        }
+        if (fnk[r] > 1) y[r] = den > 0.0 ? num / den : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(long)(4 * quad + r) * np + k] = y[r];
+  };
+
+  stage_load(nt0);
+  stage_put(0);
+  __syncthreads();
+  for (int p = 0; p < npairs; ++p) {
+    const int buf = p & 1, nt = nt0 + 2 * p;
+    stage_load(nt0 + 2 * min(p + 1, npairs - 1));   // the last pair loads itself again, unused
+    f4 p0 = f4{}, q0 = f4{}, p1 = f4{}, q1 = f4{};
+    const u4 *st = Bs[buf];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      u4 ba[3], bb[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        ba[q] = st[((ks * 2 + 0) * 3 + q) * 64 + lane];
+        bb[q] = st[((ks * 2 + 1) * 3 + q) * 64 + lane];
+      }
+      const u4(&x)[3] = a[ks];
+      p0 = mma(x[0], ba[0], p0);
+      q0 = mma(x[0], ba[2], q0);
+      p1 = mma(x[0], bb[0], p1);
+      q1 = mma(x[0], bb[2], q1);
+      p0 = mma(x[0], ba[1], p0);
+      q0 = mma(x[2], ba[0], q0);
+      p1 = mma(x[0], bb[1], p1);
+      q1 = mma(x[2], bb[0], q1);
+      p0 = mma(x[1], ba[0], p0);
+      q0 = mma(x[1], ba[1], q0);
+      p1 = mma(x[1], bb[0], p1);
+      q1 = mma(x[1], bb[1], q1);
+    }
+    store(p0 + q0, nt, 0, buf);
+    store(p1 + q1, nt + 1, 1, buf);
+    stage_put(buf ^ 1);   // buffer buf ^ 1 was last read in pair p - 1, past the barrier
+    __syncthreads();
+  }
+}
+
 inline unsigned cdiv(long n, long d) { return (unsigned)((n + d - 1) / d); }
 
 }  // namespace
@@ -437,6 +724,18 @@ hipError_t launch_sep_phi_anal_bf16(const PlanDev &P, const SepDev &S, const dou
   const dim3 grid(cdiv(cdiv(P.ntheta, 16), 4), (unsigned)P.nr);
   // 16-byte density loads need 16-byte aligned rows (the block-mean copy is)
   const int rho16 = ((uintptr_t)rho % 16) == 0;
+  if (rho16 && P.nphi % 32 == 0 && P.nphi <= kAnalFullPhi) {
+    const size_t lds = (size_t)P.nphi * sizeof(double);
+    switch (S.mt_a) {
+#define MPOLE_ANAL_FULL(MT) \
+  case MT: hipLaunchKernelGGL(k_sep_phi_anal_bf16_full<MT>, grid, dim3(256), lds, s, P, S, rho); break;
+      MPOLE_ANAL_FULL(0) MPOLE_ANAL_FULL(1) MPOLE_ANAL_FULL(2) MPOLE_ANAL_FULL(3) MPOLE_ANAL_FULL(4)
+      MPOLE_ANAL_FULL(5) MPOLE_ANAL_FULL(6) MPOLE_ANAL_FULL(7) MPOLE_ANAL_FULL(8)
+#undef MPOLE_ANAL_FULL
+      default: return hipErrorInvalidValue;   // 2L <= 128
+    }
+    return hipGetLastError();
+  }
   switch (S.mt_a) {
 #define MPOLE_ANAL(MT) \
   case MT: hipLaunchKernelGGL(k_sep_phi_anal_bf16<MT>, grid, dim3(256), 0, s, P, S, rho, rho16); break;
@@ -453,6 +752,20 @@ hipError_t launch_sep_phi_syn_bf16(const PlanDev &P, const SepDev &S, double *ph
   // leaves fewer than 4096 wavefronts
   const long rows = (long)cdiv(P.ntheta, 16) * P.nr;
   const int chunks = (int)std::min<long>(std::max<long>(1, (4096 + rows - 1) / rows), std::max(S.nt_s, 1));
+  if (P.nphi % 32 == 0 && P.ntheta % 64 == 0) {
+    // whole tile pairs per wavefront: an even chunk of the (even) tile count
+    const int ntw = 2 * (int)cdiv(S.nt_s / 2, chunks);
+    const dim3 grid(cdiv(cdiv(P.ntheta, 16), 4), (unsigned)P.nr, cdiv(S.nt_s, ntw));
+    switch (S.ks_s) {
+#define MPOLE_SYN_FULL(NKS) \
+  case NKS: hipLaunchKernelGGL(k_sep_phi_syn_bf16_full<NKS>, grid, dim3(256), 0, s, P, S, phi, ntw); break;
+      MPOLE_SYN_FULL(0) MPOLE_SYN_FULL(1) MPOLE_SYN_FULL(2) MPOLE_SYN_FULL(3) MPOLE_SYN_FULL(4)
+#undef MPOLE_SYN_FULL
+      default: return hipErrorInvalidValue;   // 2L <= 128
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_sep_block_means(P, S, phi, s) : e;
+  }
   const int ntw = (int)cdiv(S.nt_s, chunks);
   const dim3 grid(cdiv(cdiv(P.ntheta, 16), 4), (unsigned)P.nr, cdiv(S.nt_s, std::max(ntw, 1)));
   switch (S.ks_s) {
