@@ -167,10 +167,15 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   // two register sets of staged operands: the loads of stage k+2 are issued
   // before stage k is computed and land in LDS only after stage k+1 is, so
   // each load has two stages of MFMA work to hide behind.  Loads are
-  // unconditional (rows outside the operand read row 0 and are zeroed at the
-  // LDS store) and go through global address-space pointers, so nothing waits
-  // on them before the store.  With TMV = 64 the second half of the threads
-  // loads no X chunks (a wave-uniform condition).
+  // unconditional (rows outside the operand read row 0) and go through global
+  // address-space pointers, so nothing waits on them before the store.  In
+  // the moment contraction a thread whose row is outside the operand stores
+  // nothing: its LDS slots (it alone writes them) are zeroed once per tile
+  // below, so no select on the loaded values (which the scheduler hoists into
+  // the next stage's MFMAs, waiting on the loads there) is needed.  The
+  // expansion, short of registers, zeroes them at the store.  With TMV = 64
+  // the second half of the threads loads no X chunks (a wave-uniform
+  // condition).
   typedef const __attribute__((address_space(1))) u4 *gptr;
   u4 xa[NP], ya[NP], xb[NP], yb[NP];
   const u4 zero = {0u, 0u, 0u, 0u};
@@ -185,8 +190,13 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
 #define LSTORE(XV, YV, BUF)                                                          \
   {                                                                                  \
     _Pragma("unroll") for (int u = 0; u < NP; ++u) {                                 \
-      if (TMV == TMMAX || x_loader) Xs[(BUF) * CH * TMV + lx_slot[u]] = x_ok[u] ? XV[u] : zero; \
-      Ys[(BUF) * CH * TN + ly_slot[u]] = y_ok[u] ? YV[u] : zero;                      \
+      if (EXPAND) {                                                                  \
+        if (TMV == TMMAX || x_loader) Xs[(BUF) * CH * TMV + lx_slot[u]] = x_ok[u] ? XV[u] : zero; \
+        Ys[(BUF) * CH * TN + ly_slot[u]] = y_ok[u] ? YV[u] : zero;                    \
+      } else {                                                                       \
+        if ((TMV == TMMAX || x_loader) && x_ok[u]) Xs[(BUF) * CH * TMV + lx_slot[u]] = XV[u]; \
+        if (y_ok[u]) Ys[(BUF) * CH * TN + ly_slot[u]] = YV[u];                        \
+      }                                                                              \
     }                                                                                \
   }
   auto stage = [&](int buf, f16v (&ac)[AT][2]) __attribute__((always_inline)) {
@@ -224,6 +234,18 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
   };
 
   const int nk = (kend - kbeg) / TK;
+  // moment: zero slots of the rows outside the operands, both stage buffers
+  // (made visible by the first barrier; the LDS held other data before this
+  // tile)
+  if constexpr (!EXPAND) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if ((TMV == TMMAX || x_loader) && !x_ok[u]) Xs[b * CH * TMV + lx_slot[u]] = zero;
+        if (!y_ok[u]) Ys[b * CH * TN + ly_slot[u]] = zero;
+      }
+  }
   if (nk > 0) GLOAD(xa, ya, kbeg);
   if (nk > 1) GLOAD(xb, yb, kbeg + TK);
   if (nk > 0) LSTORE(xa, ya, 0);
