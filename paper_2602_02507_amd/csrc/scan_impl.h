@@ -18,7 +18,10 @@
 // the outward sums, suffix for the inward ones), and a second pass writes
 // edges and coefficients.  Chunk-boundary edges are always the scanned totals
 // (never a thread's running sum), so the two chunks meeting at an edge use
-// bitwise the same value.
+// bitwise the same value.  Chunks of at most SG shells load their operands
+// once, before the first pass, and keep them and the outward edges in
+// registers: vector memory counters retire in issue order, so a load issued
+// after a store would wait for the store.
 #pragma once
 #include "device_util.h"
 
@@ -64,6 +67,110 @@ __device__ __forceinline__ void reduce_item(const Job &J) {
 constexpr int SCAN_CHUNKS = 64;   // radial chunks per mode (one per lane of a wavefront)
 constexpr int SG = 8;             // shells whose operands are loaded together
 
+// Scan of one (mode, chunk) thread when the chunk holds at most SG shells: the
+// arithmetic of scan_item below, in the same order, from registers.
+template <int SCAN_MODES>
+__device__ __forceinline__ void scan_chunk_in_registers(const Job &J, double *lds, bool live, int n, int l, int mode,
+                                                        int c, int i0, int i1) {
+  double(*tot_r)[SCAN_MODES] = reinterpret_cast<double(*)[SCAN_MODES]>(lds);
+  double(*tot_i)[SCAN_MODES] = reinterpret_cast<double(*)[SCAN_MODES]>(lds + SCAN_CHUNKS * SCAN_MODES);
+  double(*base_r)[SCAN_MODES] = reinterpret_cast<double(*)[SCAN_MODES]>(lds + 2 * SCAN_CHUNKS * SCAN_MODES);
+  double(*base_i)[SCAN_MODES] =
+      reinterpret_cast<double(*)[SCAN_MODES]>(lds + (2 * SCAN_CHUNKS + SCAN_CHUNKS + 1) * SCAN_MODES);
+  const PlanDev &P = J.P;
+  const auto er = gmem(J.io.interior ? J.io.interior : P.edge_r);
+  const auto ei = gmem(J.io.exterior ? J.io.exterior : P.edge_i);
+  const auto coef = gmem(P.coef);
+  const auto A = gmem(P.ang);
+  const auto jr = gmem(P.jr), ji = gmem(P.ji), rr = gmem(P.rr), ri = gmem(P.ri);
+  const int ld_r = J.io.interior ? P.nam : P.namp;
+  const int ld_i = J.io.exterior ? P.nam : P.namp;
+  const int nr = P.nr, L1 = P.lmax + 1, namp = P.namp;
+  const int nc = i1 - i0;   // shells of this chunk, 0 .. SG
+  // every operand of the chunk, loaded together (entries past the chunk read
+  // its first shell, or shell 0, and are not used)
+  double av[SG], jrv[SG], jiv[SG], rrv[SG], riv[SG];
+  const int ib = min(i0, nr - 1);
+#pragma unroll
+  for (int u = 0; u < SG; ++u) {
+    const int i = u < nc ? i0 + u : ib;
+    av[u] = A[(size_t)i * namp + n];
+    jrv[u] = jr[i * L1 + l];
+    jiv[u] = ji[i * L1 + l];
+    rrv[u] = rr[i * L1 + l];
+    riv[u] = ri[i * L1 + l];
+  }
+  // pass 1: chunk totals
+  double sr = 0.0, si = 0.0;
+  if (live) {
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+      if (u >= nc) break;
+      sr += jrv[u] * av[u];
+      si += jiv[u] * av[u];
+    }
+  }
+  tot_r[c][mode] = sr;
+  tot_i[c][mode] = si;
+  __syncthreads();
+  {
+    const int t = item_tid(), w = t / 64, lane = t % 64;
+    double x = tot_r[lane][w];
+    double z = tot_i[lane][w];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const double xu = __shfl_up(x, d, 64);
+      const double zd = __shfl_down(z, d, 64);
+      if (lane >= d) x += xu;
+      if (lane + d < 64) z += zd;
+    }
+    base_r[lane + 1][w] = x;
+    base_i[lane][w] = z;
+    if (lane == 0) base_r[0][w] = 0.0;
+    if (lane == 63) base_i[SCAN_CHUNKS][w] = 0.0;
+  }
+  __syncthreads();
+  if (!live) {
+#pragma unroll
+    for (int u = 0; u < SG; ++u)
+      if (u < nc) coef[(size_t)(i0 + u) * namp + n] = 0.0;
+    return;
+  }
+  // pass 2a: outward edges i0 .. i1-1, kept for pass 2b
+  double ev[SG];
+  double mr = base_r[c][mode];
+#pragma unroll
+  for (int u = 0; u < SG; ++u) {
+    ev[u] = mr;
+    if (u < nc) {
+      er[(size_t)(i0 + u) * ld_r + n] = mr;
+      mr += jrv[u] * av[u];
+    }
+  }
+  const double mr_end = base_r[c + 1][mode];
+  const double mi_end = base_i[c + 1][mode];
+  if (i1 == nr && nc > 0) {
+    er[(size_t)nr * ld_r + n] = mr_end;
+    ei[(size_t)nr * ld_i + n] = mi_end;
+  }
+  // pass 2b: inward edges and the coefficients of Eq. Solution
+  const double dm = (n == l * l) ? 1.0 : 2.0;
+  const double f = -dm / (2.0 * l + 1.0);
+  double mi = mi_end, mr_hi = mr_end;
+#pragma unroll
+  for (int u = SG - 1; u >= 0; --u) {
+    if (u >= nc) continue;
+    const int i = i0 + u;
+    const double mi_hi = mi;
+    mi = (u == 0) ? base_i[c][mode] : mi + jiv[u] * av[u];
+    ei[(size_t)i * ld_i + n] = mi;
+    const double mr_lo = ev[u];
+    const double mic = 0.5 * (mi + mi_hi), mrc = 0.5 * (mr_lo + mr_hi);
+    coef[(size_t)i * namp + n] = f * (rrv[u] * mic + riv[u] * mrc);
+    mr_hi = mr_lo;
+  }
+}
+
 // LDS of a scan item in doubles: chunk totals and chunk bases, both sums
 template <int SCAN_MODES>
 constexpr int scan_lds() {
@@ -101,6 +208,10 @@ __device__ __forceinline__ void scan_item(const Job &J, double *lds) {
   }
   const int cs = (nr + SCAN_CHUNKS - 1) / SCAN_CHUNKS;
   const int i0 = min(nr, c * cs), i1 = min(nr, i0 + cs);
+  if (cs <= SG) {   // workgroup-uniform
+    scan_chunk_in_registers<SCAN_MODES>(J, lds, live, n, l, mode, c, i0, i1);
+    return;
+  }
   const auto A = gmem(P.ang);
   const auto jr = gmem(P.jr), ji = gmem(P.ji);
 
