@@ -162,6 +162,66 @@ __device__ __forceinline__ void tile_product(const OA &A, long a_ld, const OB &B
   }
 }
 
+// tile_product for long K (the phi analysis, K = nphi): two register sets, so
+// each load has two stages of MFMA work to hide behind.  For the short K of
+// the other contractions the extra stage of an odd count and the deeper
+// prologue cost more than they hide.
+template <bool A_KC, bool B_KC, class OA, class OB, class HOOK = NoHook>
+__device__ __forceinline__ void tile_product_deep(const OA &A, long a_ld, const OB &B, long b_ld, int b, int M,
+                                                  int N, int K, int m0, int n0, d4 acc[2][2], double (*As)[STAGE],
+                                                  double (*Bs)[STAGE], const HOOK &hook = HOOK()) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const TileLoader<A_KC, OA> la(A, b, m0, M, a_ld);
+  const TileLoader<B_KC, OB> lb(B, b, n0, N, b_ld);
+  // two register sets: the loads of stage k + 2 are issued before stage k is
+  // computed and reach LDS after stage k + 1 is, with no branch in the loop
+  // (an odd stage count computes one more stage, of zeros: every element
+  // past K is zeroed at the store, and loads past K read its last column).
+  // The selects that zero elements outside (rows, K) stay behind each
+  // stage's MFMAs (the scheduler would otherwise hoist them, and the wait for
+  // their loads, to the top of the stage).
+  double a0[4], b0[4], a1[4], b1[4];
+  auto load = [&](double (&av)[4], double (&bv)[4], int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      av[e] = la.load(e, k0, K);
+      bv[e] = lb.load(e, k0, K);
+    }
+  };
+  auto store = [&](const double (&av)[4], const double (&bv)[4], int buf, int k0) __attribute__((always_inline)) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      la.store(As[buf], e, av[e], m0 + la.r[e] < M && k0 + la.kk[e] < K);
+      lb.store(Bs[buf], e, bv[e], n0 + lb.r[e] < N && k0 + lb.kk[e] < K);
+    }
+  };
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nk = (K + BK - 1) / BK;
+  load(a0, b0, 0);
+  load(a1, b1, BK);
+  store(a0, b0, 0, 0);
+  __syncthreads();
+  load(a0, b0, 2 * BK);
+  for (int kt = 0; kt < nk; kt += 2) {
+    // stage kt in LDS 0; set 1 holds stage kt + 1, set 0 stage kt + 2
+    hook(As[0], Bs[0], kt * BK);   // the stage in LDS, before it is overwritten
+    mfma_stage<A_KC, B_KC>(As[0], Bs[0], wm, wn, lane, acc);
+    store(a1, b1, 1, (kt + 1) * BK);
+    __syncthreads();
+    load(a1, b1, (kt + 3) * BK);
+    hook(As[1], Bs[1], (kt + 1) * BK);
+    mfma_stage<A_KC, B_KC>(As[1], Bs[1], wm, wn, lane, acc);
+    store(a0, b0, 0, (kt + 2) * BK);
+    __syncthreads();
+    load(a0, b0, (kt + 4) * BK);
+  }
+}
+
 // Row and column of accumulator element (t, u, r) of this lane.
 __device__ inline void acc_pos(int t, int u, int r, int &row, int &col) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -199,9 +259,16 @@ struct RowSum {
   __device__ void operator()(const double *, const double *Bs, int k0) const {
     if (threadIdx.x >= BN) return;
     double s = *sum;
+    // dphi through scalar loads (the address is uniform): a vector load here
+    // would wait behind the tile's staged operand loads
+    if (k0 + BK <= nphi) {   // a whole stage: one batch of scalar loads
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk)
-      if (k0 + kk < nphi) s += dphi[k0 + kk] * Bs[threadIdx.x * RK + kk];
+      for (int kk = 0; kk < BK; ++kk) s += ld_const(dphi + k0 + kk) * Bs[threadIdx.x * RK + kk];
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk)
+        if (k0 + kk < nphi) s += ld_const(dphi + k0 + kk) * Bs[threadIdx.x * RK + kk];
+    }
     *sum = s;
   }
 };
@@ -218,11 +285,11 @@ __global__ __launch_bounds__(NTHREADS) void k_sep_phi_anal(PlanDev P, SepDev S, 
   double rs = 0.0;
   const auto F = gmem(S.f) + (long)i * S.tpad * P.ntheta;
   if (m0 == 0) {
-    tile_product<true, true>(A, 0, Bop, 0, i, M, P.ntheta, P.nphi, m0, n0, acc, As, Bs,
-                             RowSum{S.tw, n0, P.nphi, &rs});
+    tile_product_deep<true, true>(A, 0, Bop, 0, i, M, P.ntheta, P.nphi, m0, n0, acc, As, Bs,
+                                  RowSum{S.tw, n0, P.nphi, &rs});
     if (threadIdx.x < BN && n0 + (int)threadIdx.x < P.ntheta) F[n0 + threadIdx.x] = rs;
   } else {
-    tile_product<true, true>(A, 0, Bop, 0, i, M, P.ntheta, P.nphi, m0, n0, acc, As, Bs);
+    tile_product_deep<true, true>(A, 0, Bop, 0, i, M, P.ntheta, P.nphi, m0, n0, acc, As, Bs);
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t)
