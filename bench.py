@@ -141,7 +141,11 @@ def roofline_hbm(plan, phases, workload):
     modes = (2 * plan.lmax + 1) * float(plan.nr) * plan.shape[1]
     nbytes = 8.0 * cells + 8.0 * modes
     achieved = nbytes / (dom_ms * 1e-3)
-    return {"bound": "hbm", "kernel": kernel_name("bf16x3sep", dom), "achieved": achieved / 1e9, "peak": 8000.0,
+    # meshes of whole K steps (nphi % 32) and whole tile pairs (also ntheta %
+    # 64 for the synthesis) run the whole-tile forms of the transforms
+    full = plan.shape[2] % 32 == 0 and (dom == "moment" or plan.shape[1] % 64 == 0)
+    kernel = kernel_name("bf16x3sep", dom) + ("_full" if full else "")
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved / 1e9, "peak": 8000.0,
             "unit": "GB/s", "frac": achieved / 8e12, "traffic": measured_traffic(workload, dom), "launch_ms": dom_ms,
             "algorithmic_bytes_per_launch": nbytes,
             "phase_ms": {k: v[0] / max(v[1], 1) for k, v in phases.items() if v[1]}}
