@@ -446,7 +446,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT >= 5 ? 3
     PlanDev P, SepDev S, const double *rho) {
   constexpr int NF = MT > 0 ? MT * 3 * 64 : 64;   // fragment entries (16 bytes) per K step
   constexpr int CP = (NF + 255) / 256;             // copied per thread
-  __shared__ u4 As[2][NF];
+  // rounded up to whole copies of 256 entries: every thread stores its
+  // entries unconditionally (a guarded LDS store would leave the wait for its
+  // load in a branch, and the next fetch into the same registers would wait
+  // for all loads in flight); the entries past NF are never read
+  __shared__ u4 As[2][CP * 256];
   extern __shared__ double Ds[];                   // TW row 0: dphi_k
   const int lane = threadIdx.x & 63, quad = lane >> 4;
   const int i = blockIdx.y;
@@ -478,10 +482,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT >= 5 ? 3
   };
   auto put = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int c = 0; c < CP; ++c) {
-      const int e = threadIdx.x + 256 * c;
-      if (MT > 0 && e < NF) As[buf][e] = fr[c];
-    }
+    for (int c = 0; c < CP; ++c)
+      if (MT > 0) As[buf][threadIdx.x + 256 * c] = fr[c];
   };
   auto step = [&](double (&v)[8], int ks) __attribute__((always_inline)) {
     double d[8];
