@@ -110,23 +110,24 @@ def test_separable_bf16x3_unaligned_density_and_odd_phi():
         assert rel <= 1e-6, (npf, rel)
 
 
-@pytest.mark.parametrize("blk", [2, 4, 8])
-def test_separable_bf16x3_whole_step_analysis_equals_general(blk):
+@pytest.mark.parametrize("blk,npf", [(2, 64), (4, 64), (8, 64), (4, 96)])
+def test_separable_bf16x3_whole_step_analysis_equals_general(blk, npf):
     """The whole-step form of the BF16 x3 phi analysis (nphi a multiple of 32,
     16-byte aligned density) does the arithmetic of the general form in the
     same order: on production-rule meshes whose polar rows hold 1 x blk blocks
     (averaged inside the transforms) and whose inner shells hold blk x blk
     blocks, the aligned density (whole-step form) and a view one double into
     its storage (general form) give bitwise the same potential; both against
-    the oracle at 1e-6."""
+    the oracle at 1e-6.  nphi 96: three tile pairs per row, spread over
+    chunks of the synthesis grid."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2602_02507_amd import mpole
-    nr, nt, npf = 24, 64, 64
+    nr, nt = 24, 64
     m = wl.Mesh(wl.log_edges(1e-3, 1.0, nr), wl.uniform_edges(0.0, np.pi, nt), wl.uniform_edges(0.0, 2 * np.pi, npf), 12)
     m.shell_class, m.class_block = wl.production_merge(nr, nt, npf, inner_shells=6, polar_rows=8, blk=blk)
-    rho = wl.random_density(900 + blk, m.shape, positive=True)
+    rho = wl.random_density(900 + blk + npf, m.shape, positive=True)
     plan = mpole.Plan.from_mesh(m, precision="bf16x3sep")
     a = plan.solve(torch.from_numpy(rho).cuda())["phi"]
     store = torch.zeros(rho.size + 1, dtype=torch.float64, device="cuda")
@@ -135,10 +136,10 @@ def test_separable_bf16x3_whole_step_analysis_equals_general(blk):
     assert view.data_ptr() % 16 == 8
     b = plan.solve(view)["phi"]
     torch.cuda.synchronize()
-    assert torch.equal(a, b), blk
+    assert torch.equal(a, b), (blk, npf)
     ref = oracle.solve(rho=rho, **m.oracle_kwargs())["phi"]
     rel = np.max(np.abs(a.cpu().numpy() - ref)) / np.max(np.abs(ref))
-    assert rel <= 1e-6, (blk, rel)
+    assert rel <= 1e-6, (blk, npf, rel)
 
 
 @pytest.mark.parametrize("name", ["spheroid", "production"])
