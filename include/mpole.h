@@ -269,8 +269,9 @@ int mpole_plan_work(mpole_plan plan, double *moment_flops, double *expand_flops,
  * phi (in) and d_r, d_theta, d_phi (out) are device [nr][ntheta][nphi] FP64
  * (phi fastest), owned by the caller; an output may be NULL (not written).
  * The plan must be bound.  MPOLE_ERR_INVALID for a null plan or phi or an
- * unbound plan, MPOLE_ERR_DEVICE for a launch failure.  Asynchronous, no
- * allocation, graph-capturable.
+ * unbound plan, MPOLE_ERR_UNSUPPORTED for phi rows of 2^28 cells or more,
+ * MPOLE_ERR_DEVICE for a launch failure.  Asynchronous, no allocation,
+ * graph-capturable.
  */
 int mpole_gradient(mpole_plan plan, const double *phi, double *d_r, double *d_theta, double *d_phi,
                    void *hip_stream);
@@ -287,8 +288,9 @@ int mpole_gradient(mpole_plan plan, const double *phi, double *d_r, double *d_th
  * All are device [nr][ntheta][nphi] FP64 (phi fastest), owned by the caller;
  * outputs must not overlap the inputs.  One pass over the mesh.  The plan
  * must be bound.  MPOLE_ERR_INVALID for a null plan, phi or rho or an
- * unbound plan, MPOLE_ERR_DEVICE for a launch failure.  Asynchronous on
- * hip_stream, no allocation, graph-capturable.
+ * unbound plan, MPOLE_ERR_UNSUPPORTED for phi rows of 2^28 cells or more,
+ * MPOLE_ERR_DEVICE for a launch failure.  Asynchronous on hip_stream, no
+ * allocation, graph-capturable.
  */
 int mpole_gravity_sources(mpole_plan plan, const double *phi, const double *rho, const double *v_r,
                           const double *v_theta, const double *v_phi, double *s_r, double *s_theta,

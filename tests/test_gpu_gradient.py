@@ -31,7 +31,8 @@ def check(mesh, phi_h):
         assert err <= TOL, (name, err)
 
 
-@pytest.mark.parametrize("shape", [(37, 11, 23), (5, 1, 9), (1, 6, 1), (3, 4, 2), (64, 33, 65)])
+@pytest.mark.parametrize("shape", [(37, 11, 23), (5, 1, 9), (1, 6, 1), (3, 4, 2), (64, 33, 65), (17, 9, 128),
+                                   (16, 7, 129), (9, 5, 64)])
 def test_gradient_random_mesh(shape):
     nr, nt, npf = shape
     m = wl.random_mesh(sum(shape), nr, nt, npf, 4, r0=0.01)
@@ -39,9 +40,10 @@ def test_gradient_random_mesh(shape):
     check(m, phi)
 
 
-def test_gradient_open_phi_range():
-    m = wl.random_mesh(9, 20, 10, 16, 4, r0=0.0)
-    m.phi_edges = np.linspace(0.0, 3.0, 17)      # does not close the circle: one-sided seam
+@pytest.mark.parametrize("nphi", [16, 130])
+def test_gradient_open_phi_range(nphi):
+    m = wl.random_mesh(9, 20, 10, nphi, 4, r0=0.0)
+    m.phi_edges = np.linspace(0.0, 3.0, nphi + 1)      # does not close the circle: one-sided seam
     phi = wl.random_density(10, m.shape, positive=False)
     check(m, phi)
 
@@ -65,7 +67,8 @@ def test_gradient_of_production_potential():
 
 
 SRC_CASES = [((37, 11, 23), (True, True, True)), ((5, 1, 9), (True, False, True)), ((3, 4, 2), (False, False, False)),
-             ((64, 33, 65), (True, True, False)), ((1, 6, 1), (False, True, False))]
+             ((64, 33, 65), (True, True, False)), ((1, 6, 1), (False, True, False)),
+             ((17, 9, 128), (True, True, True)), ((16, 7, 129), (False, True, True))]
 
 
 @pytest.mark.parametrize("shape,vel", SRC_CASES, ids=[str(c[0]) for c in SRC_CASES])
