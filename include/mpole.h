@@ -62,6 +62,7 @@ extern "C" {
 
 #define MPOLE_ABI_VERSION 2
 #define MPOLE_LMAX_MAX 64
+#define MPOLE_GRADIENT_MAX_NPHI ((1 << 28) - 1)   /* longest phi row of mpole_gradient / mpole_gravity_sources */
 
 typedef enum {
   MPOLE_OK = 0,
@@ -269,7 +270,7 @@ int mpole_plan_work(mpole_plan plan, double *moment_flops, double *expand_flops,
  * phi (in) and d_r, d_theta, d_phi (out) are device [nr][ntheta][nphi] FP64
  * (phi fastest), owned by the caller; an output may be NULL (not written).
  * The plan must be bound.  MPOLE_ERR_INVALID for a null plan or phi or an
- * unbound plan, MPOLE_ERR_UNSUPPORTED for phi rows of 2^28 cells or more,
+ * unbound plan, MPOLE_ERR_UNSUPPORTED for nphi > MPOLE_GRADIENT_MAX_NPHI,
  * MPOLE_ERR_DEVICE for a launch failure.  Asynchronous, no allocation,
  * graph-capturable.
  */
@@ -288,7 +289,7 @@ int mpole_gradient(mpole_plan plan, const double *phi, double *d_r, double *d_th
  * All are device [nr][ntheta][nphi] FP64 (phi fastest), owned by the caller;
  * outputs must not overlap the inputs.  One pass over the mesh.  The plan
  * must be bound.  MPOLE_ERR_INVALID for a null plan, phi or rho or an
- * unbound plan, MPOLE_ERR_UNSUPPORTED for phi rows of 2^28 cells or more,
+ * unbound plan, MPOLE_ERR_UNSUPPORTED for nphi > MPOLE_GRADIENT_MAX_NPHI,
  * MPOLE_ERR_DEVICE for a launch failure.  Asynchronous on hip_stream, no
  * allocation, graph-capturable.
  */

@@ -59,7 +59,9 @@ __device__ inline double from_above(double x) { return dpp_shift<0x130>(x); }   
 // bytes, a lane adds only its 32-bit byte offset, so that no lane keeps a
 // 64-bit address in vector registers (and no address temporary of a store
 // still in flight is overwritten, which would wait for that store).  The
-// fourth descriptor word selects 32-bit raw data without swizzling.
+// fourth descriptor word selects 32-bit raw data without swizzling.  Byte
+// offsets within a row fit 31 bits: the entry points reject rows of 2^28
+// cells or more.
 typedef unsigned u2v __attribute__((ext_vector_type(2)));
 __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const double *row, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc((void *)row, 0, bytes, 0x00020000);
@@ -227,7 +229,6 @@ __global__ __launch_bounds__(GTH) void k_gradient(PlanDev P, const double *phi_,
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
                            hipStream_t s) {
   if (P.nr == 0 || P.ntheta == 0 || P.nphi == 0) return hipSuccess;
-  if (P.nphi > kGradMaxPhi) return hipErrorInvalidValue;
   const int tiles = ((P.ntheta + GJ - 1) / GJ) * ((P.nphi + 63) / 64);
   const unsigned groups = (unsigned)((tiles + 3) / 4), chunks = (unsigned)((P.nr + GR - 1) / GR);
   const GradIO io{{d_r, d_th, d_ph, nullptr}, nullptr, {nullptr, nullptr, nullptr}};
@@ -238,7 +239,6 @@ hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, dou
 hipError_t launch_gravity_sources(const PlanDev &P, const double *phi, const double *rho, const double *const v[3],
                                   double *const out[4], int periodic, hipStream_t s) {
   if (P.nr == 0 || P.ntheta == 0 || P.nphi == 0) return hipSuccess;
-  if (P.nphi > kGradMaxPhi) return hipErrorInvalidValue;
   const int tiles = ((P.ntheta + GJS - 1) / GJS) * ((P.nphi + 63) / 64);
   const unsigned groups = (unsigned)((tiles + 3) / 4), chunks = (unsigned)((P.nr + GR - 1) / GR);
   const GradIO io{{out[0], out[1], out[2], out[3]}, rho, {v[0], v[1], v[2]}};

@@ -263,9 +263,6 @@ hipError_t launch_reduce(const BatchDev &B, int wgs, hipStream_t s);
 hipError_t launch_scan(const BatchDev &B, int wgs, int modes, hipStream_t s);
 hipError_t launch_split_coef(const BatchDev &B, int precision, int wgs, hipStream_t s);
 hipError_t launch_expand(const BatchDev &B, int precision, int wgs, hipStream_t s);
-// the gradient kernels address a phi row through a buffer descriptor with
-// 32-bit byte offsets: rows of up to kGradMaxPhi cells
-constexpr int kGradMaxPhi = (1 << 28) - 1;
 hipError_t launch_gradient(const PlanDev &P, const double *phi, double *d_r, double *d_th, double *d_ph, int periodic,
                            hipStream_t s);
 // out[0..2] = -rho dPhi/dx^i, out[3] = -rho sum_i v^i dPhi/dx^i (any pointer may be null)

@@ -1179,7 +1179,8 @@ int mpole_gradient(mpole_plan p, const double *phi, double *d_r, double *d_theta
   if (!p->bound) return fail(MPOLE_ERR_INVALID, "plan is not bound to a workspace");
   if (!phi) return fail(MPOLE_ERR_INVALID, "phi is null");
   if (!d_r && !d_theta && !d_phi) return ok();
-  if (p->dev.nphi > kGradMaxPhi) return fail(MPOLE_ERR_UNSUPPORTED, "phi rows above %d cells", kGradMaxPhi);
+  if (p->dev.nphi > MPOLE_GRADIENT_MAX_NPHI)
+    return fail(MPOLE_ERR_UNSUPPORTED, "phi rows above %d cells", MPOLE_GRADIENT_MAX_NPHI);
   const hipError_t e = launch_gradient(p->dev, phi, d_r, d_theta, d_phi, p->phi_periodic, (hipStream_t)stream);
   if (e != hipSuccess) return fail(MPOLE_ERR_DEVICE, "gradient launch failed: %s", hipGetErrorString(e));
   return ok();
@@ -1192,7 +1193,8 @@ int mpole_gravity_sources(mpole_plan p, const double *phi, const double *rho, co
   if (!p->bound) return fail(MPOLE_ERR_INVALID, "plan is not bound to a workspace");
   if (!phi || !rho) return fail(MPOLE_ERR_INVALID, "phi and rho are required");
   if (!s_r && !s_theta && !s_phi && !s_energy) return ok();
-  if (p->dev.nphi > kGradMaxPhi) return fail(MPOLE_ERR_UNSUPPORTED, "phi rows above %d cells", kGradMaxPhi);
+  if (p->dev.nphi > MPOLE_GRADIENT_MAX_NPHI)
+    return fail(MPOLE_ERR_UNSUPPORTED, "phi rows above %d cells", MPOLE_GRADIENT_MAX_NPHI);
   const double *v[3] = {v_r, v_theta, v_phi};
   double *out[4] = {s_r, s_theta, s_phi, s_energy};
   const hipError_t e = launch_gravity_sources(p->dev, phi, rho, v, out, p->phi_periodic, (hipStream_t)stream);
