@@ -30,6 +30,7 @@
 // All four contractions run on v_mfma_f64_16x16x4 with the 64 x 64 tiles
 // and conflict-free LDS layouts of the dense FP64 kernels.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_util.h"
 #include "f64_mma.h"
@@ -365,6 +366,174 @@ __global__ __launch_bounds__(NTHREADS) void k_sep_theta_syn(PlanDev P, SepDev S)
       }
 }
 
+// ---- theta transforms with every operand load issued at once ---------------
+//
+// The tiled kernels above stream K through LDS 16 at a time, one stage
+// ahead; the theta contractions are short (K = ntheta or L + 1 - m) and their
+// grids hold about two workgroups per CU, so each stage's load latency is
+// exposed in turn.  For the common shapes the forms below issue all of a
+// workgroup's operand loads at once instead.  A workgroup takes 64 shells of
+// one trig mode t, a wavefront 16 of them (the rows of its MFMA tiles); the
+// per-shell operand goes straight into MFMA operand registers (loaded in the
+// lane order of the f64 16x16x4 operand, no LDS), the per-mode table is
+// staged once in LDS for the workgroup's four wavefronts.  The results are
+// the same sums as the tiled kernels', in another order.
+
+// k step s of a 128-wide chunk takes j = 8 (s / 2) + 2 q + s % 2 from the
+// lanes of k slot q: every 16-byte load of the F rows then covers 64
+// contiguous bytes per row.  Row s * 4 + q of the staged PW_m holds that j.
+__device__ inline int anal_row(int jj) { return ((jj >> 3) * 2 + (jj & 1)) * 4 + ((jj >> 1) & 3); }
+
+// A[i][l m a] = sum_j F[i][t][j] PW_m[j][l-m] for ntheta = 128 KCH and
+// L + 1 - m <= 16 NB; grid (shell tiles of 64, t).  Lane (r, q) = (l % 16,
+// l / 16) holds F[i0 + r][t][128 c + 8 h + 2 q + e] for h < 16, e < 2
+// (16-byte loads), the A operands of k steps 2 h + e of chunk c.  Blocks of
+// 16 columns wholly past L - m are skipped.
+template <int KCH, int NB>
+__global__ __launch_bounds__(NTHREADS) void k_sep_theta_anal_w(PlanDev P, SepDev S, double *ang_out) {
+  extern __shared__ double Bs[];   // [KCH * 128][NB * 16 + 1]
+  constexpr int PITCH = NB * 16 + 1, NBC = NB * 16, NLD = KCH * 128 * NBC / NTHREADS;
+  static_assert(KCH * 128 * NBC % NTHREADS == 0, "table staging");
+  const int t = blockIdx.y;
+  int m, a;
+  trig_mode(t, m, a);
+  const int L1 = P.lmax + 1, N = L1 - m;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int r = lane & 15, q = lane >> 4;
+  const int i0 = blockIdx.x * 64 + 16 * w;
+  // PW_m[j][n], n = l - m (columns past N read column N - 1 and stage 0)
+  const auto pw = gmem(S.pw + (long)m * P.ntheta * L1);
+  double bv[NLD];
+#pragma unroll
+  for (int e = 0; e < NLD; ++e) {
+    const int x = (int)threadIdx.x + NTHREADS * e, j = x / NBC, n = x % NBC;
+    bv[e] = pw[(long)j * L1 + min(n, N - 1)];
+  }
+  // F[i][t][.]: this lane's 32 k of each chunk (shells past nr read shell nr - 1)
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+  const dv2 *frow = reinterpret_cast<const dv2 *>(S.f + ((long)min(i0 + r, P.nr - 1) * S.tpad + t) * P.ntheta) + q;
+  dv2 av[KCH][16];
+#pragma unroll
+  for (int c = 0; c < KCH; ++c)
+#pragma unroll
+    for (int h = 0; h < 16; ++h) av[c][h] = *gmem(frow + 64 * c + 4 * h);
+#pragma unroll
+  for (int e = 0; e < NLD; ++e) {
+    const int x = (int)threadIdx.x + NTHREADS * e, j = x / NBC, n = x % NBC;
+    Bs[((j >> 7) * 128 + anal_row(j & 127)) * PITCH + n] = n < N ? bv[e] : 0.0;
+  }
+  __syncthreads();
+  d4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = d4{0.0, 0.0, 0.0, 0.0};
+  // the live column blocks, chosen once per workgroup (a branch between
+  // MFMAs would cost the hazard padding at every block boundary)
+  auto product = [&](auto nlive) __attribute__((always_inline)) {
+    constexpr int NL = decltype(nlive)::value;
+#pragma unroll
+    for (int c = 0; c < KCH; ++c)
+#pragma unroll
+      for (int s = 0; s < 32; ++s) {
+        const double x = av[c][s >> 1][s & 1];
+        const double *brow = Bs + (c * 128 + 4 * s + q) * PITCH + r;
+#pragma unroll
+        for (int nb = 0; nb < NL; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, brow[16 * nb], acc[nb], 0, 0, 0);
+      }
+  };
+  if (NB >= 3 && N > 32) product(std::integral_constant<int, NB>{});
+  else if (NB >= 2 && N > 16) product(std::integral_constant<int, (NB >= 2 ? 2 : NB)>{});
+  else product(std::integral_constant<int, 1>{});
+  // element (4 rr + q, r) of block nb: shell i0 + 4 rr + q, l = m + 16 nb + r
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int i = i0 + 4 * rr + q, lp = 16 * nb + r;
+      if (i >= P.nr || lp >= N) continue;
+      const int l = lp + m;
+      const int n = m == 0 ? l * l : l * l + 2 * m - 1 + a;
+      gmem(P.ang)[(long)i * P.namp + n] = acc[nb][rr];
+      if (ang_out != nullptr) gmem(ang_out)[(long)i * P.nam + n] = acc[nb][rr];
+    }
+}
+
+// G[i][t][j] = sum_l C[i][l m a] PT_m[l-m][j] for L + 1 <= 4 KS, over a
+// column tile of 128 theta rows; grid (shell tiles of 64 x column tiles, t).
+// Lane (r, q) holds the coefficient of l = m + 4 s + q of shell i0 + r for
+// each k step s (a gather from the coefficient rows; l past L reads l = L,
+// whose staged PT row is zero); PT_m is staged once, rows k < 4 KS.
+template <int KS>
+__global__ __launch_bounds__(NTHREADS) void k_sep_theta_syn_w(PlanDev P, SepDev S) {
+  extern __shared__ double Bs[];   // [4 KS][128 + 1]
+  constexpr int PITCH = 129, NLD = 4 * KS * 128 / NTHREADS;
+  static_assert(4 * KS * 128 % NTHREADS == 0, "table staging");
+  const int t = blockIdx.y;
+  int m, a;
+  trig_mode(t, m, a);
+  const int L1 = P.lmax + 1, K = L1 - m;
+  const int nct = P.ntheta / 128;
+  const int i0w = (blockIdx.x / nct) * 64, j0 = (blockIdx.x % nct) * 128;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int r = lane & 15, q = lane >> 4;
+  const int i0 = i0w + 16 * w;
+  // PT_m[k][j0 + jj] (rows k >= K stage 0)
+  const auto pt = gmem(S.pt + (long)m * L1 * P.ntheta + j0);
+  double bv[NLD];
+#pragma unroll
+  for (int e = 0; e < NLD; ++e) {
+    const int x = (int)threadIdx.x + NTHREADS * e, k = x >> 7, jj = x & 127;
+    bv[e] = pt[(long)min(k, K - 1) * P.ntheta + jj];
+  }
+  const auto crow = gmem(P.coef + (long)min(i0 + r, P.nr - 1) * P.namp);
+  double av[KS];
+#pragma unroll
+  for (int s2 = 0; s2 < KS; ++s2) {
+    const int l = min(m + 4 * s2 + q, P.lmax);
+    av[s2] = crow[m == 0 ? l * l : l * l + 2 * m - 1 + a];
+  }
+#pragma unroll
+  for (int e = 0; e < NLD; ++e) {
+    const int x = (int)threadIdx.x + NTHREADS * e, k = x >> 7, jj = x & 127;
+    Bs[k * PITCH + jj] = k < K ? bv[e] : 0.0;
+  }
+  __syncthreads();
+  d4 acc[8];
+#pragma unroll
+  for (int nb = 0; nb < 8; ++nb) acc[nb] = d4{0.0, 0.0, 0.0, 0.0};
+  // the k steps up to L - m, their count chosen once per workgroup (a branch
+  // between MFMAs would cost the hazard padding at every block boundary)
+  auto product = [&](auto nsteps) __attribute__((always_inline)) {
+    constexpr int NS = decltype(nsteps)::value;
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      const double *brow = Bs + (4 * s2 + q) * PITCH + r;
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], brow[16 * nb], acc[nb], 0, 0, 0);
+    }
+  };
+  using std::integral_constant;
+  switch (min((K + 3) / 4, KS)) {
+    case 1: product(integral_constant<int, 1>{}); break;
+    case 2: product(integral_constant<int, 2 <= KS ? 2 : 1>{}); break;
+    case 3: product(integral_constant<int, 3 <= KS ? 3 : 1>{}); break;
+    case 4: product(integral_constant<int, 4 <= KS ? 4 : 1>{}); break;
+    case 5: product(integral_constant<int, 5 <= KS ? 5 : 1>{}); break;
+    case 6: product(integral_constant<int, 6 <= KS ? 6 : 1>{}); break;
+    case 7: product(integral_constant<int, 7 <= KS ? 7 : 1>{}); break;
+    case 8: product(integral_constant<int, 8 <= KS ? 8 : 1>{}); break;
+    default: product(integral_constant<int, KS>{}); break;
+  }
+  // element (4 rr + q, r) of block nb: shell i0 + 4 rr + q, theta row j0 + 16 nb + r
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int i = i0 + 4 * rr + q;
+    if (i >= P.nr) continue;
+    const auto grow = gmem(S.g + ((long)i * S.tpad + t) * P.ntheta + j0 + r);
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) grow[16 * nb] = acc[nb][rr];
+  }
+}
+
 // Phihat_i[j][k] = sum_t G_i[t][j] TT[t][k]; grid (j tiles x k tiles, shells).
 __global__ __launch_bounds__(NTHREADS) void k_sep_phi_syn(PlanDev P, SepDev S, double *phi) {
   __shared__ double As[2][STAGE], Bs[2][STAGE];
@@ -474,14 +643,41 @@ hipError_t launch_sep_phi_anal(const PlanDev &P, const SepDev &S, const double *
 }
 
 hipError_t launch_sep_theta_anal(const PlanDev &P, const SepDev &S, double *ang_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sep_theta_anal, dim3(tiles(P.nr, BM) * tiles(P.lmax + 1, BN), 2 * P.lmax + 1),
-                     dim3(NTHREADS), 0, s, P, S, ang_out);
+  // whole-K form: ntheta 128 with L + 1 <= 48, or 256 with L + 1 <= 16 (the
+  // staged table within 64 KB of LDS)
+  const int nb = (P.lmax + 16) / 16;
+  const dim3 grid(tiles(P.nr, 64), 2 * P.lmax + 1);
+  auto lds = [&](int kch, int n) { return (size_t)kch * 128 * (n * 16 + 1) * sizeof(double); };
+  if (P.ntheta == 128 && nb == 1)
+    hipLaunchKernelGGL((k_sep_theta_anal_w<1, 1>), grid, dim3(NTHREADS), lds(1, 1), s, P, S, ang_out);
+  else if (P.ntheta == 128 && nb == 2)
+    hipLaunchKernelGGL((k_sep_theta_anal_w<1, 2>), grid, dim3(NTHREADS), lds(1, 2), s, P, S, ang_out);
+  else if (P.ntheta == 128 && nb == 3)
+    hipLaunchKernelGGL((k_sep_theta_anal_w<1, 3>), grid, dim3(NTHREADS), lds(1, 3), s, P, S, ang_out);
+  else if (P.ntheta == 256 && nb == 1)
+    hipLaunchKernelGGL((k_sep_theta_anal_w<2, 1>), grid, dim3(NTHREADS), lds(2, 1), s, P, S, ang_out);
+  else
+    hipLaunchKernelGGL(k_sep_theta_anal, dim3(tiles(P.nr, BM) * tiles(P.lmax + 1, BN), 2 * P.lmax + 1),
+                       dim3(NTHREADS), 0, s, P, S, ang_out);
   return hipGetLastError();
 }
 
 hipError_t launch_sep_theta_syn(const PlanDev &P, const SepDev &S, hipStream_t s) {
-  hipLaunchKernelGGL(k_sep_theta_syn, dim3(tiles(P.nr, BM) * tiles(P.ntheta, BN), 2 * P.lmax + 1), dim3(NTHREADS),
-                     0, s, P, S);
+  // whole-K form: ntheta a multiple of 128 and L + 1 <= 36 (at most 9 k steps)
+  const int ks = (P.lmax + 4) / 4;
+  const dim3 grid(tiles(P.nr, 64) * (unsigned)(P.ntheta / 128), 2 * P.lmax + 1);
+  auto lds = [&](int k) { return (size_t)4 * k * 129 * sizeof(double); };
+  if (P.ntheta % 128 != 0 || ks > 9)
+    hipLaunchKernelGGL(k_sep_theta_syn, dim3(tiles(P.nr, BM) * tiles(P.ntheta, BN), 2 * P.lmax + 1),
+                       dim3(NTHREADS), 0, s, P, S);
+  else if (ks <= 2)
+    hipLaunchKernelGGL((k_sep_theta_syn_w<2>), grid, dim3(NTHREADS), lds(2), s, P, S);
+  else if (ks <= 3)
+    hipLaunchKernelGGL((k_sep_theta_syn_w<3>), grid, dim3(NTHREADS), lds(3), s, P, S);
+  else if (ks <= 5)
+    hipLaunchKernelGGL((k_sep_theta_syn_w<5>), grid, dim3(NTHREADS), lds(5), s, P, S);
+  else
+    hipLaunchKernelGGL((k_sep_theta_syn_w<9>), grid, dim3(NTHREADS), lds(9), s, P, S);
   return hipGetLastError();
 }
 

@@ -42,6 +42,13 @@ CASES = [
     ("thin", 5, 1, 1, 0, 0.1, False),
     ("one_theta", 9, 1, 12, 4, 0.1, False),
     ("one_phi", 9, 10, 1, 5, 0.1, False),
+    # 128 and 256 theta rows (the whole-K theta transforms), shells past the
+    # last 64-shell tile
+    ("theta128_l8", 70, 128, 8, 8, 0.02, False),
+    ("theta128_l16", 70, 128, 8, 16, 0.02, True),
+    ("theta128_l32", 70, 128, 8, 32, 0.0, True),
+    ("theta256_l12", 37, 256, 8, 12, 0.02, True),
+    ("theta256_l3", 130, 256, 4, 3, 0.0, False),
 ]
 
 
