@@ -49,6 +49,8 @@ CASES = [
     ("theta128_l32", 70, 128, 8, 32, 0.0, True),
     ("theta256_l12", 37, 256, 8, 12, 0.02, True),
     ("theta256_l3", 130, 256, 4, 3, 0.0, False),
+    ("theta128_l35", 20, 128, 4, 35, 0.02, False),   # the most k steps of the synthesis form
+    ("theta128_l47", 20, 128, 4, 47, 0.02, True),    # the most column blocks of the analysis form
 ]
 
 
