@@ -254,7 +254,7 @@ __device__ __forceinline__ void expand_f64_item(const BatchDev &B, const Job &J,
           const double v = h ? acc[t][u][r] - acco[t][u][r] : acc[t][u][r] + acco[t][u][r];
           if (C.rect != nullptr) {
             if (bnj[u][h] == 1 && bnk[u][h] == 1) {
-              dst[bcell[u][h]] = v;
+              __builtin_nontemporal_store(v, &dst[bcell[u][h]]);   // the potential streams out
             } else {
               for (int j = 0; j < bnj[u][h]; ++j)
                 for (int k = 0; k < bnk[u][h]; ++k) dst[bcell[u][h] + j * P.nphi + k] = v;

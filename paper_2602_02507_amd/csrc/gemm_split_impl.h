@@ -366,7 +366,7 @@ __device__ __forceinline__ void gemm_tile(const BatchDev &B, const PlanDev &P, c
             const double v = c0 * bt0[b] + sc * (h ? ev - od : ev + od);
             if (C.rect != nullptr) {
               if (bnj[b][h] == 1 && bnk[b][h] == 1) {
-                dst[bcell[b][h]] = v;
+                __builtin_nontemporal_store(v, &dst[bcell[b][h]]);   // the potential streams out
               } else {
                 for (int j = 0; j < bnj[b][h]; ++j)
                   for (int k = 0; k < bnk[b][h]; ++k) dst[bcell[b][h] + j * P.nphi + k] = v;

@@ -69,8 +69,12 @@ __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const double *row, int bytes) 
 __device__ inline double bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
+// Stores carry the non-temporal hint: the derivatives and sources stream
+// out once and nothing in this kernel reads them back (both kernels measured
+// 5-20 % faster with it on the production and 942 x 256 x 512 meshes).
+constexpr int kStoreNT = 2;   // cache-policy operand: nt
 __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, double x) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, x), r, (int)off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, x), r, (int)off, 0, kStoreNT);
 }
 
 // Outputs of one launch: the three derivatives (SRC false), or the

@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_sep_phi_syn_bf16(PlanDev P, SepDev S, d
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jj = j0 + 4 * quad + r;
-        if (jj < P.ntheta) out[(long)jj * P.nphi + k] = y[r];
+        if (jj < P.ntheta) __builtin_nontemporal_store(y[r], &out[(long)jj * P.nphi + k]);   // streamed out
       }
     }
   };
@@ -671,7 +671,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NKS >= 3 ? 
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out[(long)(4 * quad + r) * np + k] = y[r];
+    for (int r = 0; r < 4; ++r) __builtin_nontemporal_store(y[r], &out[(long)(4 * quad + r) * np + k]);   // streamed out
   };
 
   stage_load(nt0);

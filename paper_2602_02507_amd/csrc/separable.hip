@@ -556,7 +556,8 @@ __global__ __launch_bounds__(NTHREADS) void k_sep_phi_syn(PlanDev P, SepDev S, d
         acc_pos(t, u, r, row, col);
         row += m0;
         col += n0;
-        if (row < P.ntheta && col < P.nphi) out[(long)row * P.nphi + col] = acc[t][u][r];
+        if (row < P.ntheta && col < P.nphi)
+          __builtin_nontemporal_store(acc[t][u][r], &out[(long)row * P.nphi + col]);   // the potential streams out
       }
 }
 
