@@ -114,7 +114,7 @@ __global__ __launch_bounds__(LB_THREADS) void k_band(PlanDev P, const double *in
   if (bd.w == 0) {   // single cells
     if (COPY && in_ != out_) {
       const int q0 = bd.x * P.nphi, q1 = (bd.x + bd.y) * P.nphi;
-      for (int q = q0 + threadIdx.x; q < q1; q += LB_THREADS) out[q] = in[q];
+      for (int q = q0 + threadIdx.x; q < q1; q += LB_THREADS) __builtin_nontemporal_store((double)in[q], &out[q]);
     }
     return;
   }
@@ -137,7 +137,12 @@ __global__ __launch_bounds__(LB_THREADS) void k_band(PlanDev P, const double *in
     }
     if (k < P.nphi) {
       const double v = a / w;
-      for (int j = bd.x; j < bd.x + bd.y; ++j) out[j * P.nphi + k] = v;
+      for (int j = bd.x; j < bd.x + bd.y; ++j) {
+        // the coarsened field streams out; block means of the solve stay
+        // cached for the kernel that reads them next
+        if constexpr (COPY) __builtin_nontemporal_store(v, &out[j * P.nphi + k]);
+        else out[j * P.nphi + k] = v;
+      }
     }
   }
 }
