@@ -55,7 +55,7 @@ __device__ inline double from_below(double x) { return dpp_shift<0x138>(x); }   
 __device__ inline double from_above(double x) { return dpp_shift<0x130>(x); }   // wave_shl:1
 
 // Raw buffer access to one phi row of an array: the descriptor holds the
-// row's base address (workgroup-uniform, in scalar registers) and its size in
+// row's base address (wavefront-uniform, in scalar registers) and its size in
 // bytes, a lane adds only its 32-bit byte offset, so that no lane keeps a
 // 64-bit address in vector registers (and no address temporary of a store
 // still in flight is overwritten, which would wait for that store).  The
