@@ -534,6 +534,62 @@ __global__ __launch_bounds__(NTHREADS) void k_sep_theta_syn_w(PlanDev P, SepDev 
   }
 }
 
+// Phihat_i[j][k] = sum_t G_i[t][j] TT[t][k] for 2L + 1 <= 4 KS, ntheta and
+// nphi multiples of 64; grid (j tiles x k tiles of 64, shells).  The same
+// scheme as the theta forms above: lane (r, q) holds G_i[4 s + q][j0 + r]
+// for each k step s (16 consecutive theta rows per trig mode; modes past 2L
+// read mode 2L, whose staged TT row is zero, since G's padding modes are
+// never written), and the 64 columns of TT the workgroup needs are staged
+// once in LDS.
+template <int KS>
+__global__ __launch_bounds__(NTHREADS) void k_sep_phi_syn_w(PlanDev P, SepDev S, double *phi) {
+  extern __shared__ double Bs[];   // [4 KS][64 + 1]
+  constexpr int PITCH = 65, NLD = 4 * KS * 64 / NTHREADS;
+  static_assert(4 * KS * 64 % NTHREADS == 0, "table staging");
+  const int i = blockIdx.y;
+  const int ntk = P.nphi / 64;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int r = lane & 15, q = lane >> 4;
+  const int j0 = (blockIdx.x / ntk) * 64 + 16 * w, k0 = (blockIdx.x % ntk) * 64;
+  const int K = 2 * P.lmax + 1;
+  // TT[t][k0 + kk] (TT follows TW; its rows 2L < t < tpad are zero, and
+  // tpad, a multiple of 16, exceeds the odd 2L + 1: rows past it read the
+  // last, zero row)
+  const auto tt = gmem(S.tw + (long)S.tpad * P.nphi + k0);
+  double bv[NLD];
+#pragma unroll
+  for (int e = 0; e < NLD; ++e) {
+    const int x = (int)threadIdx.x + NTHREADS * e, t = x >> 6, kk = x & 63;
+    bv[e] = tt[(long)min(t, S.tpad - 1) * P.nphi + kk];
+  }
+  const auto g = gmem(S.g + (long)i * S.tpad * P.ntheta + j0 + r);
+  double av[KS];
+#pragma unroll
+  for (int s2 = 0; s2 < KS; ++s2) av[s2] = g[(long)min(4 * s2 + q, K - 1) * P.ntheta];
+#pragma unroll
+  for (int e = 0; e < NLD; ++e) {
+    const int x = (int)threadIdx.x + NTHREADS * e, t = x >> 6, kk = x & 63;
+    Bs[t * PITCH + kk] = bv[e];
+  }
+  __syncthreads();
+  d4 acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s2 = 0; s2 < KS; ++s2) {
+    const double *brow = Bs + (4 * s2 + q) * PITCH + r;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s2], brow[16 * nb], acc[nb], 0, 0, 0);
+  }
+  // element (4 rr + q, r) of block nb: theta row j0 + 4 rr + q, phi column k0 + 16 nb + r
+  const auto out = gmem(phi) + (long)i * P.ncell + k0 + r;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+      __builtin_nontemporal_store(acc[nb][rr], &out[(long)(j0 + 4 * rr + q) * P.nphi + 16 * nb]);   // streamed out
+}
+
 // Phihat_i[j][k] = sum_t G_i[t][j] TT[t][k]; grid (j tiles x k tiles, shells).
 __global__ __launch_bounds__(NTHREADS) void k_sep_phi_syn(PlanDev P, SepDev S, double *phi) {
   __shared__ double As[2][STAGE], Bs[2][STAGE];
@@ -683,8 +739,24 @@ hipError_t launch_sep_theta_syn(const PlanDev &P, const SepDev &S, hipStream_t s
 }
 
 hipError_t launch_sep_phi_syn(const PlanDev &P, const SepDev &S, double *phi, hipStream_t s) {
-  hipLaunchKernelGGL(k_sep_phi_syn, dim3(tiles(P.ntheta, BM) * tiles(P.nphi, BN), P.nr), dim3(NTHREADS), 0, s, P, S,
-                     phi);
+  // whole-K form: 64-row, 64-column tiles and 2L + 1 <= 100 (the staged TT
+  // columns within 64 KB of LDS)
+  const int ks = (2 * P.lmax + 4) / 4;
+  const dim3 grid((unsigned)((P.ntheta / 64) * (P.nphi / 64)), (unsigned)P.nr);
+  auto lds = [&](int k) { return (size_t)4 * k * 65 * sizeof(double); };
+  if (P.ntheta % 64 != 0 || P.nphi % 64 != 0 || ks > 25)
+    hipLaunchKernelGGL(k_sep_phi_syn, dim3(tiles(P.ntheta, BM) * tiles(P.nphi, BN), P.nr), dim3(NTHREADS), 0, s, P,
+                       S, phi);
+  else if (ks <= 5)
+    hipLaunchKernelGGL((k_sep_phi_syn_w<5>), grid, dim3(NTHREADS), lds(5), s, P, S, phi);
+  else if (ks <= 9)
+    hipLaunchKernelGGL((k_sep_phi_syn_w<9>), grid, dim3(NTHREADS), lds(9), s, P, S, phi);
+  else if (ks <= 13)
+    hipLaunchKernelGGL((k_sep_phi_syn_w<13>), grid, dim3(NTHREADS), lds(13), s, P, S, phi);
+  else if (ks <= 17)
+    hipLaunchKernelGGL((k_sep_phi_syn_w<17>), grid, dim3(NTHREADS), lds(17), s, P, S, phi);
+  else
+    hipLaunchKernelGGL((k_sep_phi_syn_w<25>), grid, dim3(NTHREADS), lds(25), s, P, S, phi);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? launch_sep_block_means(P, S, phi, s) : e;
 }

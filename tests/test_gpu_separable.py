@@ -51,6 +51,10 @@ CASES = [
     ("theta256_l3", 130, 256, 4, 3, 0.0, False),
     ("theta128_l35", 20, 128, 4, 35, 0.02, False),   # the most k steps of the synthesis form
     ("theta128_l47", 20, 128, 4, 47, 0.02, True),    # the most column blocks of the analysis form
+    # 64-row, 64-column tiles (the whole-K phi synthesis) at three k-step counts
+    ("phi64_l12", 21, 64, 64, 12, 0.02, True),
+    ("phi128_l24", 9, 64, 128, 24, 0.0, False),
+    ("phi64_l40", 7, 128, 64, 40, 0.02, True),
 ]
 
 
