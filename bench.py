@@ -212,7 +212,13 @@ def roofline(plan, phases, precision, workload):
     products = {"fp64": 1, "bf16x3": 6, "fp16x2": 3, "fp64sep": 1, "bf16x3sep": 6}[precision]
     # a folded plan executes half the algorithmic multiply-adds (block pairs)
     fold = 0.5 if getattr(plan, "folded", False) else 1.0
-    return {"bound": "mfma", "kernel": kernel_name(precision, dom),
+    kernel = kernel_name(precision, dom)
+    # the FP64 separable synthesis on 64 x 64 tiles with 2L + 1 <= 100 runs its
+    # whole-K form
+    if precision == "fp64sep" and dom == "expand" and plan.shape[1] % 64 == 0 and plan.shape[2] % 64 == 0 \
+            and (2 * plan.lmax + 4) // 4 <= 25:
+        kernel += "_w"
+    return {"bound": "mfma", "kernel": kernel,
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": punit, "frac": achieved / peak,
             "traffic": measured_traffic(workload, dom), "launch_ms": dom_ms,
             "algorithmic_flops_per_launch": flops, "narrow_products_per_madd": products,
