@@ -154,3 +154,34 @@ def test_irregular_large_blocks(precision, tol):
         f = wl.random_density(24, m.shape, positive=False)
         got = plan.coarsen(torch.from_numpy(f).cuda()).cpu().numpy()
         assert np.max(np.abs(got - coarsen_ref(m, f))) <= 1e-14 * np.abs(f).max()
+
+
+def test_coarsen_replays_from_a_graph():
+    """The coarsening captured in a HIP graph (the entry point promises
+    capture): every replay, with the output overwritten eagerly between
+    replays, equals the eager result bitwise (band, large-block and copied
+    cells alike)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_02507_amd import mpole
+    m = genasis_case(48, 3, 4)
+    plan = mpole.Plan.from_mesh(m, precision="fp64")
+    f = torch.from_numpy(wl.random_density(13, m.shape, positive=False)).cuda()
+    out = torch.empty_like(f)
+    plan.coarsen(f, out=out)
+    torch.cuda.synchronize()
+    eager = out.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.coarsen(f, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        out.fill_(3.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
